@@ -1,0 +1,186 @@
+"""Seeded synthetic inputs shared by the oracle and the GPU path.
+
+This module only draws random numbers and evaluates initial fields; it holds
+none of the method's arithmetic (no time stepping, no residuals, no coarse
+solves).  Every array is float64, row-major, shaped ``[n]`` for one time
+slice (``n = nx * ny``, index ``y * nx + x``) or ``[nt + 1, n]`` for a
+space-time iterate.
+
+Problem kinds (the integrator of the one-step form u_i = Phi(u_{i-1}) + g_i of
+section 2, eq. (2); g_i = 0 for i >= 1 and g_0 = u0):
+
+* ``HEAT1D`` -- u_t = nu u_xx on [0, L], zero Dirichlet, nx interior points,
+  h = L / (nx + 1), backward Euler.
+* ``HEAT2D`` -- u_t = nu (u_xx + u_yy) on [0, L]^2, zero Dirichlet, nx * ny
+  interior points, 5-point stencil, backward Euler solved by Jacobi-PCG.
+* ``AC2D``   -- u_t = nu Lap(u) + (u - u^3) / eps^2 on the periodic square
+  [0, L)^2, h = L / nx, IMEX step (implicit diffusion by CG, explicit cubic).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+HEAT1D = 1
+HEAT2D = 2
+AC2D = 3
+
+KIND_NAMES = {HEAT1D: "heat1d", HEAT2D: "heat2d", AC2D: "ac2d"}
+
+
+@dataclasses.dataclass
+class Problem:
+    """Statement of the discrete initial value problem (section 2)."""
+
+    kind: int
+    nx: int
+    ny: int = 1
+    length: float = 1.0
+    nu: float = 1.0
+    eps: float = 1.0
+    t0: float = 0.0
+    tf: float = 1.0
+    nt: int = 16
+    cg_rtol: float = 1e-12
+    cg_max_iter: int = 1000
+
+    @property
+    def n(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def dt(self) -> float:
+        return (self.tf - self.t0) / self.nt
+
+
+@dataclasses.dataclass
+class Options:
+    """Two-level AT-MGRIT parameters (section 2.1, Alg. 1)."""
+
+    m: int = 2
+    k: int = 2
+    relax: int = 1          # 0 = F-relaxation, 1 = FCF-relaxation
+    tol: float = 1e-8       # absolute 2-norm of the space-time residual
+    max_iter: int = 100
+    coarse_substeps: int = 1
+    coarse_form: int = 0    # 0 auto (linear for heat, FAS for Allen-Cahn), 1 linear, 2 FAS
+    precision: int = 0      # 0 FP64 throughout, 1 FP32 fine sweeps + FP64 residual/correction
+
+    def n_intervals(self, nt: int) -> int:
+        return nt // self.m
+
+
+def default_k(n_intervals: int) -> int:
+    """k = max(2, ceil(0.1 (N_T + 1))), the 10 % rule of the heat k-study (section 4.3)."""
+    return max(2, math.ceil(0.1 * (n_intervals + 1)))
+
+
+# ---------------------------------------------------------------------------
+# initial fields
+# ---------------------------------------------------------------------------
+
+def heat1d_u0(nx: int, seed: int, length: float = 1.0, modes=range(2, 9), sigma: float = 0.1):
+    """sin(pi x / L) plus seeded N(0, sigma^2) amplitudes on the given sine modes."""
+    rng = np.random.default_rng(seed)
+    h = length / (nx + 1)
+    x = h * np.arange(1, nx + 1)
+    u = np.sin(np.pi * x / length)
+    amps = rng.normal(0.0, sigma, size=len(list(modes)))
+    for a, j in zip(amps, modes):
+        u = u + a * np.sin(j * np.pi * x / length)
+    return np.ascontiguousarray(u, dtype=np.float64), dict(zip(list(modes), amps))
+
+
+def heat2d_u0(nx: int, ny: int, seed: int, length: float = 1.0, n_modes: int = 16, max_mode: int = 16):
+    """Sum of n_modes sine modes sin(j pi x) sin(l pi y), (j, l) i.i.d. U{1..max_mode}, amplitudes N(0, 1)."""
+    rng = np.random.default_rng(seed)
+    hx = length / (nx + 1)
+    hy = length / (ny + 1)
+    x = hx * np.arange(1, nx + 1)
+    y = hy * np.arange(1, ny + 1)
+    js = rng.integers(1, max_mode + 1, size=n_modes)
+    ls = rng.integers(1, max_mode + 1, size=n_modes)
+    amps = rng.normal(0.0, 1.0, size=n_modes)
+    u = np.zeros((ny, nx))
+    for a, j, l in zip(amps, js, ls):
+        u += a * np.outer(np.sin(l * np.pi * y / length), np.sin(j * np.pi * x / length))
+    return np.ascontiguousarray(u.reshape(-1), dtype=np.float64), list(zip(js.tolist(), ls.tolist(), amps.tolist()))
+
+
+def ac2d_u0(nx: int, ny: int, seed: int, amp: float = 0.05):
+    """i.i.d. U[-amp, amp] field on the periodic grid."""
+    rng = np.random.default_rng(seed)
+    return np.ascontiguousarray(rng.uniform(-amp, amp, size=nx * ny), dtype=np.float64)
+
+
+def initial_guess(prob: Problem, u0: np.ndarray, kind: str = "zero", seed: int = 0):
+    """Space-time iterate [nt+1, n] with u[0] = g_0 = u0 and the guess at t > 0.
+
+    kind = "zero": zeros at t > 0.  kind = "random": i.i.d. U[-1, 1] at t > 0
+    (the heat study of section 4.3 uses a random guess so that no knowledge of
+    the right-hand side enters).
+    """
+    u = np.zeros((prob.nt + 1, prob.n), dtype=np.float64)
+    u[0] = u0
+    if kind == "random":
+        rng = np.random.default_rng(seed)
+        u[1:] = rng.uniform(-1.0, 1.0, size=(prob.nt, prob.n))
+    elif kind != "zero":
+        raise ValueError(kind)
+    return u
+
+
+# ---------------------------------------------------------------------------
+# the five workloads
+# ---------------------------------------------------------------------------
+
+def config(name: str):
+    """Return (Problem, Options, u0) for a named workload.
+
+    c1  1D heat, nx=63, Nt=1024 on [0,1], m=16, FCF, FP64.
+    c2  2D heat nu=0.1, 128x128 interior, Nt=4096 on [0,1], m=32, CG rtol 1e-12.
+    c3  2D Allen-Cahn eps=0.02, periodic 256x256, dt=1e-5, Nt=8192, m=64, 4 coarse substeps.
+    c5  2D Allen-Cahn eps=0.03, periodic 128x128, dt=1e-5, Nt=4096, m=32.
+    """
+    if name == "c1":
+        p = Problem(HEAT1D, nx=63, ny=1, length=1.0, nu=1.0, t0=0.0, tf=1.0, nt=1024)
+        o = Options(m=16, k=default_k(1024 // 16), relax=1, tol=1e-8)
+        u0, _ = heat1d_u0(63, seed=1)
+    elif name == "c2":
+        p = Problem(HEAT2D, nx=128, ny=128, length=1.0, nu=0.1, t0=0.0, tf=1.0, nt=4096, cg_rtol=1e-12)
+        o = Options(m=32, k=default_k(4096 // 32), relax=1, tol=1e-8)
+        u0, _ = heat2d_u0(128, 128, seed=2)
+    elif name == "c3":
+        p = Problem(AC2D, nx=256, ny=256, length=1.0, nu=1.0, eps=0.02, t0=0.0, tf=8192 * 1e-5, nt=8192,
+                    cg_rtol=1e-12)
+        o = Options(m=64, k=default_k(8192 // 64), relax=1, tol=1e-8, coarse_substeps=4, precision=1)
+        u0 = ac2d_u0(256, 256, seed=3)
+    elif name == "c5":
+        p = Problem(AC2D, nx=128, ny=128, length=1.0, nu=1.0, eps=0.03, t0=0.0, tf=4096 * 1e-5, nt=4096,
+                    cg_rtol=1e-12)
+        o = Options(m=32, k=default_k(4096 // 32), relax=1, tol=1e-8, coarse_substeps=1, precision=1)
+        u0 = ac2d_u0(128, 128, seed=7)
+    else:
+        raise KeyError(name)
+    return p, o, u0
+
+
+def small_problem(kind: int, seed: int = 0, nt: int = 48, nx: int = 7, ny: int = None, **kw):
+    """A tiny problem of the given kind with seeded initial data, for oracle pins and parity."""
+    if kind == HEAT1D:
+        p = Problem(HEAT1D, nx=nx, ny=1, nu=kw.pop("nu", 1.0), tf=kw.pop("tf", 0.5), nt=nt, **kw)
+        u0, _ = heat1d_u0(nx, seed=seed)
+    elif kind == HEAT2D:
+        ny = nx if ny is None else ny
+        p = Problem(HEAT2D, nx=nx, ny=ny, nu=kw.pop("nu", 0.1), tf=kw.pop("tf", 0.5), nt=nt, **kw)
+        u0, _ = heat2d_u0(nx, ny, seed=seed, n_modes=4, max_mode=min(nx, ny, 4))
+    elif kind == AC2D:
+        ny = nx if ny is None else ny
+        p = Problem(AC2D, nx=nx, ny=ny, nu=1.0, eps=kw.pop("eps", 0.1), tf=kw.pop("tf", nt * 1e-3), nt=nt, **kw)
+        rng = np.random.default_rng(seed)
+        u0 = np.ascontiguousarray(rng.uniform(-0.5, 0.5, size=nx * ny))
+    else:
+        raise KeyError(kind)
+    return p, u0
