@@ -1,0 +1,153 @@
+"""Benchmark: space-time point-updates per second to a 1e-8 residual, one GPU.
+
+A step is one complete two-level AT-MGRIT solve (every hot-path row: FCF
+relaxation sweeps, the truncated local coarse solves, correction and
+interpolation, residual norm and stopping test) of the 2D heat workload
+(128x128 interior, nu = 0.1, Nt = 4096, m = 32, k = 13, CG rtol 1e-12, FP64)
+from the zero initial guess, with all inputs resident in HBM.  The initial
+guess is restored by a device copy at the start of each step (inside the
+timed region).
+
+Prints one JSON line (see the keys below).  --gpus > 1 is refused: this build
+runs on a single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks used for the roofline fraction
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic FP64 flops per grid point of the sweep kernel's CG:
+#   per iteration: M p (7), (p, Mp) (2), x += a p (2), r -= a Mp (2), z = r/d (1),
+#   (r, z) (2), (r, r) (2), p = z + b p (2)                                    = 20
+#   per solve (initial residual r = b - M x, (b,b), (r,r), (r,z), p = z)       = 14
+FLOPS_PER_CG_ITER_POINT = 20
+FLOPS_PER_SOLVE_POINT = 14
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=4096,
+                    help="time steps of the oracle's sequential stepping timed for cpu_baseline")
+    return ap.parse_args()
+
+
+def cpu_baseline(p, u0, steps):
+    """The oracle (test infrastructure) timed on the host: sequential time stepping, 1 thread."""
+    import oracle
+    import workloads as W
+    oracle.build()
+    oracle.set_threads(1)
+    q = W.Problem(**{**p.__dict__, "nt": steps, "tf": p.t0 + steps * p.dt})
+    t0 = time.perf_counter()
+    oracle.sequential(q, u0)
+    dt = time.perf_counter() - t0
+    return {
+        "value": p.n * steps / dt, "unit": "space-time point-updates/s", "cores": 1, "kind": "oracle",
+        "sample": f"oracle sequential time stepping (exact forward solve, residual 0) of the first {steps} "
+                  f"of {p.nt} steps of the same workload, 1 thread, {dt:.2f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2107_09596_amd as atm
+    import workloads as W
+
+    p, o, u0 = W.config(args.config)
+    o.profile = 1
+    dev = torch.device("cuda:0")
+    guess = torch.from_numpy(W.initial_guess(p, u0)).to(dev)
+    u = torch.empty_like(guess)
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o), device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        u.copy_(guess)
+        return atm.atm_solve(p, o, u, ws=ws, allow=(atm.ATM_OK,))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    agg = {"ms_sweep": 0.0, "ms_coarse": 0.0, "ms_norm": 0.0, "cg_fine": 0, "cg_coarse": 0, "fine_steps": 0,
+           "coarse_steps": 0, "n_sweeps": 0, "iterations": 0}
+    last = None
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        status, hist, st = step()
+        for key in agg:
+            agg[key] += st[key]
+        last = (hist, st)
+        print(f"# step {i + 1}/{args.steps}: {st['iterations']} cycles, residual {hist[-1]:.3e}, "
+              f"{st['ms_total']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = p.n * p.nt / (ms_per_step / 1e3)
+
+    # roofline of the dominant kernel: the relaxation sweep (FP64 VALU-bound CG)
+    sweep_flops = p.n * (FLOPS_PER_CG_ITER_POINT * agg["cg_fine"] + FLOPS_PER_SOLVE_POINT * agg["fine_steps"])
+    achieved = sweep_flops / (agg["ms_sweep"] / 1e3) / 1e12 if agg["ms_sweep"] > 0 else 0.0
+    roofline = {
+        "kernel": "sweep2d_kernel (FCF/F relaxation + correction sweeps)",
+        "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+        "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+        "avg_launch_ms": agg["ms_sweep"] / max(agg["n_sweeps"], 1),
+        "launches": agg["n_sweeps"],
+    }
+
+    # context: sequential time stepping on the same GPU (one workgroup; the paper's baseline method)
+    useq = torch.zeros_like(guess)
+    useq[0].copy_(guess[0])
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    atm.atm_sequential(p, useq)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - ts
+    max_diff = float((useq - u).abs().max())
+
+    out = {
+        "metric": "space-time point-updates/s to 1e-8 residual",
+        "value": value, "unit": "space-time point-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{args.config}: 2D heat 128x128 interior, nu=0.1, Nt=4096 on [0,1], m=32, "
+                               f"k={o.k}, FCF, backward Euler + Jacobi-PCG rtol 1e-12, tol 1e-8, FP64",
+                   "global_batch": 1, "seq_len": p.nt, "parallelism": "time-parallel, 1 GPU"},
+        "iterations": last[1]["iterations"], "final_residual": last[0][-1],
+        "phase_ms_per_step": {k: agg[k] / args.steps for k in ("ms_sweep", "ms_coarse", "ms_norm")},
+        "cg_iters_per_step": {"fine": agg["cg_fine"] / args.steps, "coarse": agg["cg_coarse"] / args.steps},
+        "roofline": roofline,
+        "gpu_sequential": {"value": p.n * p.nt / seq_s, "ms": seq_s * 1e3,
+                           "speedup_of_atmgrit": seq_s * 1e3 / ms_per_step,
+                           "max_abs_diff_to_atmgrit": max_diff},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, u0, min(args.cpu_steps, p.nt))
+        out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,177 @@
+/*
+ * atm.h -- C-ABI of libatmgrit.so: two-level asynchronous truncated
+ * multigrid-reduction-in-time (AT-MGRIT) on one AMD MI355X (gfx950).
+ *
+ * Method: J. Hahne, B. S. Southworth, S. Friedhoff, "Asynchronous Truncated
+ * Multigrid-reduction-in-time", arXiv 2107.09596.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Plain C; all pointers marked (device) are HIP device pointers owned by the
+ *   caller (e.g. PyTorch tensors); (host) pointers are ordinary host memory.
+ * - `stream` is a hipStream_t passed as void*.  Work is enqueued on it; calls
+ *   that return a residual norm or statistics synchronise the stream first.
+ *   All other calls return after enqueueing (results valid after a stream sync).
+ * - The library never allocates device memory in these calls except a few
+ *   bytes of pinned host memory for residual readback (one per thread, kept).
+ *   All scratch lives in the caller's workspace `ws` of at least
+ *   atm_workspace_bytes() bytes, 256-byte aligned.
+ * - Arguments are validated before any launch; on error nothing is enqueued,
+ *   the status is returned and atm_last_error() holds a message
+ *   (thread-local).  No exception crosses the ABI.
+ * - Space-time layout: u is [nt+1][n] FP64, row-major, n = nx*ny, spatial
+ *   index y*nx + x.  For a coarsening factor m this is the
+ *   [interval][step][space] layout: time index t = j*m + i.
+ * - The library is re-entrant for distinct workspaces; calls that share a
+ *   workspace must be ordered on one stream.
+ *
+ * Problem statement (section 2, eq. (2)): u_0 = g_0, u_i = Phi(u_{i-1}) + g_i,
+ * with g_i = 0 for i >= 1.  Time grid t_i = t0 + i dt, dt = (tf - t0)/nt.
+ */
+#ifndef ATM_H
+#define ATM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t atm_status;
+#define ATM_OK 0
+#define ATM_NOT_CONVERGED 1      /* max_iter reached; result and stats valid */
+#define ATM_ERR_INVALID_ARG (-1)
+#define ATM_ERR_UNSUPPORTED (-2) /* valid but not implemented (e.g. a grid too large for a CU) */
+#define ATM_ERR_DEVICE (-3)      /* HIP runtime error; see atm_last_error() */
+#define ATM_ERR_DIVERGED (-4)    /* non-finite residual norm */
+#define ATM_ERR_INNER_SOLVE (-5) /* a CG solve inside Phi or Psi missed rtol within cg_max_iter */
+#define ATM_ERR_WORKSPACE (-6)   /* workspace smaller than atm_workspace_bytes() */
+
+/* problem kinds: the one-step integrator Phi (section 2, eq. (2)) */
+#define ATM_HEAT1D 1 /* u_t = nu u_xx on [0,L], zero Dirichlet, nx interior points,
+                        h = L/(nx+1); backward Euler, tridiagonal solve */
+#define ATM_HEAT2D 2 /* u_t = nu (u_xx+u_yy) on [0,L]^2, zero Dirichlet, nx*ny interior
+                        points, 5-point stencil; backward Euler by Jacobi-PCG */
+#define ATM_AC2D 3   /* u_t = nu Lap u + (u - u^3)/eps^2, periodic [0,L)^2, h = L/nx;
+                        IMEX: (I - dt nu Lap) u_i = u_{i-1} + dt (u_{i-1} - u_{i-1}^3)/eps^2 by CG */
+
+typedef struct atm_problem {
+    double length;  /* L, side of the domain */
+    double nu;      /* diffusion coefficient */
+    double eps;     /* Allen-Cahn interface width (ATM_AC2D only) */
+    double t0, tf;  /* time interval (t0, tf] */
+    double cg_rtol; /* CG stops when ||b - M x||_2 <= cg_rtol ||b||_2 (2D kinds) */
+    int64_t nt;     /* number of fine time steps N_t; nt+1 time points */
+    int32_t kind;   /* ATM_HEAT1D, ATM_HEAT2D or ATM_AC2D */
+    int32_t nx, ny; /* spatial points; ny = 1 for ATM_HEAT1D */
+    int32_t cg_max_iter;
+} atm_problem;
+
+typedef struct atm_options {
+    double tol;            /* stop when ||g - A(u)||_2 <= tol (absolute, all space-time points) */
+    double reserved_d;     /* must be 0 */
+    int32_t m;             /* coarsening factor, >= 2 (section 2.1) */
+    int32_t k;             /* C-points per local coarse grid, >= 1; k >= N_T+1 is Parareal */
+    int32_t relax;         /* 0: F-relaxation, 1: FCF-relaxation (section 2.2) */
+    int32_t max_iter;      /* maximum number of cycles */
+    int32_t coarse_substeps; /* Psi = s steps of size m dt / s, s >= 1 */
+    int32_t coarse_form;   /* 0 auto (linear for heat, FAS for Allen-Cahn), 1 linear, 2 FAS */
+    int32_t precision;     /* 0: FP64 throughout; 1: FP32 fine sweeps, FP64 residual/correction */
+    int32_t profile;       /* 1: time every kernel launch of atm_solve with HIP events (atm_stats.ms_*) */
+} atm_options;
+
+typedef struct atm_stats {
+    double final_residual; /* ||g - A(u)||_2 of the returned iterate */
+    double ms_total;       /* wall time of atm_solve (host clock, stream synchronised) */
+    double ms_sweep;       /* summed device time of the relaxation sweeps (profile = 1, else 0) */
+    double ms_coarse;      /* summed device time of the local coarse solves incl. FAS tau (profile = 1) */
+    double ms_norm;        /* summed device time of the residual-norm kernels (profile = 1) */
+    int64_t fine_steps;    /* Phi applications (all intervals, all sweeps) */
+    int64_t coarse_steps;  /* Psi applications (all windows) */
+    int64_t cg_fine;       /* CG iterations inside the sweeps' Phi steps (2D kinds) */
+    int64_t cg_coarse;     /* CG iterations inside Psi (windows and FAS tau; 2D kinds) */
+    int32_t iterations;    /* cycles applied (number of coarse corrections) */
+    int32_t n_sweeps;      /* sweep launches */
+} atm_stats;
+
+/* Number of coarse intervals N_T = floor(nt / m); C-points are 0..N_T. */
+int64_t atm_num_intervals(const atm_problem* prob, const atm_options* opts);
+
+/* First C-point of the local coarse grid T^(p) = {max(0, p-k+1), ..., p}
+   (section 2.1, definition of the local grids; Fig. 1). */
+int64_t atm_window_start(int64_t p, int32_t k);
+
+/* Workspace size in bytes for the calls below with this problem and options,
+   or 0 if the arguments are invalid. */
+size_t atm_workspace_bytes(const atm_problem* prob, const atm_options* opts);
+
+/* Relaxation sweep over every interval at once (section 2.1 F-relaxation,
+   section 2.2 CF-relaxation, Alg. 1 correction with selective ideal
+   interpolation P_S).  Every interval j (0..N_T-1, plus a ragged tail after
+   C-point N_T when m does not divide nt) first sets its C-point value c_j:
+     mode 0: c_j = u_{jm}                 (F-relaxation)
+     mode 1: c_j = u_{jm} + aux_j         (correction by e_j = aux_j, then F-interpolation)
+     mode 2: c_j = aux_j for j >= 1, u_0 for j = 0   (C-relaxation from aux = Phi(u_{jm-1}),
+                                                      then F-relaxation)
+   writes u_{jm} = c_j, then u_{jm+i} = Phi(u_{jm+i-1}) for its F-points, and
+   for j < N_T writes y_{j+1} = Phi(u_{jm+m-1}).  The C-point residual of the
+   result is r_j = y_j - u_{jm} (j >= 1); r_0 = 0; F-point residuals are 0.
+   u    (device) [nt+1][n] FP64, in/out.
+   aux  (device) [N_T+1][n] FP64, read in modes 1 and 2, else may be NULL.
+   y    (device) [N_T+1][n] FP64, out (row 0 untouched); must not alias aux.
+   Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE, DEVICE.  A CG failure inside
+   Phi is reported by the next call that synchronises (atm_residual_norm,
+   atm_solve) as ATM_ERR_INNER_SOLVE. */
+atm_status atm_sweep(const atm_problem* prob, const atm_options* opts, int32_t mode, double* u,
+                     const double* aux, double* y, void* ws, size_t ws_bytes, void* stream);
+
+/* The N_T+1 mutually independent local coarse-grid solves (Alg. 1: restrict
+   by injection, solve A~_c^(p) u_c^(p) = r_c^(p); section 3.1.2 defines A~_c^(p)
+   as the bidiagonal matrix with I on the diagonal and -Psi below).  With
+   r_j = y_j - u_{jm} (j >= 1), r_0 = 0 and s = max(0, p-k+1):
+     linear form: e = r_s; e = Psi(e) + r_j for j = s+1..p; e_p = e.
+     FAS form (Alg. 2, coarsest level): v_j = u_{jm}; w = v_s + r_s;
+       w = Psi(w) + (v_j - Psi(v_{j-1}) + r_j) for j = s+1..p; e_p = w - v_p.
+   u (device) [nt+1][n] in; y (device) [N_T+1][n] in; e (device) [N_T+1][n] out. */
+atm_status atm_coarse_solve(const atm_problem* prob, const atm_options* opts, const double* u,
+                            const double* y, double* e, void* ws, size_t ws_bytes, void* stream);
+
+/* Residual 2-norm ||g - A(u)||_2 of an iterate whose F-points are relaxed
+   (the stopping test of section 4.3): sqrt(sum_{j=1..N_T} ||y_j - u_{jm}||^2).
+   Synchronises the stream and writes the value to *norm_out (host).
+   Returns INNER_SOLVE if a CG failure was flagged in this workspace since
+   the last synchronising call. */
+atm_status atm_residual_norm(const atm_problem* prob, const atm_options* opts, const double* u,
+                             const double* y, double* norm_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Sequential time stepping on the GPU: u_i = Phi(u_{i-1}) for i = 1..nt from
+   u_0 (the forward block solve of A u = g, section 2), in one workgroup.
+   u (device) [nt+1][n], in: u_0, out: all slices.  Needs nt >= 2 and a
+   workspace of atm_sequential_workspace_bytes().  Synchronises the stream.
+   Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE, DEVICE, INNER_SOLVE. */
+atm_status atm_sequential(const atm_problem* prob, double* u, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for atm_sequential, or 0 if the problem is invalid. */
+size_t atm_sequential_workspace_bytes(const atm_problem* prob);
+
+/* Two-level AT-MGRIT (Alg. 1) until ||g - A(u)||_2 <= tol or max_iter cycles.
+   u (device) [nt+1][n]: in, u_0 = g_0 and the initial guess at t > 0; out,
+   the final iterate.  hist (host, nullable) receives hist_cap residual norms:
+   hist[0] of the F-relaxed initial guess, hist[i] after cycle i.
+   stats (host, nullable).  Synchronises the stream once per cycle.
+   Returns OK, NOT_CONVERGED, DIVERGED, INNER_SOLVE, or an argument error. */
+atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u, void* ws,
+                     size_t ws_bytes, double* hist, int32_t hist_cap, atm_stats* stats, void* stream);
+
+/* Human-readable name of a status code (static string). */
+const char* atm_status_string(atm_status status);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* atm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ATM_H */

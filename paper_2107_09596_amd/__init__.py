@@ -1,0 +1,130 @@
+"""Two-level AT-MGRIT (arXiv 2107.09596) on one MI355X: thin Python binding.
+
+The functions below carry the names of the C-ABI in include/atm.h and only
+marshal arguments: torch tensors (device memory) become pointers, the current
+torch stream becomes the hipStream_t.  All arithmetic of the hot path runs in
+the HIP kernels of libatmgrit.so; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _abi
+from ._abi import (ATM_AC2D, ATM_ERR_DEVICE, ATM_ERR_DIVERGED, ATM_ERR_INNER_SOLVE, ATM_ERR_INVALID_ARG,
+                   ATM_ERR_UNSUPPORTED, ATM_ERR_WORKSPACE, ATM_HEAT1D, ATM_HEAT2D, ATM_NOT_CONVERGED, ATM_OK,
+                   AtmError)
+
+__all__ = [
+    "atm_num_intervals", "atm_window_start", "atm_workspace_bytes", "atm_sweep", "atm_coarse_solve",
+    "atm_residual_norm", "atm_sequential", "atm_sequential_workspace_bytes", "atm_solve", "atm_status_string",
+    "atm_last_error", "workspace", "AtmError", "ATM_OK", "ATM_NOT_CONVERGED", "ATM_ERR_INVALID_ARG",
+    "ATM_ERR_UNSUPPORTED", "ATM_ERR_DEVICE", "ATM_ERR_DIVERGED", "ATM_ERR_INNER_SOLVE", "ATM_ERR_WORKSPACE",
+    "ATM_HEAT1D", "ATM_HEAT2D", "ATM_AC2D",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, dtype=None, name="tensor"):
+    if t is None:
+        return None
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    del torch
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def atm_num_intervals(prob, opts) -> int:
+    return int(_abi.lib().atm_num_intervals(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts))))
+
+
+def atm_window_start(p: int, k: int) -> int:
+    return int(_abi.lib().atm_window_start(int(p), int(k)))
+
+
+def atm_workspace_bytes(prob, opts) -> int:
+    return int(_abi.lib().atm_workspace_bytes(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts))))
+
+
+def atm_sequential_workspace_bytes(prob) -> int:
+    return int(_abi.lib().atm_sequential_workspace_bytes(ctypes.byref(_abi.problem(prob))))
+
+
+def workspace(nbytes: int, device="cuda"):
+    """A device byte buffer usable as the workspace (torch allocations are 512-byte aligned)."""
+    torch = _torch()
+    if nbytes <= 0:
+        raise ValueError("workspace size is 0: the problem or options are invalid (see atm_last_error())")
+    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+
+
+def _f64():
+    return _torch().float64
+
+
+def atm_sweep(prob, opts, mode: int, u, aux, y, ws, stream=None) -> None:
+    st = _abi.lib().atm_sweep(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts)), int(mode),
+                              _ptr(u, _f64(), "u"), _ptr(aux, _f64(), "aux"), _ptr(y, _f64(), "y"),
+                              _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(stream))
+    _abi.check(st, "atm_sweep")
+
+
+def atm_coarse_solve(prob, opts, u, y, e, ws, stream=None) -> None:
+    st = _abi.lib().atm_coarse_solve(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts)),
+                                     _ptr(u, _f64(), "u"), _ptr(y, _f64(), "y"), _ptr(e, _f64(), "e"),
+                                     _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(stream))
+    _abi.check(st, "atm_coarse_solve")
+
+
+def atm_residual_norm(prob, opts, u, y, ws, stream=None) -> float:
+    out = ctypes.c_double(0.0)
+    st = _abi.lib().atm_residual_norm(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts)),
+                                      _ptr(u, _f64(), "u"), _ptr(y, _f64(), "y"), ctypes.byref(out),
+                                      _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(stream))
+    _abi.check(st, "atm_residual_norm")
+    return out.value
+
+
+def atm_sequential(prob, u, ws=None, stream=None) -> None:
+    if ws is None:
+        ws = workspace(atm_sequential_workspace_bytes(prob), device=u.device)
+    st = _abi.lib().atm_sequential(ctypes.byref(_abi.problem(prob)), _ptr(u, _f64(), "u"), _ptr(ws, None, "ws"),
+                                   ws.numel() * ws.element_size(), _stream(stream))
+    _abi.check(st, "atm_sequential")
+
+
+def atm_solve(prob, opts, u, ws=None, hist_cap: int = 256, stream=None, allow=(ATM_OK, ATM_NOT_CONVERGED)):
+    """Run AT-MGRIT in place on u; returns (status, residual history list, stats dict)."""
+    if ws is None:
+        ws = workspace(atm_workspace_bytes(prob, opts), device=u.device)
+    hist = (ctypes.c_double * max(hist_cap, 1))()
+    stats = _abi.AtmStats()
+    st = _abi.lib().atm_solve(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts)),
+                              _ptr(u, _f64(), "u"), _ptr(ws, None, "ws"), ws.numel() * ws.element_size(),
+                              hist, int(hist_cap), ctypes.byref(stats), _stream(stream))
+    _abi.check(st, "atm_solve", allow=allow)
+    sd = {name: getattr(stats, name) for name, _ in _abi.AtmStats._fields_}
+    n = min(sd["iterations"] + 1, hist_cap)
+    return st, [hist[i] for i in range(n)], sd
+
+
+def atm_status_string(status: int) -> str:
+    return _abi.lib().atm_status_string(int(status)).decode()
+
+
+def atm_last_error() -> str:
+    return _abi.lib().atm_last_error().decode()

@@ -1,0 +1,501 @@
+// Host side of libatmgrit.so: argument validation, workspace layout, launch
+// sequencing of the two-level AT-MGRIT cycle (Alg. 1) and the C-ABI.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <string>
+
+#include "../../include/atm.h"
+#include "atm_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+atm_status fail(atm_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+atm_status fail(atm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define ATM_HIP(call)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess) return fail(ATM_ERR_DEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t header, partials, ya, yb, e, tau, total;
+};
+
+int64_t n_intervals(const atm_problem* p, const atm_options* o) { return p->nt / o->m; }
+int64_t n_space(const atm_problem* p) { return (int64_t)p->nx * p->ny; }
+
+bool use_fas(const atm_problem* p, const atm_options* o)
+{
+    if (o->coarse_form == 1) return false;
+    if (o->coarse_form == 2) return true;
+    return p->kind == ATM_AC2D;
+}
+
+Layout layout(const atm_problem* p, const atm_options* o)
+{
+    const size_t NT = (size_t)n_intervals(p, o);
+    const size_t slab = (NT + 1) * (size_t)n_space(p) * sizeof(double);
+    Layout L;
+    size_t off = 0;
+    L.header = off;
+    off += align_up(sizeof(atm::Header));
+    L.partials = off;
+    off += align_up((NT + 1) * sizeof(double));
+    L.ya = off;
+    off += align_up(slab);
+    L.yb = off;
+    off += align_up(slab);
+    L.e = off;
+    off += align_up(slab);
+    L.tau = off;
+    off += use_fas(p, o) ? align_up(slab) : 0;
+    L.total = off;
+    return L;
+}
+
+atm_status validate(const atm_problem* p, const atm_options* o)
+{
+    if (!p || !o) return fail(ATM_ERR_INVALID_ARG, "null problem or options");
+    if (p->kind != ATM_HEAT1D && p->kind != ATM_HEAT2D && p->kind != ATM_AC2D)
+        return fail(ATM_ERR_INVALID_ARG, "unknown problem kind %d", p->kind);
+    if (p->nx < 1 || p->ny < 1) return fail(ATM_ERR_INVALID_ARG, "nx, ny must be >= 1");
+    if (p->kind == ATM_HEAT1D && p->ny != 1) return fail(ATM_ERR_INVALID_ARG, "ATM_HEAT1D needs ny == 1");
+    if (!(p->length > 0.0) || !(p->nu > 0.0)) return fail(ATM_ERR_INVALID_ARG, "length and nu must be > 0");
+    if (p->kind == ATM_AC2D && !(p->eps > 0.0)) return fail(ATM_ERR_INVALID_ARG, "eps must be > 0");
+    if (!(p->tf > p->t0)) return fail(ATM_ERR_INVALID_ARG, "tf must exceed t0");
+    if (p->nt < 1) return fail(ATM_ERR_INVALID_ARG, "nt must be >= 1");
+    if (p->kind != ATM_HEAT1D && (!(p->cg_rtol >= 0.0) || p->cg_max_iter < 1))
+        return fail(ATM_ERR_INVALID_ARG, "cg_rtol must be >= 0 and cg_max_iter >= 1");
+    if (o->m < 2) return fail(ATM_ERR_INVALID_ARG, "coarsening factor m must be >= 2");
+    if (p->nt < o->m) return fail(ATM_ERR_INVALID_ARG, "nt (%lld) must be >= m (%d)", (long long)p->nt, o->m);
+    if (o->k < 1) return fail(ATM_ERR_INVALID_ARG, "k must be >= 1");
+    if (o->relax != 0 && o->relax != 1) return fail(ATM_ERR_INVALID_ARG, "relax must be 0 (F) or 1 (FCF)");
+    if (o->coarse_substeps < 1) return fail(ATM_ERR_INVALID_ARG, "coarse_substeps must be >= 1");
+    if (o->coarse_form < 0 || o->coarse_form > 2) return fail(ATM_ERR_INVALID_ARG, "coarse_form must be 0, 1 or 2");
+    if (o->max_iter < 0) return fail(ATM_ERR_INVALID_ARG, "max_iter must be >= 0");
+    if (!(o->tol >= 0.0)) return fail(ATM_ERR_INVALID_ARG, "tol must be >= 0");
+    if (o->precision != 0) return fail(ATM_ERR_UNSUPPORTED, "only precision 0 (FP64) is available in this entry point");
+    if (o->reserved_d != 0.0) return fail(ATM_ERR_INVALID_ARG, "reserved fields must be 0");
+    if (o->profile != 0 && o->profile != 1) return fail(ATM_ERR_INVALID_ARG, "profile must be 0 or 1");
+    if (p->kind == ATM_HEAT1D) {
+        if (p->nx > 1024) return fail(ATM_ERR_UNSUPPORTED, "1D grids are limited to nx <= 1024");
+    } else {
+        if (p->nx > atm::kMaxSide2D || p->ny > atm::kMaxSide2D)
+            return fail(ATM_ERR_UNSUPPORTED, "2D FP64 grids are limited to %d x %d", atm::kMaxSide2D, atm::kMaxSide2D);
+        if (p->kind == ATM_AC2D && (p->nx < 3 || p->ny < 3))
+            return fail(ATM_ERR_UNSUPPORTED, "periodic grids need at least 3 points per side");
+    }
+    return ATM_OK;
+}
+
+atm::StepCoef step_coef(const atm_problem* p, double dt)
+{
+    atm::StepCoef c;
+    const bool per = (p->kind == ATM_AC2D);
+    const double hx = per ? p->length / p->nx : p->length / (p->nx + 1);
+    const double hy = per ? p->length / p->ny : p->length / (p->ny + 1);
+    c.cx = p->nu * dt / (hx * hx);
+    c.cy = (p->kind == ATM_HEAT1D) ? 0.0 : p->nu * dt / (hy * hy);
+    c.d = 1.0 + 2.0 * c.cx + 2.0 * c.cy;
+    c.inv_d = 1.0 / c.d;
+    c.react = (p->kind == ATM_AC2D) ? dt / (p->eps * p->eps) : 0.0;
+    return c;
+}
+
+// Fill the kernel argument block for a workspace (or NULL for size-only).
+atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_t ws_bytes, atm::KArgs& a)
+{
+    atm_status st = validate(p, o);
+    if (st) return st;
+    const Layout L = layout(p, o);
+    if (ws_bytes < L.total)
+        return fail(ATM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, L.total);
+    if (!ws) return fail(ATM_ERR_INVALID_ARG, "null workspace");
+    if (((uintptr_t)ws) % kAlign) return fail(ATM_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
+    memset(&a, 0, sizeof(a));
+    char* base = (char*)ws;
+    a.hdr = (atm::Header*)(base + L.header);
+    a.fail = &a.hdr->fail;
+    a.cg_count = &a.hdr->cg_fine;
+    a.partials = (double*)(base + L.partials);
+    a.tau = use_fas(p, o) ? (double*)(base + L.tau) : nullptr;
+    a.nt = p->nt;
+    a.n = n_space(p);
+    a.NT = n_intervals(p, o);
+    a.m = o->m;
+    a.k = o->k;
+    a.fas = use_fas(p, o) ? 1 : 0;
+    a.substeps = o->coarse_substeps;
+    a.nx = p->nx;
+    a.is1d = (p->kind == ATM_HEAT1D);
+    const double dt = (p->tf - p->t0) / (double)p->nt;
+    a.fine = step_coef(p, dt);
+    a.coarse = step_coef(p, dt * o->m / o->coarse_substeps);
+    a.rtol2 = p->cg_rtol * p->cg_rtol;
+    a.maxit = p->cg_max_iter;
+    if (!a.is1d) {
+        // strips: TX = 64 or 128 threads along x, TY = 512 / TX strips along y,
+        // rows a multiple of 2 (16-byte LDS accesses of doubles)
+        const int tx_log2 = p->nx > 64 ? 7 : 6;
+        const int TX = 1 << tx_log2;
+        const int TY = atm::kBlock2D / TX;
+        int rows = (p->ny + TY - 1) / TY;
+        rows = (rows + 1) / 2 * 2;
+        a.g.nx = p->nx;
+        a.g.ny = p->ny;
+        a.g.tx_log2 = tx_log2;
+        a.g.rows = rows;
+        a.g.periodic = (p->kind == ATM_AC2D);
+        a.s_tmpl = rows <= 8 ? 8 : (rows <= 16 ? 16 : 32);
+        if (rows > 32) return fail(ATM_ERR_UNSUPPORTED, "grid needs %d rows per strip (max 32)", rows);
+        a.exact = (p->nx == TX && rows * TY == p->ny && rows == a.s_tmpl) ? 1 : 0;
+        // Every LDS access of a strip stays inside its own column of H values:
+        // the deepest strip that owns rows starts at y0_last and touches column
+        // indices up to y0_last + V + S (the value below its last row).
+        const int H = atm::Lds2D<double>::H, V = atm::Lds2D<double>::V;
+        const int y0_last = ((p->ny - 1) / rows) * rows;
+        if (y0_last + V + a.s_tmpl >= H || p->nx + 2 > atm::kMaxSide2D + 2)
+            return fail(ATM_ERR_UNSUPPORTED, "grid %d x %d does not fit the LDS strip layout", p->nx, p->ny);
+    }
+    return ATM_OK;
+}
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+atm_status check_launch()
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(ATM_ERR_DEVICE, "kernel launch: %s", hipGetErrorString(e));
+    return ATM_OK;
+}
+
+int64_t sweep_tasks(const atm_problem* p, const atm_options* o)
+{
+    const int64_t NT = n_intervals(p, o);
+    return (NT * o->m < p->nt) ? NT + 1 : NT;
+}
+
+// Read back the header (norm, failure flag, CG count) after synchronising.
+atm_status read_header(const atm::KArgs& a, hipStream_t s, atm::Header* out)
+{
+    ATM_HIP(hipMemcpyAsync(out, a.hdr, sizeof(atm::Header), hipMemcpyDeviceToHost, s));
+    ATM_HIP(hipStreamSynchronize(s));
+    return ATM_OK;
+}
+
+atm_status do_sweep(atm::KArgs a, const atm_problem* p, const atm_options* o, int mode, double* u, const double* aux,
+                    double* y, hipStream_t s)
+{
+    a.mode = mode;
+    a.u = u;
+    a.aux = aux;
+    a.y = y;
+    atm::launch_sweep(a, sweep_tasks(p, o), s);
+    return check_launch();
+}
+
+atm_status do_coarse(atm::KArgs a, double* u, double* y, double* e, hipStream_t s)
+{
+    a.cg_count = &a.hdr->cg_coarse;
+    a.u = u;
+    a.y = y;
+    a.e = e;
+    if (a.fas) {
+        atm::launch_tau(a, s);
+        atm_status st = check_launch();
+        if (st) return st;
+    }
+    atm::launch_coarse(a, s);
+    return check_launch();
+}
+
+atm_status do_norm(atm::KArgs a, double* u, double* y, hipStream_t s, double* norm_out, atm::Header* hdr)
+{
+    a.u = u;
+    a.y = y;
+    atm::launch_norm(a, s);
+    atm_status st = check_launch();
+    if (st) return st;
+    st = read_header(a, s, hdr);
+    if (st) return st;
+    *norm_out = sqrt(hdr->norm2);
+    if (hdr->fail) return fail(ATM_ERR_INNER_SOLVE, "a CG solve inside Phi or Psi did not reach cg_rtol within %d iterations",
+                               a.maxit);
+    return ATM_OK;
+}
+
+// Options used by atm_sequential (only the workspace header is needed).
+atm_options sequential_options()
+{
+    atm_options o;
+    memset(&o, 0, sizeof(o));
+    o.m = 2;
+    o.k = 1;
+    o.max_iter = 1;
+    o.coarse_substeps = 1;
+    o.coarse_form = 1;
+    return o;
+}
+
+// Optional per-launch device timing with HIP events on the solve's stream.
+struct PhaseTimer {
+    bool on = false;
+    hipEvent_t ev[8];
+    int used = 0;
+    double ms[3] = {0.0, 0.0, 0.0};
+    int phase[4];
+    atm_status init(bool enable)
+    {
+        on = enable;
+        if (!on) return ATM_OK;
+        for (int i = 0; i < 8; ++i) ATM_HIP(hipEventCreate(&ev[i]));
+        return ATM_OK;
+    }
+    atm_status begin(int ph, hipStream_t s)
+    {
+        if (!on) return ATM_OK;
+        phase[used / 2] = ph;
+        ATM_HIP(hipEventRecord(ev[used++], s));
+        return ATM_OK;
+    }
+    atm_status end(hipStream_t s)
+    {
+        if (!on) return ATM_OK;
+        ATM_HIP(hipEventRecord(ev[used++], s));
+        return ATM_OK;
+    }
+    // after a stream synchronisation: fold the recorded pairs into the totals
+    atm_status collect()
+    {
+        if (!on) return ATM_OK;
+        for (int i = 0; i + 1 < used; i += 2) {
+            float t = 0.0f;
+            ATM_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+            ms[phase[i / 2]] += t;
+        }
+        used = 0;
+        return ATM_OK;
+    }
+    ~PhaseTimer()
+    {
+        if (on)
+            for (int i = 0; i < 8; ++i) (void)hipEventDestroy(ev[i]);
+    }
+};
+enum { kPhSweep = 0, kPhCoarse = 1, kPhNorm = 2 };
+
+int64_t window_psi_count(int64_t NT, int64_t k)
+{
+    // sum over p = 0..N_T of min(p, k-1)
+    int64_t tot = 0;
+    for (int64_t p = 0; p <= NT; ++p) tot += (p < k - 1 ? p : k - 1);
+    return tot;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t atm_num_intervals(const atm_problem* prob, const atm_options* opts)
+{
+    if (!prob || !opts || opts->m < 1) return 0;
+    return n_intervals(prob, opts);
+}
+
+int64_t atm_window_start(int64_t p, int32_t k) { return p - k + 1 > 0 ? p - k + 1 : 0; }
+
+size_t atm_workspace_bytes(const atm_problem* prob, const atm_options* opts)
+{
+    if (validate(prob, opts) != ATM_OK) return 0;
+    return layout(prob, opts).total;
+}
+
+atm_status atm_sweep(const atm_problem* prob, const atm_options* opts, int32_t mode, double* u, const double* aux,
+                     double* y, void* ws, size_t ws_bytes, void* stream)
+{
+    atm::KArgs a;
+    atm_status st = make_args(prob, opts, ws, ws_bytes, a);
+    if (st) return st;
+    if (mode < 0 || mode > 2) return fail(ATM_ERR_INVALID_ARG, "sweep mode must be 0, 1 or 2");
+    if (!u || !y) return fail(ATM_ERR_INVALID_ARG, "null u or y");
+    if (mode != 0 && !aux) return fail(ATM_ERR_INVALID_ARG, "sweep modes 1 and 2 need aux");
+    if (aux == y) return fail(ATM_ERR_INVALID_ARG, "aux and y must not alias");
+    return do_sweep(a, prob, opts, mode, u, aux, y, as_stream(stream));
+}
+
+atm_status atm_coarse_solve(const atm_problem* prob, const atm_options* opts, const double* u, const double* y,
+                            double* e, void* ws, size_t ws_bytes, void* stream)
+{
+    atm::KArgs a;
+    atm_status st = make_args(prob, opts, ws, ws_bytes, a);
+    if (st) return st;
+    if (!u || !y || !e) return fail(ATM_ERR_INVALID_ARG, "null u, y or e");
+    if (e == y) return fail(ATM_ERR_INVALID_ARG, "e and y must not alias");
+    return do_coarse(a, (double*)u, (double*)y, e, as_stream(stream));
+}
+
+atm_status atm_residual_norm(const atm_problem* prob, const atm_options* opts, const double* u, const double* y,
+                             double* norm_out, void* ws, size_t ws_bytes, void* stream)
+{
+    atm::KArgs a;
+    atm_status st = make_args(prob, opts, ws, ws_bytes, a);
+    if (st) return st;
+    if (!u || !y || !norm_out) return fail(ATM_ERR_INVALID_ARG, "null u, y or norm_out");
+    atm::Header h;
+    st = do_norm(a, (double*)u, (double*)y, as_stream(stream), norm_out, &h);
+    if (st == ATM_OK && !isfinite(*norm_out)) return fail(ATM_ERR_DIVERGED, "non-finite residual norm");
+    return st;
+}
+
+atm_status atm_sequential(const atm_problem* prob, double* u, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!prob) return fail(ATM_ERR_INVALID_ARG, "null problem");
+    if (prob->nt < 2) return fail(ATM_ERR_INVALID_ARG, "atm_sequential needs nt >= 2");
+    const atm_options o = sequential_options();
+    atm::KArgs a;
+    atm_status st = make_args(prob, &o, ws, ws_bytes, a);
+    if (st) return st;
+    if (!u) return fail(ATM_ERR_INVALID_ARG, "null u");
+    a.u = u;
+    hipStream_t s = as_stream(stream);
+    atm::launch_reset(a.hdr, s);
+    atm::launch_sequential(a, s);
+    st = check_launch();
+    if (st) return st;
+    atm::Header h;
+    st = read_header(a, s, &h);
+    if (st) return st;
+    if (h.fail) return fail(ATM_ERR_INNER_SOLVE, "a CG solve did not reach cg_rtol within %d iterations", a.maxit);
+    return ATM_OK;
+}
+
+size_t atm_sequential_workspace_bytes(const atm_problem* prob)
+{
+    if (!prob || prob->nt < 2) return 0;
+    const atm_options o = sequential_options();
+    return atm_workspace_bytes(prob, &o);
+}
+
+atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u, void* ws, size_t ws_bytes,
+                     double* hist, int32_t hist_cap, atm_stats* stats, void* stream)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    atm::KArgs a;
+    atm_status st = make_args(prob, opts, ws, ws_bytes, a);
+    if (st) return st;
+    if (!u) return fail(ATM_ERR_INVALID_ARG, "null u");
+    if (hist_cap < 0) return fail(ATM_ERR_INVALID_ARG, "hist_cap must be >= 0");
+    const Layout L = layout(prob, opts);
+    char* base = (char*)ws;
+    double* ya = (double*)(base + L.ya);
+    double* yb = (double*)(base + L.yb);
+    double* e = (double*)(base + L.e);
+    hipStream_t s = as_stream(stream);
+    atm::launch_reset(a.hdr, s);
+    if ((st = check_launch())) return st;
+
+    const int64_t NT = n_intervals(prob, opts);
+    atm_stats S;
+    memset(&S, 0, sizeof(S));
+    atm::Header h;
+    memset(&h, 0, sizeof(h));
+    PhaseTimer T;
+    if ((st = T.init(opts->profile == 1))) return st;
+#define ATM_TIMED(ph, expr)                           \
+    do {                                              \
+        if ((st = T.begin((ph), s))) break;           \
+        if ((st = (expr))) break;                     \
+        if ((st = T.end(s))) break;                   \
+    } while (0)
+    // F-relax the initial guess, then its residual
+    ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 0, u, nullptr, ya, s));
+    if (st) return st;
+    S.fine_steps += prob->nt;
+    S.n_sweeps += 1;
+    double res = 0.0;
+    ATM_TIMED(kPhNorm, do_norm(a, u, ya, s, &res, &h));
+    if (st == ATM_OK) st = T.collect();
+    if (st == ATM_OK && hist && hist_cap > 0) hist[0] = res;
+    int it = 0;
+    while (st == ATM_OK && !(res <= opts->tol)) {
+        if (!isfinite(res)) {
+            st = fail(ATM_ERR_DIVERGED, "non-finite residual norm after %d cycles", it);
+            break;
+        }
+        if (it >= opts->max_iter) {
+            st = ATM_NOT_CONVERGED;
+            break;
+        }
+        double* ycur = ya;
+        if (opts->relax == 1) {
+            // CF: C-points take Phi of their preceding F-point (held in ya), then F-relax
+            ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 2, u, ya, yb, s));
+            if (st) break;
+            S.fine_steps += prob->nt;
+            S.n_sweeps += 1;
+            ycur = yb;
+        }
+        ATM_TIMED(kPhCoarse, do_coarse(a, u, ycur, e, s));
+        if (st) break;
+        S.coarse_steps += window_psi_count(NT, opts->k) + (a.fas ? NT : 0);
+        // correction u_{pm} += e_p and F-interpolation; ya receives Phi of every last F-point
+        ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 1, u, e, ya, s));
+        if (st) break;
+        S.fine_steps += prob->nt;
+        S.n_sweeps += 1;
+        ++it;
+        ATM_TIMED(kPhNorm, do_norm(a, u, ya, s, &res, &h));
+        if (st == ATM_OK) st = T.collect();
+        if (st == ATM_OK && hist && it < hist_cap) hist[it] = res;
+    }
+#undef ATM_TIMED
+    if (st == ATM_OK && !isfinite(res)) st = fail(ATM_ERR_DIVERGED, "non-finite residual norm");
+    S.iterations = it;
+    S.final_residual = res;
+    S.cg_fine = (int64_t)h.cg_fine;
+    S.cg_coarse = (int64_t)h.cg_coarse;
+    S.ms_sweep = T.ms[kPhSweep];
+    S.ms_coarse = T.ms[kPhCoarse];
+    S.ms_norm = T.ms[kPhNorm];
+    S.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (stats) *stats = S;
+    return st;
+}
+
+const char* atm_status_string(atm_status status)
+{
+    switch (status) {
+        case ATM_OK: return "ATM_OK";
+        case ATM_NOT_CONVERGED: return "ATM_NOT_CONVERGED";
+        case ATM_ERR_INVALID_ARG: return "ATM_ERR_INVALID_ARG";
+        case ATM_ERR_UNSUPPORTED: return "ATM_ERR_UNSUPPORTED";
+        case ATM_ERR_DEVICE: return "ATM_ERR_DEVICE";
+        case ATM_ERR_DIVERGED: return "ATM_ERR_DIVERGED";
+        case ATM_ERR_INNER_SOLVE: return "ATM_ERR_INNER_SOLVE";
+        case ATM_ERR_WORKSPACE: return "ATM_ERR_WORKSPACE";
+        default: return "ATM_UNKNOWN_STATUS";
+    }
+}
+
+const char* atm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

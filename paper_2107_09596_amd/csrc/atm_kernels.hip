@@ -1,0 +1,413 @@
+// HIP kernels of the two-level AT-MGRIT hot path (FP64 form), gfx950.
+//
+// Layout: u is [nt+1][n] FP64, t = j m + i; y, e, tau are [N_T+1][n].
+// One workgroup owns one coarse interval (relaxation sweeps) or one local coarse
+// grid (window solves); the sequential time loop of that interval/window runs
+// inside the workgroup with the current state held on chip, so HBM sees each
+// fine point written once per sweep and never re-read by the sweep.
+#include "atm_device.hpp"
+#include "atm_kernels.hpp"
+
+namespace atm {
+
+// ---------------------------------------------------------------------------
+// shared helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double cpoint_residual(const KArgs& a, int64_t j, int64_t idx)
+{
+    // r_0 = g_0 - u_0 = 0 (u_0 is never modified); r_j = Phi(u_{jm-1}) - u_{jm}
+    if (j == 0) return 0.0;
+    return a.y[j * a.n + idx] - a.u[(j * a.m) * a.n + idx];
+}
+
+// C-point value that starts interval j of a sweep
+__device__ __forceinline__ double sweep_start(const KArgs& a, int64_t j, int64_t idx)
+{
+    const double uc = a.u[(j * a.m) * a.n + idx];
+    if (a.mode == 1) return uc + a.aux[j * a.n + idx];
+    if (a.mode == 2) return j == 0 ? uc : a.aux[j * a.n + idx];
+    return uc;
+}
+
+__device__ __forceinline__ void count_cg(const KArgs& a, long long its)
+{
+    if (threadIdx.x == 0 && its) atomicAdd(a.cg_count, (unsigned long long)its);
+}
+
+// ---------------------------------------------------------------------------
+// 1D heat: PCR tridiagonal steps, one workgroup (nx rounded up to wave64) per task
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void sweep1d_kernel(KArgs a)
+{
+    __shared__ double lds[3 * 1024];
+    const int64_t j = blockIdx.x;
+    const int i = threadIdx.x;
+    const bool act = i < a.nx;
+    Pcr1D f;
+    pcr_setup(f, a.nx, a.fine.cx, lds);
+    double x = 0.0;
+    if (act) {
+        x = sweep_start(a, j, i);
+        if (a.mode != 0) a.u[(j * a.m) * a.n + i] = x;
+    }
+    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
+    for (int64_t t = 1; t <= total; ++t) {
+        x = pcr_solve(f, a.nx, x, lds);
+        if (act) {
+            if (t < a.m)
+                a.u[(j * a.m + t) * a.n + i] = x;
+            else
+                a.y[(j + 1) * a.n + i] = x;
+        }
+    }
+}
+
+// Psi: s substeps with the coarse factors
+__device__ __forceinline__ double psi1d(const KArgs& a, const Pcr1D& fc, double x, double* lds)
+{
+    for (int q = 0; q < a.substeps; ++q) x = pcr_solve(fc, a.nx, x, lds);
+    return x;
+}
+
+__global__ __launch_bounds__(1024) void coarse1d_kernel(KArgs a)
+{
+    __shared__ double lds[3 * 1024];
+    const int64_t p = blockIdx.x;
+    const int i = threadIdx.x;
+    const bool act = i < a.nx;
+    Pcr1D fc;
+    pcr_setup(fc, a.nx, a.coarse.cx, lds);
+    const int64_t s = p - a.k + 1 > 0 ? p - a.k + 1 : 0;
+    double w = 0.0, vs = 0.0;
+    if (act) {
+        if (a.fas) {
+            vs = a.u[(s * a.m) * a.n + i];
+            w = vs + cpoint_residual(a, s, i);
+        } else {
+            w = cpoint_residual(a, s, i);
+        }
+    }
+    for (int64_t jj = s + 1; jj <= p; ++jj) {
+        w = psi1d(a, fc, w, lds);
+        if (act) w = w + (a.fas ? a.tau[jj * a.n + i] : cpoint_residual(a, jj, i));
+    }
+    if (act) a.e[p * a.n + i] = a.fas ? w - a.u[(p * a.m) * a.n + i] : w;
+}
+
+// tau_j = (v_j - Psi(v_{j-1})) + r_j, j = 1..N_T (FAS right-hand side, shared by all windows)
+__global__ __launch_bounds__(1024) void tau1d_kernel(KArgs a)
+{
+    __shared__ double lds[3 * 1024];
+    const int64_t j = blockIdx.x + 1;
+    const int i = threadIdx.x;
+    const bool act = i < a.nx;
+    Pcr1D fc;
+    pcr_setup(fc, a.nx, a.coarse.cx, lds);
+    double v = act ? a.u[((j - 1) * a.m) * a.n + i] : 0.0;
+    v = psi1d(a, fc, v, lds);
+    if (act) {
+        const double vj = a.u[(j * a.m) * a.n + i];
+        a.tau[j * a.n + i] = (vj - v) + cpoint_residual(a, j, i);
+    }
+}
+
+__global__ __launch_bounds__(1024) void seq1d_kernel(KArgs a)
+{
+    __shared__ double lds[3 * 1024];
+    const int i = threadIdx.x;
+    const bool act = i < a.nx;
+    Pcr1D f;
+    pcr_setup(f, a.nx, a.fine.cx, lds);
+    double x = act ? a.u[i] : 0.0;
+    for (int64_t t = 1; t <= a.nt; ++t) {
+        x = pcr_solve(f, a.nx, x, lds);
+        if (act) a.u[t * a.n + i] = x;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D: one 512-thread workgroup per task, CG with p in LDS
+// ---------------------------------------------------------------------------
+
+
+template <int S>
+struct Strip2DState {
+    double x[S], r[S], q[S];
+};
+
+// Strip offsets in global memory pass through an empty asm at every use, so
+// the compiler recomputes the per-row addresses instead of hoisting all of
+// them out of the time loop (which would cost a register pair per row).
+__device__ __forceinline__ int64_t opaque_off(int v)
+{
+    __asm__ volatile("" : "+v"(v));
+    return (int64_t)v;
+}
+
+template <int S, bool EX>
+__device__ __forceinline__ void strip_store(double* dst, const Strip& st, int nx, const double (&v)[S])
+{
+    const int64_t off = opaque_off(st.gbase);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if (row_ok<EX, S>(st, s)) dst[off + (int64_t)s * nx] = v[s];
+}
+
+// One integrator step of size given by coefficients c, on the strip state.
+template <int S, bool EX, bool PER>
+__device__ __forceinline__ int step2d(const KArgs& a, const StepCoef& c, const Strip& st, Strip2DState<S>& v,
+                                      double* lp, double* red, int& slot)
+{
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const double xs = v.x[s];
+        v.r[s] = c.react != 0.0 ? xs + c.react * (xs - xs * xs * xs) : xs;
+    }
+    return cg2d<double, S, EX, PER, true>(a.g, c, st, v.x, v.r, v.q, lp, red, slot, a.rtol2, a.maxit, a.fail);
+}
+
+template <int S, bool EX, bool PER>
+__global__ __launch_bounds__(kBlock2D) void sweep2d_kernel(KArgs a)
+{
+    __shared__ __align__(16) double lp[Lds2D<double>::size];
+    __shared__ double red[4 * kWaves2D];
+    int slot = 0;
+    const int64_t j = blockIdx.x;
+    const Strip st = make_strip<double>(a.g);
+    lds_clear(lp);
+    Strip2DState<S> v;
+    const int nx = a.g.nx;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        v.x[s] = 0.0;
+        if (row_ok<EX, S>(st, s)) {
+            const int64_t idx = (int64_t)(st.gbase + s * nx);
+            v.x[s] = sweep_start(a, j, idx);
+            if (a.mode != 0) a.u[(j * a.m) * a.n + idx] = v.x[s];
+        }
+    }
+    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
+    long long its = 0;
+    for (int64_t t = 1; t <= total; ++t) {
+        its += step2d<S, EX, PER>(a, a.fine, st, v, lp, red, slot);
+        double* dst = (t < a.m) ? a.u + (j * a.m + t) * a.n : a.y + (j + 1) * a.n;
+        strip_store<S, EX>(dst, st, nx, v.x);
+    }
+    count_cg(a, its);
+}
+
+template <int S, bool EX, bool PER>
+__device__ __forceinline__ long long psi2d(const KArgs& a, const Strip& st, Strip2DState<S>& v, double* lp,
+                                           double* red, int& slot)
+{
+    long long its = 0;
+    for (int q = 0; q < a.substeps; ++q) its += step2d<S, EX, PER>(a, a.coarse, st, v, lp, red, slot);
+    return its;
+}
+
+template <int S, bool EX, bool PER>
+__global__ __launch_bounds__(kBlock2D) void coarse2d_kernel(KArgs a)
+{
+    __shared__ __align__(16) double lp[Lds2D<double>::size];
+    __shared__ double red[4 * kWaves2D];
+    int slot = 0;
+    const int64_t p = blockIdx.x;
+    const int64_t s0 = p - a.k + 1 > 0 ? p - a.k + 1 : 0;
+    const Strip st = make_strip<double>(a.g);
+    lds_clear(lp);
+    const int nx = a.g.nx;
+    Strip2DState<S> v;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        v.x[s] = 0.0;
+        if (row_ok<EX, S>(st, s)) {
+            const int64_t idx = (int64_t)(st.gbase + s * nx);
+            const double r = cpoint_residual(a, s0, idx);
+            v.x[s] = a.fas ? a.u[(s0 * a.m) * a.n + idx] + r : r;
+        }
+    }
+    long long its = 0;
+    for (int64_t jj = s0 + 1; jj <= p; ++jj) {
+        its += psi2d<S, EX, PER>(a, st, v, lp, red, slot);
+        const int64_t off = opaque_off(st.gbase);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (row_ok<EX, S>(st, s)) {
+                const int64_t idx = off + (int64_t)s * nx;
+                v.x[s] = v.x[s] + (a.fas ? a.tau[jj * a.n + idx] : cpoint_residual(a, jj, idx));
+            }
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if (row_ok<EX, S>(st, s)) {
+            const int64_t idx = (int64_t)(st.gbase + s * nx);
+            a.e[p * a.n + idx] = a.fas ? v.x[s] - a.u[(p * a.m) * a.n + idx] : v.x[s];
+        }
+    count_cg(a, its);
+}
+
+template <int S, bool EX, bool PER>
+__global__ __launch_bounds__(kBlock2D) void tau2d_kernel(KArgs a)
+{
+    __shared__ __align__(16) double lp[Lds2D<double>::size];
+    __shared__ double red[4 * kWaves2D];
+    int slot = 0;
+    const int64_t j = blockIdx.x + 1;
+    const Strip st = make_strip<double>(a.g);
+    lds_clear(lp);
+    const int nx = a.g.nx;
+    Strip2DState<S> v;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        v.x[s] = 0.0;
+        if (row_ok<EX, S>(st, s)) v.x[s] = a.u[((j - 1) * a.m) * a.n + (int64_t)(st.gbase + s * nx)];
+    }
+    long long its = psi2d<S, EX, PER>(a, st, v, lp, red, slot);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if (row_ok<EX, S>(st, s)) {
+            const int64_t idx = (int64_t)(st.gbase + s * nx);
+            const double vj = a.u[(j * a.m) * a.n + idx];
+            a.tau[j * a.n + idx] = (vj - v.x[s]) + cpoint_residual(a, j, idx);
+        }
+    count_cg(a, its);
+}
+
+template <int S, bool EX, bool PER>
+__global__ __launch_bounds__(kBlock2D) void seq2d_kernel(KArgs a)
+{
+    __shared__ __align__(16) double lp[Lds2D<double>::size];
+    __shared__ double red[4 * kWaves2D];
+    int slot = 0;
+    const Strip st = make_strip<double>(a.g);
+    lds_clear(lp);
+    const int nx = a.g.nx;
+    Strip2DState<S> v;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        v.x[s] = 0.0;
+        if (row_ok<EX, S>(st, s)) v.x[s] = a.u[(int64_t)(st.gbase + s * nx)];
+    }
+    long long its = 0;
+    for (int64_t t = 1; t <= a.nt; ++t) {
+        its += step2d<S, EX, PER>(a, a.fine, st, v, lp, red, slot);
+        strip_store<S, EX>(a.u + t * a.n, st, nx, v.x);
+    }
+    count_cg(a, its);
+}
+
+// ---------------------------------------------------------------------------
+// residual norm: deterministic two-stage sum of ||y_j - u_{jm}||^2, j = 1..N_T
+// ---------------------------------------------------------------------------
+
+constexpr int kNormBlock = 256;
+
+__global__ __launch_bounds__(kNormBlock) void norm_partial_kernel(KArgs a)
+{
+    __shared__ double red[2 * 2 * (kNormBlock / 64)];
+    int slot = 0;
+    const int64_t j = blockIdx.x + 1;
+    double acc = 0.0, unused = 0.0;
+    for (int64_t idx = threadIdx.x; idx < a.n; idx += kNormBlock) {
+        const double r = a.y[j * a.n + idx] - a.u[(j * a.m) * a.n + idx];
+        acc += r * r;
+    }
+    block_sum2(acc, unused, red, slot, kNormBlock / 64);
+    if (threadIdx.x == 0) a.partials[j] = acc;
+}
+
+__global__ __launch_bounds__(kNormBlock) void norm_final_kernel(KArgs a)
+{
+    __shared__ double red[2 * 2 * (kNormBlock / 64)];
+    int slot = 0;
+    double acc = 0.0, unused = 0.0;
+    for (int64_t j = 1 + threadIdx.x; j <= a.NT; j += kNormBlock) acc += a.partials[j];
+    block_sum2(acc, unused, red, slot, kNormBlock / 64);
+    if (threadIdx.x == 0) a.hdr->norm2 = acc;
+}
+
+__global__ void reset_header_kernel(Header* h)
+{
+    if (threadIdx.x == 0) {
+        h->norm2 = 0.0;
+        h->fail = 0;
+        h->cg_fine = 0ull;
+        h->cg_coarse = 0ull;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+#define ATM_LAUNCH_S(kernel, S, EX, PER, grid, stream, args)                                                 \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(kernel<S, EX, PER>), dim3(grid), dim3(kBlock2D), 0, (hipStream_t)(stream), \
+                       args)
+
+#define ATM_LAUNCH_EP(kernel, S, grid, stream, args)                             \
+    do {                                                                         \
+        if ((args).exact) {                                                      \
+            if ((args).g.periodic) ATM_LAUNCH_S(kernel, S, true, true, grid, stream, args);    \
+            else ATM_LAUNCH_S(kernel, S, true, false, grid, stream, args);                     \
+        } else {                                                                 \
+            if ((args).g.periodic) ATM_LAUNCH_S(kernel, S, false, true, grid, stream, args);   \
+            else ATM_LAUNCH_S(kernel, S, false, false, grid, stream, args);                    \
+        }                                                                        \
+    } while (0)
+
+// strip length S in {8, 16, 32}; EX = exact tiling (no masked rows); PER = periodic halo
+#define ATM_LAUNCH_2D(kernel, grid, stream, args)                      \
+    do {                                                               \
+        switch ((args).s_tmpl) {                                       \
+            case 8: ATM_LAUNCH_EP(kernel, 8, grid, stream, args); break;   \
+            case 16: ATM_LAUNCH_EP(kernel, 16, grid, stream, args); break; \
+            default: ATM_LAUNCH_EP(kernel, 32, grid, stream, args); break; \
+        }                                                              \
+    } while (0)
+
+static int block1d(const KArgs& a) { return ((a.nx + 63) / 64) * 64; }
+
+void launch_reset(Header* h, hipStream_t s) { hipLaunchKernelGGL(reset_header_kernel, dim3(1), dim3(64), 0, s, h); }
+
+void launch_sweep(const KArgs& a, int64_t n_tasks, hipStream_t s)
+{
+    if (a.is1d)
+        hipLaunchKernelGGL(sweep1d_kernel, dim3(n_tasks), dim3(block1d(a)), 0, s, a);
+    else
+        ATM_LAUNCH_2D(sweep2d_kernel, n_tasks, s, a);
+}
+
+void launch_tau(const KArgs& a, hipStream_t s)
+{
+    if (a.NT < 1) return;
+    if (a.is1d)
+        hipLaunchKernelGGL(tau1d_kernel, dim3(a.NT), dim3(block1d(a)), 0, s, a);
+    else
+        ATM_LAUNCH_2D(tau2d_kernel, a.NT, s, a);
+}
+
+void launch_coarse(const KArgs& a, hipStream_t s)
+{
+    if (a.is1d)
+        hipLaunchKernelGGL(coarse1d_kernel, dim3(a.NT + 1), dim3(block1d(a)), 0, s, a);
+    else
+        ATM_LAUNCH_2D(coarse2d_kernel, a.NT + 1, s, a);
+}
+
+void launch_norm(const KArgs& a, hipStream_t s)
+{
+    if (a.NT >= 1) hipLaunchKernelGGL(norm_partial_kernel, dim3(a.NT), dim3(kNormBlock), 0, s, a);
+    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kNormBlock), 0, s, a);
+}
+
+void launch_sequential(const KArgs& a, hipStream_t s)
+{
+    if (a.is1d)
+        hipLaunchKernelGGL(seq1d_kernel, dim3(1), dim3(block1d(a)), 0, s, a);
+    else
+        ATM_LAUNCH_2D(seq2d_kernel, 1, s, a);
+}
+
+}  // namespace atm
