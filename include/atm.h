@@ -108,8 +108,9 @@ size_t atm_workspace_bytes(const atm_problem* prob, const atm_options* opts);
 
 /* Relaxation sweep over every interval at once (section 2.1 F-relaxation,
    section 2.2 CF-relaxation, Alg. 1 correction with selective ideal
-   interpolation P_S).  Every interval j (0..N_T-1, plus a ragged tail after
-   C-point N_T when m does not divide nt) first sets its C-point value c_j:
+   interpolation P_S).  Every interval j = 0..N_T (interval N_T holds only
+   C-point N_T and the ragged tail after it, empty when m divides nt) first
+   sets its C-point value c_j:
      mode 0: c_j = u_{jm}                 (F-relaxation)
      mode 1: c_j = u_{jm} + aux_j         (correction by e_j = aux_j, then F-interpolation)
      mode 2: c_j = aux_j for j >= 1, u_0 for j = 0   (C-relaxation from aux = Phi(u_{jm-1}),

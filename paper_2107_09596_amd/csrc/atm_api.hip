@@ -188,11 +188,9 @@ atm_status check_launch()
     return ATM_OK;
 }
 
-int64_t sweep_tasks(const atm_problem* p, const atm_options* o)
-{
-    const int64_t NT = n_intervals(p, o);
-    return (NT * o->m < p->nt) ? NT + 1 : NT;
-}
+// Intervals 0..N_T-1 plus task N_T, which owns C-point N_T (its correction and
+// C-relaxation) and the F-points of a ragged tail after it (none when m | nt).
+int64_t sweep_tasks(const atm_problem* p, const atm_options* o) { return n_intervals(p, o) + 1; }
 
 // Read back the header (norm, failure flag, CG count) after synchronising.
 atm_status read_header(const atm::KArgs& a, hipStream_t s, atm::Header* out)
@@ -287,6 +285,7 @@ struct PhaseTimer {
     atm_status collect()
     {
         if (!on) return ATM_OK;
+        if (used > 0) ATM_HIP(hipEventSynchronize(ev[used - 1]));
         for (int i = 0; i + 1 < used; i += 2) {
             float t = 0.0f;
             ATM_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));

@@ -114,8 +114,9 @@ def test_coarse_solves_match_oracle(atm, orc, case, form):
     p, u0 = small(kind, nx, ny, nt)
     o = W.Options(m=m, k=k, relax=1, coarse_form=form, coarse_substeps=2 if kind == W.AC2D else 1)
     NT = p.nt // m
-    u = orc.f_relax(p, o, W.initial_guess(p, u0, "random", seed=4) * 0.5)
-    u[0] = u0
+    g = W.initial_guess(p, u0, "random", seed=4) * 0.5
+    g[0] = u0
+    u = orc.f_relax(p, o, g)
     y = y_of(orc, p, o, u)
     ws = atm.workspace(atm.atm_workspace_bytes(p, o))
     ed = dev(np.zeros((NT + 1, p.n)))
@@ -131,9 +132,9 @@ def test_residual_norm_matches_oracle(atm, orc, case):
     kind, nx, ny, nt, m, k = case
     p, u0 = small(kind, nx, ny, nt)
     o = W.Options(m=m, k=k)
-    NT = p.nt // m
-    u = orc.f_relax(p, o, W.initial_guess(p, u0, "random", seed=6) * 0.5)
-    u[0] = u0
+    g = W.initial_guess(p, u0, "random", seed=6) * 0.5
+    g[0] = u0
+    u = orc.f_relax(p, o, g)
     y = y_of(orc, p, o, u)
     ws = atm.workspace(atm.atm_workspace_bytes(p, o))
     got = atm.atm_residual_norm(p, o, dev(u), dev(y), ws)
@@ -155,7 +156,9 @@ def test_solve_iterates_match_oracle(atm, orc, case, relax):
         status, ghist, gst = atm.atm_solve(p, o, ud)
         assert gst["iterations"] == st["iterations"]
         assert_close(host(ud), ref, what=f"u after {K} cycles")
-        np.testing.assert_allclose(ghist, hist[: len(ghist)], rtol=1e-11, atol=1e-300)
+        # residual norms agree to 1e-11 relative, down to a floor of 1e-13 of the initial residual
+        # (small problems converge exactly, after which both sides print rounding noise)
+        np.testing.assert_allclose(ghist, hist[: len(ghist)], rtol=1e-11, atol=1e-13 * hist[0])
 
 
 @pytest.mark.parametrize("kind,nx,ny,nt", [(W.HEAT1D, 63, 1, 50), (W.HEAT2D, 40, 33, 12), (W.AC2D, 20, 20, 15),
