@@ -70,7 +70,9 @@ typedef struct atm_problem {
 
 typedef struct atm_options {
     double tol;            /* stop when ||g - A(u)||_2 <= tol (absolute, all space-time points) */
-    double reserved_d;     /* must be 0 */
+    double coarse_cg_rtol; /* CG tolerance inside Psi (2D kinds); 0 = the problem's cg_rtol.  Psi only
+                              approximates Phi^m, so this changes the convergence rate, not the
+                              fixed point */
     int32_t m;             /* coarsening factor, >= 2 (section 2.1) */
     int32_t k;             /* C-points per local coarse grid, >= 1; k >= N_T+1 is Parareal */
     int32_t relax;         /* 0: F-relaxation, 1: FCF-relaxation (section 2.2) */

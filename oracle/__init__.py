@@ -34,7 +34,7 @@ class OrProblem(ctypes.Structure):
 
 class OrOptions(ctypes.Structure):
     _fields_ = [
-        ("tol", ctypes.c_double),
+        ("tol", ctypes.c_double), ("coarse_cg_rtol", ctypes.c_double),
         ("m", ctypes.c_int32), ("k", ctypes.c_int32), ("relax", ctypes.c_int32),
         ("max_iter", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32), ("coarse_form", ctypes.c_int32),
     ]
@@ -101,7 +101,8 @@ def _prob(p) -> OrProblem:
 
 
 def _opts(o) -> OrOptions:
-    return OrOptions(tol=o.tol, m=o.m, k=o.k, relax=o.relax, max_iter=o.max_iter,
+    return OrOptions(tol=o.tol, coarse_cg_rtol=getattr(o, "coarse_cg_rtol", 0.0), m=o.m, k=o.k, relax=o.relax,
+                     max_iter=o.max_iter,
                      coarse_substeps=o.coarse_substeps, coarse_form=o.coarse_form)
 
 

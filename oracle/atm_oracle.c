@@ -34,7 +34,9 @@
  *     Jacobi-preconditioned CG started from the input state, stopped when the
  *     recursively updated residual satisfies ||r|| <= rtol ||b||.
  *   - Psi is coarse_substeps steps of size m dt / coarse_substeps of the same
- *     integrator (a re-discretisation with step dT, section 2.1 end).
+ *     integrator (a re-discretisation with step dT, section 2.1 end); its CG
+ *     tolerance is coarse_cg_rtol when set (Psi only approximates Phi^m, so its
+ *     solve accuracy changes the convergence rate, never the fixed point).
  *
  * Status codes: 0 ok, 1 not converged (result valid), -1 invalid argument,
  * -4 diverged (non-finite residual), -5 inner CG did not reach rtol.
@@ -58,6 +60,7 @@ typedef struct {
 
 typedef struct {
     double tol;
+    double coarse_cg_rtol; /* CG tolerance inside Psi; 0 means the fine cg_rtol */
     int32_t m, k, relax, max_iter, coarse_substeps, coarse_form;
 } or_options;
 
@@ -127,7 +130,7 @@ static double dot(int64_t n, const double* a, const double* b)
 /* Jacobi-preconditioned conjugate gradients for M x = b, started from x.
    work holds 4n doubles.  Returns 0, or OR_INNER when rtol is not reached
    within cg_max_iter iterations. */
-static int pcg2d(const or_problem* P, double cx, double cy, const double* b, double* x,
+static int pcg2d(const or_problem* P, double cx, double cy, double rtol, const double* b, double* x,
                  double* work, int64_t* its)
 {
     const int64_t n = nspace(P);
@@ -147,7 +150,7 @@ static int pcg2d(const or_problem* P, double cx, double cy, const double* b, dou
     for (int64_t i = 0; i < n; ++i) p[i] = z[i];
     double rz = dot(n, r, z);
     double rr = dot(n, r, r);
-    const double thresh = P->cg_rtol * P->cg_rtol * bb;
+    const double thresh = rtol * rtol * bb;
     int it = 0;
     while (rr > thresh) {
         if (it >= P->cg_max_iter) return OR_INNER;
@@ -186,10 +189,20 @@ static void thomas(int n, double c, const double* b, double* x, double* work)
     for (int i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
 }
 
-/* One step of the integrator with step size dt: out = Phi_dt(in).
+/* One step of the integrator with step size dt: out = Phi_dt(in), with the
+   linear systems of the 2D kinds solved to relative tolerance rtol.
    work must hold 6n doubles.  out may not alias in. */
+static int step_dt_tol(const or_problem* P, double dt, double rtol, const double* in, double* out,
+                       double* work, int64_t* cg_its);
+
 static int step_dt(const or_problem* P, double dt, const double* in, double* out, double* work,
                    int64_t* cg_its)
+{
+    return step_dt_tol(P, dt, P->cg_rtol, in, out, work, cg_its);
+}
+
+static int step_dt_tol(const or_problem* P, double dt, double rtol, const double* in, double* out,
+                       double* work, int64_t* cg_its)
 {
     const int64_t n = nspace(P);
     if (P->kind == OR_HEAT1D) {
@@ -207,7 +220,7 @@ static int step_dt(const or_problem* P, double dt, const double* in, double* out
         for (int64_t i = 0; i < n; ++i) b[i] = in[i] + s * (in[i] - in[i] * in[i] * in[i]);
     }
     for (int64_t i = 0; i < n; ++i) out[i] = in[i];
-    return pcg2d(P, cx, cy, b, out, work, cg_its);
+    return pcg2d(P, cx, cy, rtol, b, out, work, cg_its);
 }
 
 static int64_t work_len(const or_problem* P) { return 6 * nspace(P); }
@@ -225,11 +238,12 @@ static int coarse_step(const or_problem* P, const or_options* O, const double* i
     const int64_t n = nspace(P);
     const int s = O->coarse_substeps < 1 ? 1 : O->coarse_substeps;
     const double dts = step_size(P) * (double)O->m / (double)s;
+    const double rtol = O->coarse_cg_rtol > 0.0 ? O->coarse_cg_rtol : P->cg_rtol;
     double* tmp = work + work_len(P);
     const double* src = in;
     for (int i = 0; i < s; ++i) {
         double* dst = (i == s - 1) ? out : tmp + (i & 1) * n;
-        int st = step_dt(P, dts, src, dst, work, cg);
+        int st = step_dt_tol(P, dts, rtol, src, dst, work, cg);
         if (st) return st;
         src = dst;
     }

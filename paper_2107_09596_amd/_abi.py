@@ -36,7 +36,7 @@ class AtmProblem(ctypes.Structure):
 
 class AtmOptions(ctypes.Structure):
     _fields_ = [
-        ("tol", ctypes.c_double), ("reserved_d", ctypes.c_double),
+        ("tol", ctypes.c_double), ("coarse_cg_rtol", ctypes.c_double),
         ("m", ctypes.c_int32), ("k", ctypes.c_int32), ("relax", ctypes.c_int32),
         ("max_iter", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32), ("coarse_form", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("profile", ctypes.c_int32),
@@ -113,6 +113,6 @@ def problem(p) -> AtmProblem:
 
 def options(o) -> AtmOptions:
     """AtmOptions from any object with the fields of workloads.Options."""
-    return AtmOptions(tol=o.tol, reserved_d=0.0, m=o.m, k=o.k, relax=o.relax, max_iter=o.max_iter,
+    return AtmOptions(tol=o.tol, coarse_cg_rtol=float(getattr(o, "coarse_cg_rtol", 0.0)), m=o.m, k=o.k, relax=o.relax, max_iter=o.max_iter,
                       coarse_substeps=o.coarse_substeps, coarse_form=o.coarse_form,
                       precision=getattr(o, "precision", 0), profile=int(getattr(o, "profile", 0)))

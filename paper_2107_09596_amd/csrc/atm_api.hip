@@ -94,7 +94,7 @@ atm_status validate(const atm_problem* p, const atm_options* o)
     if (o->max_iter < 0) return fail(ATM_ERR_INVALID_ARG, "max_iter must be >= 0");
     if (!(o->tol >= 0.0)) return fail(ATM_ERR_INVALID_ARG, "tol must be >= 0");
     if (o->precision != 0) return fail(ATM_ERR_UNSUPPORTED, "only precision 0 (FP64) is available in this entry point");
-    if (o->reserved_d != 0.0) return fail(ATM_ERR_INVALID_ARG, "reserved fields must be 0");
+    if (!(o->coarse_cg_rtol >= 0.0)) return fail(ATM_ERR_INVALID_ARG, "coarse_cg_rtol must be >= 0");
     if (o->profile != 0 && o->profile != 1) return fail(ATM_ERR_INVALID_ARG, "profile must be 0 or 1");
     if (p->kind == ATM_HEAT1D) {
         if (p->nx > 1024) return fail(ATM_ERR_UNSUPPORTED, "1D grids are limited to nx <= 1024");
@@ -151,6 +151,8 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
     a.fine = step_coef(p, dt);
     a.coarse = step_coef(p, dt * o->m / o->coarse_substeps);
     a.rtol2 = p->cg_rtol * p->cg_rtol;
+    const double crtol = o->coarse_cg_rtol > 0.0 ? o->coarse_cg_rtol : p->cg_rtol;
+    a.rtol2_coarse = crtol * crtol;
     a.maxit = p->cg_max_iter;
     if (!a.is1d) {
         // strips: TX = 64 or 128 threads along x, TY = 512 / TX strips along y,

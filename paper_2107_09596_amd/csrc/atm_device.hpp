@@ -24,13 +24,36 @@ constexpr int kWaves2D = kBlock2D / 64;
 // reductions
 // ---------------------------------------------------------------------------
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v)
+// Move a double through a DPP lane permutation (two 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
 {
-    // xor butterfly: every lane ends with the same, order-independent value
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wave.  Each 16-lane row is summed by rotations
+// (row_ror 8, 4, 2, 1: every lane of the row ends with the row total, in a
+// lane-dependent order), then lane 0 of every row is read into a scalar and
+// the four row totals are added in a fixed order, so every lane returns the
+// same, reproducible value.  No LDS traffic.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_f64<0x128>(v);  // row_ror:8
+    v += dpp_f64<0x124>(v);  // row_ror:4
+    v += dpp_f64<0x122>(v);  // row_ror:2
+    v += dpp_f64<0x121>(v);  // row_ror:1
+    const double r0 = readlane_f64(v, 0), r1 = readlane_f64(v, 16);
+    const double r2 = readlane_f64(v, 32), r3 = readlane_f64(v, 48);
+    return (r0 + r1) + (r2 + r3);
 }
 
 // Sum two doubles over the block.  `red` holds 2 * 2 * nwaves doubles; the
@@ -61,6 +84,21 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red, in
     b = sb;
     slot ^= 1;
     __builtin_amdgcn_sched_barrier(0);
+}
+
+// One-value form of block_sum2.
+__device__ __forceinline__ double block_sum1(double a, double* red, int& slot, int nwaves)
+{
+    __builtin_amdgcn_sched_barrier(0);
+    a = wave_sum(a);
+    double* base = red + slot * 2 * nwaves;
+    if ((threadIdx.x & 63) == 0) base[threadIdx.x >> 6] = a;
+    __syncthreads();
+    double sa = 0.0;
+    for (int w = 0; w < nwaves; ++w) sa += base[w];
+    slot ^= 1;
+    __builtin_amdgcn_sched_barrier(0);
+    return sa;
 }
 
 // ---------------------------------------------------------------------------
@@ -332,13 +370,17 @@ __device__ __forceinline__ T stencil_value(const StepCoef& c, T up, T cen, T dn,
     return (T)c.d * cen - (T)c.cx * (w + e) - (T)c.cy * (up + dn);
 }
 
-// Jacobi-preconditioned CG for M x = b on one workgroup.
+// Jacobi-preconditioned CG for M x = b on one workgroup.  M has the constant
+// diagonal d, so the Jacobi preconditioner is the scalar 1/d: with the scaled
+// direction p~ = d p the iterates x_k, r_k are exactly those of Jacobi-PCG
+// (alpha~ = (r,r)/(p~,Mp~), beta = (r',r')/(r,r)), without the division and
+// without the second dot product.
 //   x : in the initial guess, out the solution (strip registers)
 //   r : in b, out the final recursive residual (strip registers)
-//   q : scratch strip registers (M p of the current iteration)
+//   q : scratch strip registers (M p~ of the current iteration, then p~)
 //   lp: column-major haloed LDS vector (halo zeroed by the caller; periodic
-//       halos are maintained by lds_put_strip);  red: LDS reduction scratch
-// Stops when (r, r) <= rtol2 (b, b); b = 0 returns x = 0.  On exceeding maxit
+//       halos are maintained by lds_put_fn);  red: LDS reduction scratch
+// Stops when (r, r) <= rtol2 (b, b); b = 0 returns x = 0.  On reaching maxit
 // sets *fail and returns with the current iterate.  Returns the iteration count.
 template <typename T, int S, bool EXACT, bool PER, bool STOREQ>
 __device__ int cg2d(const Grid2D& g, const StepCoef& c, const Strip& st, T (&x)[S], T (&r)[S], T (&q)[S], T* lp,
@@ -346,38 +388,32 @@ __device__ int cg2d(const Grid2D& g, const StepCoef& c, const Strip& st, T (&x)[
 {
     constexpr int V = Lds2D<T>::V;
     typedef typename Lds2D<T>::vec vec;
-    const T inv_d = (T)c.inv_d;
     const bool any = EXACT || st.nr > 0;
     // stage the initial guess for the stencil; (b, b)
-    double bb = 0.0, dummy = 0.0;
+    double bb = 0.0, rr = 0.0;
 #pragma unroll
     for (int s = 0; s < S; ++s)
         if (row_ok<EXACT, S>(st, s)) bb += (double)r[s] * (double)r[s];
     lds_put_fn<T, S, EXACT, PER, false>(g, st, lp, [&](int s, T) { return x[s]; });
     __syncthreads();
-    double rr = 0.0, rz = 0.0;
     if (any)
         strip_stencil<T, S, EXACT>(st, lp, [&](int s, T up, T cen, T dn, T w, T e) {
             r[s] = r[s] - stencil_value(c, up, cen, dn, w, e);
-            const T z = r[s] * inv_d;
             rr += (double)r[s] * (double)r[s];
-            rz += (double)r[s] * (double)z;
             return r[s];
         });
-    block_sum2(bb, dummy, red, slot, kWaves2D);
-    block_sum2(rr, rz, red, slot, kWaves2D);
+    block_sum2(bb, rr, red, slot, kWaves2D);
     // b = 0 has the solution x = 0 (set after the loop, which is skipped)
     const bool bzero = (bb == 0.0);
     const double thresh = rtol2 * bb;
-    // p = z (every reader of the staged x has passed the reductions' barriers)
-    T inv_d0 = inv_d;
-    __asm__ volatile("" : "+v"(inv_d0));
-    lds_put_fn<T, S, EXACT, PER, false>(g, st, lp, [&](int s, T) { return r[s] * inv_d0; });
+    double gamma = rr;
+    // p~ = r (every reader of the staged x has passed the reduction's barrier)
+    lds_put_fn<T, S, EXACT, PER, false>(g, st, lp, [&](int s, T) { return r[s]; });
     __syncthreads();
     int it = 0;
     while (!bzero && rr > thresh && it < maxit) {
-        // q = M p and (p, q)
-        double pq = 0.0, unused = 0.0;
+        // q = M p~ and (p~, q)
+        double pq = 0.0;
         if (any)
             strip_stencil<T, S, EXACT>(st, lp, [&](int s, T up, T cen, T dn, T w, T e) {
                 const T v = stencil_value(c, up, cen, dn, w, e);
@@ -385,10 +421,9 @@ __device__ int cg2d(const Grid2D& g, const StepCoef& c, const Strip& st, T (&x)[
                 pq += (double)cen * (double)v;
                 return v;
             });
-        block_sum2(pq, unused, red, slot, kWaves2D);
-        const T alpha = (T)(rz / pq);
-        // x += alpha p, r -= alpha q; q takes the old p for the direction update
-        double rz_new = 0.0;
+        pq = block_sum1(pq, red, slot, kWaves2D);
+        const T alpha = (T)(gamma / pq);
+        // x += alpha p~, r -= alpha q; q takes p~ for the direction update
         rr = 0.0;
         if (any && STOREQ) {
             int base = st.lbase;
@@ -401,8 +436,6 @@ __device__ int cg2d(const Grid2D& g, const StepCoef& c, const Strip& st, T (&x)[
                     if (row_ok<EXACT, S>(st, s + i)) {
                         x[s + i] = x[s + i] + alpha * p.a[i];
                         r[s + i] = r[s + i] - alpha * q[s + i];
-                        const T z = r[s + i] * inv_d;
-                        rz_new += (double)r[s + i] * (double)z;
                         rr += (double)r[s + i] * (double)r[s + i];
                         q[s + i] = p.a[i];
                     }
@@ -413,24 +446,18 @@ __device__ int cg2d(const Grid2D& g, const StepCoef& c, const Strip& st, T (&x)[
                 const T v = stencil_value(c, up, cen, dn, w, e);
                 x[s] = x[s] + alpha * cen;
                 r[s] = r[s] - alpha * v;
-                const T z = r[s] * inv_d;
-                rz_new += (double)r[s] * (double)z;
                 rr += (double)r[s] * (double)r[s];
                 return r[s];
             });
         }
-        block_sum2(rz_new, rr, red, slot, kWaves2D);
-        const T beta = (T)(rz_new / rz);
-        rz = rz_new;
-        // an opaque copy of the Jacobi scale stops the compiler from keeping every
-        // z = r * inv_d of the update pass alive across the reduction for reuse here
-        T inv_d2 = inv_d;
-        __asm__ volatile("" : "+v"(inv_d2));
-        // p = z + beta p_old (each thread rewrites only its own cells and halo copies)
+        rr = block_sum1(rr, red, slot, kWaves2D);
+        const T beta = (T)(rr / gamma);
+        gamma = rr;
+        // p~ = r + beta p~ (each thread rewrites only its own cells and halo copies)
         if (STOREQ)
-            lds_put_fn<T, S, EXACT, PER, false>(g, st, lp, [&](int s, T) { return r[s] * inv_d2 + beta * q[s]; });
+            lds_put_fn<T, S, EXACT, PER, false>(g, st, lp, [&](int s, T) { return r[s] + beta * q[s]; });
         else
-            lds_put_fn<T, S, EXACT, PER, true>(g, st, lp, [&](int s, T old) { return r[s] * inv_d2 + beta * old; });
+            lds_put_fn<T, S, EXACT, PER, true>(g, st, lp, [&](int s, T old) { return r[s] + beta * old; });
         __syncthreads();
         ++it;
     }

@@ -157,15 +157,15 @@ __device__ __forceinline__ void strip_store(double* dst, const Strip& st, int nx
 
 // One integrator step of size given by coefficients c, on the strip state.
 template <int S, bool EX, bool PER>
-__device__ __forceinline__ int step2d(const KArgs& a, const StepCoef& c, const Strip& st, Strip2DState<S>& v,
-                                      double* lp, double* red, int& slot)
+__device__ __forceinline__ int step2d(const KArgs& a, const StepCoef& c, double rtol2, const Strip& st,
+                                      Strip2DState<S>& v, double* lp, double* red, int& slot)
 {
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const double xs = v.x[s];
         v.r[s] = c.react != 0.0 ? xs + c.react * (xs - xs * xs * xs) : xs;
     }
-    return cg2d<double, S, EX, PER, true>(a.g, c, st, v.x, v.r, v.q, lp, red, slot, a.rtol2, a.maxit, a.fail);
+    return cg2d<double, S, EX, PER, true>(a.g, c, st, v.x, v.r, v.q, lp, red, slot, rtol2, a.maxit, a.fail);
 }
 
 template <int S, bool EX, bool PER>
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kBlock2D) void sweep2d_kernel(KArgs a)
     const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
     long long its = 0;
     for (int64_t t = 1; t <= total; ++t) {
-        its += step2d<S, EX, PER>(a, a.fine, st, v, lp, red, slot);
+        its += step2d<S, EX, PER>(a, a.fine, a.rtol2, st, v, lp, red, slot);
         double* dst = (t < a.m) ? a.u + (j * a.m + t) * a.n : a.y + (j + 1) * a.n;
         strip_store<S, EX>(dst, st, nx, v.x);
     }
@@ -203,7 +203,7 @@ __device__ __forceinline__ long long psi2d(const KArgs& a, const Strip& st, Stri
                                            double* red, int& slot)
 {
     long long its = 0;
-    for (int q = 0; q < a.substeps; ++q) its += step2d<S, EX, PER>(a, a.coarse, st, v, lp, red, slot);
+    for (int q = 0; q < a.substeps; ++q) its += step2d<S, EX, PER>(a, a.coarse, a.rtol2_coarse, st, v, lp, red, slot);
     return its;
 }
 
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kBlock2D) void seq2d_kernel(KArgs a)
     }
     long long its = 0;
     for (int64_t t = 1; t <= a.nt; ++t) {
-        its += step2d<S, EX, PER>(a, a.fine, st, v, lp, red, slot);
+        its += step2d<S, EX, PER>(a, a.fine, a.rtol2, st, v, lp, red, slot);
         strip_store<S, EX>(a.u + t * a.n, st, nx, v.x);
     }
     count_cg(a, its);

@@ -35,7 +35,8 @@ struct KArgs {
     int is1d, s_tmpl, exact;
     Grid2D g;
     StepCoef fine, coarse;
-    double rtol2;
+    double rtol2;         // squared CG tolerance of Phi
+    double rtol2_coarse;  // squared CG tolerance of Psi
     int maxit;
 };
 

@@ -68,6 +68,7 @@ class Options:
     coarse_form: int = 0    # 0 auto (linear for heat, FAS for Allen-Cahn), 1 linear, 2 FAS
     precision: int = 0      # 0 FP64 throughout, 1 FP32 fine sweeps + FP64 residual/correction
     profile: int = 0        # 1: the GPU solve times every kernel launch with HIP events
+    coarse_cg_rtol: float = 0.0  # CG tolerance inside Psi; 0 = the problem's cg_rtol
 
     def n_intervals(self, nt: int) -> int:
         return nt // self.m
