@@ -468,3 +468,17 @@ def test_fine_and_coarse_steps_share_the_integrator(orc):
     for _ in range(3):
         x = orc.step(p, p.dt * 4 / 3, x)
     assert np.array_equal(orc.coarse_step(p, o, u0), x)
+
+
+def test_coarse_tolerance_keeps_fixed_point(orc):
+    """A loose CG tolerance inside Psi changes the iteration, not its fixed point (sequential stepping)."""
+    p, u0 = W.small_problem(W.HEAT2D, seed=4, nt=48, nx=8, ny=6)
+    o = W.Options(m=4, k=3, relax=1, tol=1e-11, coarse_cg_rtol=1e-3)
+    u, hist, st = orc.solve(p, o, W.initial_guess(p, u0))
+    assert st["status"] == 0 and hist[-1] <= 1e-11
+    assert np.linalg.norm(u - orc.sequential(p, u0)) <= (p.nt + 1) * 1.0000001e-11
+    tight = W.Options(m=4, k=3, relax=1, tol=1e-11)
+    g = W.initial_guess(p, u0, "random", seed=1)
+    a = orc.cycle(p, o, g)
+    b = orc.cycle(p, tight, g)
+    assert not np.array_equal(a, b)      # the option reaches Psi
