@@ -76,6 +76,8 @@ def lib():
             "or_c_relax": (ctypes.c_int, [P, O, dp, i64p]),
             "or_residual": (ctypes.c_int, [P, dp, dp, dp, i64p]),
             "or_norm2": (ctypes.c_double, [ctypes.c_int64, dp]),
+            "or_implicit_residual": (ctypes.c_int, [P, dp, dp]),
+            "or_step_residual": (ctypes.c_int, [P, dp, dp, i64p]),
             "or_local_solve": (ctypes.c_int, [P, O, ctypes.c_int64, dp, dp, dp, i64p]),
             "or_local_solves": (ctypes.c_int, [P, O, dp, dp, dp, i64p, i64p]),
             "or_correct": (ctypes.c_int, [P, O, dp, dp, i64p]),
@@ -177,6 +179,22 @@ def residual(p, u, g0):
 
 def residual_norm(p, u, g0):
     return float(np.sqrt(np.sum(residual(p, u, g0) ** 2)))
+
+
+def implicit_residual(p, u):
+    """rho_i = psi(u_{i-1}) - M u_i, [nt+1, n] (row 0 is zero)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    rho = np.empty_like(u)
+    _check(lib().or_implicit_residual(ctypes.byref(_prob(p)), _ptr(u), _ptr(rho)), "implicit_residual")
+    return rho
+
+
+def step_residual(p, u):
+    """r_i = M^{-1} rho_i (the residual with the step solved from zero), [nt+1, n]."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    r = np.empty_like(u)
+    _check(lib().or_step_residual(ctypes.byref(_prob(p)), _ptr(u), _ptr(r), None), "step_residual")
+    return r
 
 
 def local_solve(p, o, pidx, rc, vc):

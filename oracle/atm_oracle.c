@@ -189,6 +189,39 @@ static void thomas(int n, double c, const double* b, double* x, double* work)
     for (int i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
 }
 
+/* The right-hand side of the step's linear system M u_i = psi(u_{i-1}):
+   psi is the identity for heat; for Allen-Cahn the reaction term is taken
+   explicitly, psi(v) = v + dt (v - v^3) / eps^2 (IMEX). */
+static void explicit_part(const or_problem* P, double dt, const double* in, double* b)
+{
+    const int64_t n = nspace(P);
+    if (P->kind != OR_AC2D) {
+        for (int64_t i = 0; i < n; ++i) b[i] = in[i];
+    } else {
+        const double s = dt / (P->eps * P->eps);
+        for (int64_t i = 0; i < n; ++i) b[i] = in[i] + s * (in[i] - in[i] * in[i] * in[i]);
+    }
+}
+
+/* y = M x for the fine step, M = I - dt nu L_h (1D: the tridiagonal matrix of thomas()) */
+static void apply_M_fine(const or_problem* P, const double* x, double* y)
+{
+    const double dt = step_size(P);
+    const double hx = spacing(P, P->nx);
+    const double cx = P->nu * dt / (hx * hx);
+    if (P->kind == OR_HEAT1D) {
+        const int nx = P->nx;
+        for (int i = 0; i < nx; ++i) {
+            const double w = i > 0 ? x[i - 1] : 0.0;
+            const double e = i < nx - 1 ? x[i + 1] : 0.0;
+            y[i] = (1.0 + 2.0 * cx) * x[i] - cx * (w + e);
+        }
+        return;
+    }
+    const double hy = spacing(P, P->ny);
+    apply_M2d(P, cx, P->nu * dt / (hy * hy), x, y);
+}
+
 /* One step of the integrator with step size dt: out = Phi_dt(in), with the
    linear systems of the 2D kinds solved to relative tolerance rtol.
    work must hold 6n doubles.  out may not alias in. */
@@ -213,12 +246,7 @@ static int step_dt_tol(const or_problem* P, double dt, double rtol, const double
     const double hx = spacing(P, P->nx), hy = spacing(P, P->ny);
     const double cx = P->nu * dt / (hx * hx), cy = P->nu * dt / (hy * hy);
     double* b = work + 4 * n;
-    if (P->kind == OR_HEAT2D) {
-        for (int64_t i = 0; i < n; ++i) b[i] = in[i];
-    } else {
-        const double s = dt / (P->eps * P->eps);
-        for (int64_t i = 0; i < n; ++i) b[i] = in[i] + s * (in[i] - in[i] * in[i] * in[i]);
-    }
+    explicit_part(P, dt, in, b);
     for (int64_t i = 0; i < n; ++i) out[i] = in[i];
     return pcg2d(P, cx, cy, rtol, b, out, work, cg_its);
 }
@@ -408,6 +436,74 @@ int or_residual(const or_problem* P, const double* u, const double* g0, double* 
 }
 
 double or_norm2(int64_t len, const double* v) { return sqrt(dot(len, v, v)); }
+
+/* The implicit form of the residual.  Every fine step solves M u_i = psi(u_{i-1})
+   (eq. (2) for the integrators above), so the paper's residual at a point,
+   r_i = Phi(u_{i-1}) - u_i, equals M^{-1} rho_i with
+       rho_i = psi(u_{i-1}) - M u_i           (i = 1..nt; rho_0 = 0 as g_0 - u_0 = 0).
+   rho needs no solve.  M = I - dt nu L_h has eigenvalues >= 1, so |r_i| <= |rho_i|. */
+int or_implicit_residual(const or_problem* P, const double* u, double* rho)
+{
+    const int64_t n = nspace(P);
+    const double dt = step_size(P);
+    for (int64_t x = 0; x < n; ++x) rho[x] = 0.0;
+#pragma omp parallel num_threads(g_threads)
+    {
+        double* mu = malloc(sizeof(double) * n);
+        double* ps = malloc(sizeof(double) * n);
+#pragma omp for schedule(static)
+        for (int64_t i = 1; i <= P->nt; ++i) {
+            explicit_part(P, dt, u + (i - 1) * n, ps);
+            apply_M_fine(P, u + i * n, mu);
+            for (int64_t x = 0; x < n; ++x) rho[i * n + x] = ps[x] - mu[x];
+        }
+        free(ps);
+        free(mu);
+    }
+    return OR_OK;
+}
+
+/* r_i = M^{-1} rho_i for i = 1..nt (r_0 = 0): the paper's residual with the
+   step's linear system solved by CG from zero to cg_rtol relative to |rho_i|
+   (2D) or exactly by the Thomas algorithm (1D).  Unlike Phi(u_{i-1}) - u_i it
+   keeps its relative accuracy when the residual is tiny. */
+int or_step_residual(const or_problem* P, const double* u, double* r, int64_t* cg)
+{
+    const int64_t n = nspace(P);
+    int st = or_implicit_residual(P, u, r);
+    if (st) return st;
+    const double dt = step_size(P);
+    int status = OR_OK;
+    int64_t cg_total = 0;
+#pragma omp parallel num_threads(g_threads) reduction(+ : cg_total)
+    {
+        double* work = malloc(sizeof(double) * work_len(P));
+        double* z = malloc(sizeof(double) * n);
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t i = 1; i <= P->nt; ++i) {
+            double* ri = r + i * n;
+            if (P->kind == OR_HEAT1D) {
+                const double h = spacing(P, P->nx);
+                thomas(P->nx, P->nu * dt / (h * h), ri, z, work);
+            } else {
+                const double hx = spacing(P, P->nx), hy = spacing(P, P->ny);
+                int64_t c = 0;
+                for (int64_t x = 0; x < n; ++x) z[x] = 0.0;
+                int s2 = pcg2d(P, P->nu * dt / (hx * hx), P->nu * dt / (hy * hy), P->cg_rtol, ri, z, work, &c);
+                cg_total += c;
+                if (s2) {
+#pragma omp critical
+                    status = s2;
+                }
+            }
+            for (int64_t x = 0; x < n; ++x) ri[x] = z[x];
+        }
+        free(z);
+        free(work);
+    }
+    if (cg) *cg += cg_total;
+    return status;
+}
 
 /* ------------------------------------------------------------------------ */
 /* local coarse-grid solves (Alg. 1; approximate local matrix of 3.1.2)      */

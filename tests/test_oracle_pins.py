@@ -482,3 +482,72 @@ def test_coarse_tolerance_keeps_fixed_point(orc):
     a = orc.cycle(p, o, g)
     b = orc.cycle(p, tight, g)
     assert not np.array_equal(a, b)      # the option reaches Psi
+
+
+# ---------------------------------------------------------------------------
+# implicit form of the residual (stopping test of the FP32-fine form)
+# ---------------------------------------------------------------------------
+
+def dense_M_psi(p):
+    """M = I - dt nu L (dense, from the operator definitions) and psi, the explicit part of the step."""
+    if p.kind == W.HEAT1D:
+        L = lap1d(p.nx, p.length / (p.nx + 1))
+    elif p.kind == W.HEAT2D:
+        L = lap2d(p.nx, p.ny, p.length / (p.nx + 1), p.length / (p.ny + 1))
+    else:
+        L = lap2d(p.nx, p.ny, p.length / p.nx, p.length / p.ny, periodic=True)
+    M = np.eye(p.n) - p.dt * p.nu * L
+    if p.kind == W.AC2D:
+        def psi(v):
+            return v + p.dt / p.eps ** 2 * (v - v ** 3)
+    else:
+        def psi(v):
+            return v
+    return M, psi
+
+
+def _kind_cases():
+    return [
+        W.small_problem(W.HEAT1D, seed=2, nt=6, nx=9, cg_rtol=1e-14),
+        W.small_problem(W.HEAT2D, seed=3, nt=6, nx=7, ny=5, cg_rtol=1e-14),
+        W.small_problem(W.AC2D, seed=4, nt=6, nx=6, ny=5, cg_rtol=1e-14),
+    ]
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_implicit_residual_matches_dense_operator(orc, case):
+    """rho_i = psi(u_{i-1}) - M u_i with M assembled densely (row 0 is g_0 - u_0 = 0)."""
+    p, _ = _kind_cases()[case]
+    u = np.random.default_rng(11).uniform(-1, 1, size=(p.nt + 1, p.n))
+    M, psi = dense_M_psi(p)
+    rho = orc.implicit_residual(p, u)
+    assert np.all(rho[0] == 0.0)
+    for i in range(1, p.nt + 1):
+        ref = psi(u[i - 1]) - M @ u[i]
+        assert np.max(np.abs(rho[i] - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_step_residual_equals_paper_residual(orc, case):
+    """M^-1 rho_i (solve from zero) equals Phi(u_{i-1}) - u_i (step, then difference) on a rough iterate."""
+    p, u0 = _kind_cases()[case]
+    u = np.random.default_rng(12).uniform(-1, 1, size=(p.nt + 1, p.n))
+    u[0] = u0
+    r_step = orc.step_residual(p, u)
+    r_paper = orc.residual(p, u, u0)
+    assert np.all(r_step[0] == 0.0)
+    assert np.max(np.abs(r_step - r_paper)) <= 1e-12 * np.max(np.abs(r_paper))
+    # |M^-1| <= 1: every slice of the residual is no longer than its implicit form
+    rho = orc.implicit_residual(p, u)
+    for i in range(1, p.nt + 1):
+        assert np.linalg.norm(r_step[i]) <= np.linalg.norm(rho[i]) * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_implicit_residual_vanishes_on_sequential_solution(orc, case):
+    """Sequential stepping solves every step, so rho and M^-1 rho are zero up to the CG tolerance."""
+    p, u0 = _kind_cases()[case]
+    u = orc.sequential(p, u0)
+    scale = np.max(np.abs(u))
+    assert np.max(np.abs(orc.implicit_residual(p, u))) <= 1e-13 * scale
+    assert np.max(np.abs(orc.step_residual(p, u))) <= 1e-13 * scale
