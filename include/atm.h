@@ -12,10 +12,13 @@
  * - `stream` is a hipStream_t passed as void*.  Work is enqueued on it; calls
  *   that return a residual norm or statistics synchronise the stream first.
  *   All other calls return after enqueueing (results valid after a stream sync).
- * - The library never allocates device memory in these calls except a few
- *   bytes of pinned host memory for residual readback (one per thread, kept).
- *   All scratch lives in the caller's workspace `ws` of at least
- *   atm_workspace_bytes() bytes, 256-byte aligned.
+ * - The library allocates no device memory: all scratch lives in the
+ *   caller's workspace `ws` of at least atm_workspace_bytes() bytes, 256-byte
+ *   aligned.  Norms are read back into host stack memory.  A workspace must
+ *   be zero-filled before its first use unless that use is atm_solve or
+ *   atm_sequential (which initialise it); its header carries the CG failure
+ *   flag from launch to launch, and a norm call outside atm_solve clears it
+ *   after reporting.
  * - Arguments are validated before any launch; on error nothing is enqueued,
  *   the status is returned and atm_last_error() holds a message
  *   (thread-local).  No exception crosses the ABI.
@@ -73,18 +76,23 @@ typedef struct atm_options {
     double coarse_cg_rtol; /* CG tolerance inside Psi (2D kinds); 0 = the problem's cg_rtol.  Psi only
                               approximates Phi^m, so this changes the convergence rate, not the
                               fixed point */
+    double mixed_cg_rtol;  /* precision 1: relative tolerance of the FP32 CG of each fine step's
+                              correction solve; 0 = 1e-6.  The FP64 fixed point does not depend on it */
     int32_t m;             /* coarsening factor, >= 2 (section 2.1) */
     int32_t k;             /* C-points per local coarse grid, >= 1; k >= N_T+1 is Parareal */
     int32_t relax;         /* 0: F-relaxation, 1: FCF-relaxation (section 2.2) */
     int32_t max_iter;      /* maximum number of cycles */
     int32_t coarse_substeps; /* Psi = s steps of size m dt / s, s >= 1 */
     int32_t coarse_form;   /* 0 auto (linear for heat, FAS for Allen-Cahn), 1 linear, 2 FAS */
-    int32_t precision;     /* 0: FP64 throughout; 1: FP32 fine sweeps, FP64 residual/correction */
+    int32_t precision;     /* 0: FP64 throughout; 1 (2D kinds): FP32 fine solves in defect-correction
+                              form with the residual, coarse correction and iterate in FP64
+                              (see atm_sweep and atm_solve) */
     int32_t profile;       /* 1: time every kernel launch of atm_solve with HIP events (atm_stats.ms_*) */
 } atm_options;
 
 typedef struct atm_stats {
-    double final_residual; /* ||g - A(u)||_2 of the returned iterate */
+    double final_residual; /* ||g - A(u)||_2 of the returned iterate: precision 0, the C-point form
+                              sqrt(sum_j ||y_j - u_{jm}||^2); precision 1, atm_step_residual_norm */
     double ms_total;       /* wall time of atm_solve (host clock, stream synchronised) */
     double ms_sweep;       /* summed device time of the relaxation sweeps (profile = 1, else 0) */
     double ms_coarse;      /* summed device time of the local coarse solves incl. FAS tau (profile = 1) */
@@ -123,6 +131,14 @@ size_t atm_workspace_bytes(const atm_problem* prob, const atm_options* opts);
    u    (device) [nt+1][n] FP64, in/out.
    aux  (device) [N_T+1][n] FP64, read in modes 1 and 2, else may be NULL.
    y    (device) [N_T+1][n] FP64, out (row 0 untouched); must not alias aux.
+   Precision 1 (2D kinds): every step that produces a value v_i = Phi(v_{i-1})
+   starts from the value s_i stored at that point, rho = psi(v_{i-1}) - M s_i
+   in FP64 (M = I - dt nu L; psi is the identity for heat and the explicit
+   Allen-Cahn part otherwise), solves M d = rho by FP32 CG to mixed_cg_rtol and
+   stores v_i = s_i + d in FP64.  For the F-points s_i is u_{jm+i} on entry;
+   for y_{j+1} it is, by mode: 0 u_{(j+1)m}, 1 y_{j+1} on entry (y is then
+   in/out and must hold finite values), 2 aux_{j+1}.  v_i equals Phi(v_{i-1})
+   up to mixed_cg_rtol times |Phi(v_{i-1}) - s_i|.
    Errors: INVALID_ARG, UNSUPPORTED, WORKSPACE, DEVICE.  A CG failure inside
    Phi is reported by the next call that synchronises (atm_residual_norm,
    atm_solve) as ATM_ERR_INNER_SOLVE. */
@@ -148,6 +164,26 @@ atm_status atm_coarse_solve(const atm_problem* prob, const atm_options* opts, co
 atm_status atm_residual_norm(const atm_problem* prob, const atm_options* opts, const double* u,
                              const double* y, double* norm_out, void* ws, size_t ws_bytes, void* stream);
 
+/* FP64 implicit residual norm sqrt(sum_{i=1..nt} ||rho_i||^2),
+   rho_i = psi(u_{i-1}) - M u_i with M = I - dt nu L the matrix of the implicit
+   solve of Phi and psi its explicit part (section 2, eq. (2), written as
+   M u_i = psi(u_{i-1})).  Since the paper-form residual is r_i = M^-1 rho_i
+   and ||M^-1||_2 <= 1, ||r||_2 <= this value: the stopping test of precision 1.
+   All time points are included, F-points too.  u (device) [nt+1][n] in.
+   Synchronises the stream; writes *norm_out (host). */
+atm_status atm_implicit_residual_norm(const atm_problem* prob, const atm_options* opts, const double* u,
+                                      double* norm_out, void* ws, size_t ws_bytes, void* stream);
+
+/* Paper-form residual norm with the step solved to FP64 accuracy,
+   sqrt(sum_{i=1..nt} ||M^-1 rho_i||^2) (section 4.3 stopping norm; the
+   definition of rho_i is above).  M r_i = rho_i is solved by FP64 CG from zero
+   to cg_rtol relative to ||rho_i|| (2D) or by a direct tridiagonal solve (1D),
+   so small residuals are not lost to the cancellation of Phi(u_{i-1}) - u_i.
+   u (device) [nt+1][n] in.  Synchronises the stream; writes *norm_out (host).
+   Errors as atm_residual_norm. */
+atm_status atm_step_residual_norm(const atm_problem* prob, const atm_options* opts, const double* u,
+                                  double* norm_out, void* ws, size_t ws_bytes, void* stream);
+
 /* Sequential time stepping on the GPU: u_i = Phi(u_{i-1}) for i = 1..nt from
    u_0 (the forward block solve of A u = g, section 2), in one workgroup.
    u (device) [nt+1][n], in: u_0, out: all slices.  Needs nt >= 2 and a
@@ -161,7 +197,11 @@ size_t atm_sequential_workspace_bytes(const atm_problem* prob);
 /* Two-level AT-MGRIT (Alg. 1) until ||g - A(u)||_2 <= tol or max_iter cycles.
    u (device) [nt+1][n]: in, u_0 = g_0 and the initial guess at t > 0; out,
    the final iterate.  hist (host, nullable) receives hist_cap residual norms:
-   hist[0] of the F-relaxed initial guess, hist[i] after cycle i.
+   hist[0] of the F-relaxed initial guess, hist[i] after cycle i.  Precision 0
+   stops on the C-point residual (atm_residual_norm); precision 1 on the FP64
+   implicit residual (atm_implicit_residual_norm, which bounds the paper-form
+   residual), reports the paper-form residual of the final iterate in
+   stats->final_residual (atm_step_residual_norm), and uses FP64 coarse solves.
    stats (host, nullable).  Synchronises the stream once per cycle.
    Returns OK, NOT_CONVERGED, DIVERGED, INNER_SOLVE, or an argument error. */
 atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u, void* ws,

@@ -16,7 +16,7 @@ from ._abi import (ATM_AC2D, ATM_ERR_DEVICE, ATM_ERR_DIVERGED, ATM_ERR_INNER_SOL
 
 __all__ = [
     "atm_num_intervals", "atm_window_start", "atm_workspace_bytes", "atm_sweep", "atm_coarse_solve",
-    "atm_residual_norm", "atm_sequential", "atm_sequential_workspace_bytes", "atm_solve", "atm_status_string",
+    "atm_residual_norm", "atm_implicit_residual_norm", "atm_step_residual_norm", "atm_sequential", "atm_sequential_workspace_bytes", "atm_solve", "atm_status_string",
     "atm_last_error", "workspace", "AtmError", "ATM_OK", "ATM_NOT_CONVERGED", "ATM_ERR_INVALID_ARG",
     "ATM_ERR_UNSUPPORTED", "ATM_ERR_DEVICE", "ATM_ERR_DIVERGED", "ATM_ERR_INNER_SOLVE", "ATM_ERR_WORKSPACE",
     "ATM_HEAT1D", "ATM_HEAT2D", "ATM_AC2D",
@@ -65,11 +65,11 @@ def atm_sequential_workspace_bytes(prob) -> int:
 
 
 def workspace(nbytes: int, device="cuda"):
-    """A device byte buffer usable as the workspace (torch allocations are 512-byte aligned)."""
+    """A zero-filled device byte buffer usable as the workspace (torch allocations are 512-byte aligned)."""
     torch = _torch()
     if nbytes <= 0:
         raise ValueError("workspace size is 0: the problem or options are invalid (see atm_last_error())")
-    return torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+    return torch.zeros(int(nbytes), dtype=torch.uint8, device=device)
 
 
 def _f64():
@@ -97,6 +97,23 @@ def atm_residual_norm(prob, opts, u, y, ws, stream=None) -> float:
                                       _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(stream))
     _abi.check(st, "atm_residual_norm")
     return out.value
+
+
+def _norm_of_u(fname, prob, opts, u, ws, stream):
+    out = ctypes.c_double(0.0)
+    st = getattr(_abi.lib(), fname)(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts)),
+                                    _ptr(u, _f64(), "u"), ctypes.byref(out), _ptr(ws, None, "ws"),
+                                    ws.numel() * ws.element_size(), _stream(stream))
+    _abi.check(st, fname)
+    return out.value
+
+
+def atm_implicit_residual_norm(prob, opts, u, ws, stream=None) -> float:
+    return _norm_of_u("atm_implicit_residual_norm", prob, opts, u, ws, stream)
+
+
+def atm_step_residual_norm(prob, opts, u, ws, stream=None) -> float:
+    return _norm_of_u("atm_step_residual_norm", prob, opts, u, ws, stream)
 
 
 def atm_sequential(prob, u, ws=None, stream=None) -> None:

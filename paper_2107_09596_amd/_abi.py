@@ -36,7 +36,7 @@ class AtmProblem(ctypes.Structure):
 
 class AtmOptions(ctypes.Structure):
     _fields_ = [
-        ("tol", ctypes.c_double), ("coarse_cg_rtol", ctypes.c_double),
+        ("tol", ctypes.c_double), ("coarse_cg_rtol", ctypes.c_double), ("mixed_cg_rtol", ctypes.c_double),
         ("m", ctypes.c_int32), ("k", ctypes.c_int32), ("relax", ctypes.c_int32),
         ("max_iter", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32), ("coarse_form", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("profile", ctypes.c_int32),
@@ -66,6 +66,8 @@ SIGNATURES = {
     "atm_sweep": (ctypes.c_int32, [_P, _O, ctypes.c_int32, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "atm_coarse_solve": (ctypes.c_int32, [_P, _O, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "atm_residual_norm": (ctypes.c_int32, [_P, _O, _vp, _vp, _dp, _vp, ctypes.c_size_t, _vp]),
+    "atm_implicit_residual_norm": (ctypes.c_int32, [_P, _O, _vp, _dp, _vp, ctypes.c_size_t, _vp]),
+    "atm_step_residual_norm": (ctypes.c_int32, [_P, _O, _vp, _dp, _vp, ctypes.c_size_t, _vp]),
     "atm_sequential": (ctypes.c_int32, [_P, _vp, _vp, ctypes.c_size_t, _vp]),
     "atm_sequential_workspace_bytes": (ctypes.c_size_t, [_P]),
     "atm_solve": (ctypes.c_int32, [_P, _O, _vp, _vp, ctypes.c_size_t, _dp, ctypes.c_int32, _S, _vp]),
@@ -113,6 +115,7 @@ def problem(p) -> AtmProblem:
 
 def options(o) -> AtmOptions:
     """AtmOptions from any object with the fields of workloads.Options."""
-    return AtmOptions(tol=o.tol, coarse_cg_rtol=float(getattr(o, "coarse_cg_rtol", 0.0)), m=o.m, k=o.k, relax=o.relax, max_iter=o.max_iter,
-                      coarse_substeps=o.coarse_substeps, coarse_form=o.coarse_form,
+    return AtmOptions(tol=o.tol, coarse_cg_rtol=float(getattr(o, "coarse_cg_rtol", 0.0)),
+                      mixed_cg_rtol=float(getattr(o, "mixed_cg_rtol", 0.0)), m=o.m, k=o.k, relax=o.relax,
+                      max_iter=o.max_iter, coarse_substeps=o.coarse_substeps, coarse_form=o.coarse_form,
                       precision=getattr(o, "precision", 0), profile=int(getattr(o, "profile", 0)))

@@ -34,6 +34,7 @@ atm_status fail(atm_status st, const char* fmt, ...)
     } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr double kMixedRtolDefault = 1e-6;  // FP32 CG tolerance of the mixed sweeps
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
@@ -59,7 +60,7 @@ Layout layout(const atm_problem* p, const atm_options* o)
     L.header = off;
     off += align_up(sizeof(atm::Header));
     L.partials = off;
-    off += align_up((NT + 1) * sizeof(double));
+    off += align_up((NT + 1 > (size_t)atm::kResidBlocks ? NT + 1 : (size_t)atm::kResidBlocks) * sizeof(double));
     L.ya = off;
     off += align_up(slab);
     L.yb = off;
@@ -93,7 +94,11 @@ atm_status validate(const atm_problem* p, const atm_options* o)
     if (o->coarse_form < 0 || o->coarse_form > 2) return fail(ATM_ERR_INVALID_ARG, "coarse_form must be 0, 1 or 2");
     if (o->max_iter < 0) return fail(ATM_ERR_INVALID_ARG, "max_iter must be >= 0");
     if (!(o->tol >= 0.0)) return fail(ATM_ERR_INVALID_ARG, "tol must be >= 0");
-    if (o->precision != 0) return fail(ATM_ERR_UNSUPPORTED, "only precision 0 (FP64) is available in this entry point");
+    if (o->precision != 0 && o->precision != 1) return fail(ATM_ERR_INVALID_ARG, "precision must be 0 or 1");
+    if (o->precision == 1 && p->kind == ATM_HEAT1D)
+        return fail(ATM_ERR_UNSUPPORTED, "precision 1 (FP32 fine solves) is available for the 2D kinds only");
+    if (!(o->mixed_cg_rtol >= 0.0) || !(o->mixed_cg_rtol < 1.0))
+        return fail(ATM_ERR_INVALID_ARG, "mixed_cg_rtol must be in [0, 1)");
     if (!(o->coarse_cg_rtol >= 0.0)) return fail(ATM_ERR_INVALID_ARG, "coarse_cg_rtol must be >= 0");
     if (o->profile != 0 && o->profile != 1) return fail(ATM_ERR_INVALID_ARG, "profile must be 0 or 1");
     if (p->kind == ATM_HEAT1D) {
@@ -153,15 +158,19 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
     a.rtol2 = p->cg_rtol * p->cg_rtol;
     const double crtol = o->coarse_cg_rtol > 0.0 ? o->coarse_cg_rtol : p->cg_rtol;
     a.rtol2_coarse = crtol * crtol;
+    const double mrtol = o->mixed_cg_rtol > 0.0 ? o->mixed_cg_rtol : kMixedRtolDefault;
+    a.rtol2_mixed = mrtol * mrtol;
     a.maxit = p->cg_max_iter;
     if (!a.is1d) {
         // strips: TX = 64 or 128 threads along x, TY = 512 / TX strips along y,
-        // rows a multiple of 2 (16-byte LDS accesses of doubles)
+        // rows a multiple of 2 (16-byte LDS accesses of doubles), of 4 for the
+        // mixed-precision sweeps (16-byte accesses of floats)
         const int tx_log2 = p->nx > 64 ? 7 : 6;
         const int TX = 1 << tx_log2;
         const int TY = atm::kBlock2D / TX;
+        const int chunk = o->precision == 1 ? 4 : 2;
         int rows = (p->ny + TY - 1) / TY;
-        rows = (rows + 1) / 2 * 2;
+        rows = (rows + chunk - 1) / chunk * chunk;
         a.g.nx = p->nx;
         a.g.ny = p->ny;
         a.g.tx_log2 = tx_log2;
@@ -175,7 +184,8 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
         // indices up to y0_last + V + S (the value below its last row).
         const int H = atm::Lds2D<double>::H, V = atm::Lds2D<double>::V;
         const int y0_last = ((p->ny - 1) / rows) * rows;
-        if (y0_last + V + a.s_tmpl >= H || p->nx + 2 > atm::kMaxSide2D + 2)
+        const int Hf = atm::Lds2D<float>::H, Vf = atm::Lds2D<float>::V;
+        if (y0_last + V + a.s_tmpl >= H || y0_last + Vf + a.s_tmpl >= Hf || p->nx + 2 > atm::kMaxSide2D + 2)
             return fail(ATM_ERR_UNSUPPORTED, "grid %d x %d does not fit the LDS strip layout", p->nx, p->ny);
     }
     return ATM_OK;
@@ -209,7 +219,10 @@ atm_status do_sweep(atm::KArgs a, const atm_problem* p, const atm_options* o, in
     a.u = u;
     a.aux = aux;
     a.y = y;
-    atm::launch_sweep(a, sweep_tasks(p, o), s);
+    if (o->precision == 1)
+        atm::launch_sweep_mixed(a, sweep_tasks(p, o), s);
+    else
+        atm::launch_sweep(a, sweep_tasks(p, o), s);
     return check_launch();
 }
 
@@ -241,6 +254,53 @@ atm_status do_norm(atm::KArgs a, double* u, double* y, hipStream_t s, double* no
     if (hdr->fail) return fail(ATM_ERR_INNER_SOLVE, "a CG solve inside Phi or Psi did not reach cg_rtol within %d iterations",
                                a.maxit);
     return ATM_OK;
+}
+
+// The stopping norm of precision 1 (implicit residual) and the paper-form
+// norm of the exact step; both synchronise and read the header.
+atm_status finish_norm(const atm::KArgs& a, hipStream_t s, double* norm_out, atm::Header* hdr)
+{
+    atm_status st = check_launch();
+    if (st) return st;
+    st = read_header(a, s, hdr);
+    if (st) return st;
+    *norm_out = sqrt(hdr->norm2);
+    if (hdr->fail) return fail(ATM_ERR_INNER_SOLVE, "a CG solve inside Phi or Psi did not reach its tolerance within %d iterations",
+                               a.maxit);
+    return ATM_OK;
+}
+
+atm_status do_implicit_norm(atm::KArgs a, const double* u, hipStream_t s, double* norm_out, atm::Header* hdr)
+{
+    // one partial sum per workgroup; the workspace holds max(N_T + 1, kResidBlocks) of them
+    const int64_t cap = a.NT + 1 > atm::kResidBlocks ? a.NT + 1 : atm::kResidBlocks;
+    if (atm::implicit_residual_blocks(a) > cap)
+        return fail(ATM_ERR_UNSUPPORTED, "implicit residual: %lld partial sums exceed the workspace's %lld",
+                    (long long)atm::implicit_residual_blocks(a), (long long)cap);
+    a.u = (double*)u;
+    atm::launch_implicit_residual(a, s);
+    return finish_norm(a, s, norm_out, hdr);
+}
+
+atm_status do_step_norm(atm::KArgs a, const atm_problem* p, const atm_options* o, const double* u, hipStream_t s,
+                        double* norm_out, atm::Header* hdr)
+{
+    a.u = (double*)u;
+    atm::launch_step_residual(a, sweep_tasks(p, o), s);
+    return finish_norm(a, s, norm_out, hdr);
+}
+
+// A norm call outside atm_solve ends the window in which CG failures of earlier
+// calls on this workspace are reported: the header is cleared once it is read.
+atm_status after_standalone_norm(const atm::KArgs& a, atm_status st, double norm, hipStream_t s)
+{
+    if (st == ATM_OK || st == ATM_ERR_INNER_SOLVE) {
+        atm::launch_reset(a.hdr, s);
+        atm_status st2 = check_launch();
+        if (st2) return st2;
+    }
+    if (st == ATM_OK && !isfinite(norm)) return fail(ATM_ERR_DIVERGED, "non-finite residual norm");
+    return st;
 }
 
 // Options used by atm_sequential (only the workspace header is needed).
@@ -363,8 +423,31 @@ atm_status atm_residual_norm(const atm_problem* prob, const atm_options* opts, c
     if (!u || !y || !norm_out) return fail(ATM_ERR_INVALID_ARG, "null u, y or norm_out");
     atm::Header h;
     st = do_norm(a, (double*)u, (double*)y, as_stream(stream), norm_out, &h);
-    if (st == ATM_OK && !isfinite(*norm_out)) return fail(ATM_ERR_DIVERGED, "non-finite residual norm");
-    return st;
+    return after_standalone_norm(a, st, *norm_out, as_stream(stream));
+}
+
+atm_status atm_implicit_residual_norm(const atm_problem* prob, const atm_options* opts, const double* u,
+                                      double* norm_out, void* ws, size_t ws_bytes, void* stream)
+{
+    atm::KArgs a;
+    atm_status st = make_args(prob, opts, ws, ws_bytes, a);
+    if (st) return st;
+    if (!u || !norm_out) return fail(ATM_ERR_INVALID_ARG, "null u or norm_out");
+    atm::Header h;
+    st = do_implicit_norm(a, u, as_stream(stream), norm_out, &h);
+    return after_standalone_norm(a, st, *norm_out, as_stream(stream));
+}
+
+atm_status atm_step_residual_norm(const atm_problem* prob, const atm_options* opts, const double* u, double* norm_out,
+                                  void* ws, size_t ws_bytes, void* stream)
+{
+    atm::KArgs a;
+    atm_status st = make_args(prob, opts, ws, ws_bytes, a);
+    if (st) return st;
+    if (!u || !norm_out) return fail(ATM_ERR_INVALID_ARG, "null u or norm_out");
+    atm::Header h;
+    st = do_step_norm(a, prob, opts, u, as_stream(stream), norm_out, &h);
+    return after_standalone_norm(a, st, *norm_out, as_stream(stream));
 }
 
 atm_status atm_sequential(const atm_problem* prob, double* u, void* ws, size_t ws_bytes, void* stream)
@@ -427,15 +510,22 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
         if ((st = (expr))) break;                     \
         if ((st = T.end(s))) break;                   \
     } while (0)
+    const bool mixed = (opts->precision == 1);
+    // stopping norm: the C-point residual (FP64 form) or the FP64 implicit residual (mixed form)
+    auto stop_norm = [&](double* yv, double* out) {
+        return mixed ? do_implicit_norm(a, u, s, out, &h) : do_norm(a, u, yv, s, out, &h);
+    };
     // F-relax the initial guess, then its residual
     ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 0, u, nullptr, ya, s));
     if (st) return st;
     S.fine_steps += prob->nt;
     S.n_sweeps += 1;
     double res = 0.0;
-    ATM_TIMED(kPhNorm, do_norm(a, u, ya, s, &res, &h));
+    ATM_TIMED(kPhNorm, stop_norm(ya, &res));
     if (st == ATM_OK) st = T.collect();
     if (st == ATM_OK && hist && hist_cap > 0) hist[0] = res;
+    // yprev holds Phi of every last F-point from the latest sweep
+    double* yprev = ya;
     int it = 0;
     while (st == ATM_OK && !(res <= opts->tol)) {
         if (!isfinite(res)) {
@@ -446,32 +536,43 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
             st = ATM_NOT_CONVERGED;
             break;
         }
-        double* ycur = ya;
+        double* ycur = yprev;
         if (opts->relax == 1) {
-            // CF: C-points take Phi of their preceding F-point (held in ya), then F-relax
-            ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 2, u, ya, yb, s));
+            // CF: C-points take Phi of their preceding F-point (held in yprev), then F-relax
+            ycur = (yprev == ya) ? yb : ya;
+            ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 2, u, yprev, ycur, s));
             if (st) break;
             S.fine_steps += prob->nt;
             S.n_sweeps += 1;
-            ycur = yb;
         }
         ATM_TIMED(kPhCoarse, do_coarse(a, u, ycur, e, s));
         if (st) break;
         S.coarse_steps += window_psi_count(NT, opts->k) + (a.fas ? NT : 0);
-        // correction u_{pm} += e_p and F-interpolation; ya receives Phi of every last F-point
-        ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 1, u, e, ya, s));
+        // correction u_{pm} += e_p and F-interpolation; ycur receives Phi of every
+        // last F-point (in the mixed form its entries also start those steps)
+        ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 1, u, e, ycur, s));
         if (st) break;
         S.fine_steps += prob->nt;
         S.n_sweeps += 1;
+        yprev = ycur;
         ++it;
-        ATM_TIMED(kPhNorm, do_norm(a, u, ya, s, &res, &h));
+        ATM_TIMED(kPhNorm, stop_norm(yprev, &res));
         if (st == ATM_OK) st = T.collect();
         if (st == ATM_OK && hist && it < hist_cap) hist[it] = res;
     }
-#undef ATM_TIMED
     if (st == ATM_OK && !isfinite(res)) st = fail(ATM_ERR_DIVERGED, "non-finite residual norm");
+    double final_res = res;
+    if (mixed && (st == ATM_OK || st == ATM_NOT_CONVERGED)) {
+        // the paper-form residual of the returned iterate (bounded by the stopping norm)
+        atm_status st2 = ATM_OK;
+        if ((st2 = T.begin(kPhNorm, s)) == ATM_OK && (st2 = do_step_norm(a, prob, opts, u, s, &final_res, &h)) == ATM_OK &&
+            (st2 = T.end(s)) == ATM_OK)
+            st2 = T.collect();
+        if (st2 != ATM_OK) st = st2;
+    }
+#undef ATM_TIMED
     S.iterations = it;
-    S.final_residual = res;
+    S.final_residual = final_res;
     S.cg_fine = (int64_t)h.cg_fine;
     S.cg_coarse = (int64_t)h.cg_coarse;
     S.ms_sweep = T.ms[kPhSweep];

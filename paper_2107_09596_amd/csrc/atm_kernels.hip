@@ -11,31 +11,6 @@
 namespace atm {
 
 // ---------------------------------------------------------------------------
-// shared helpers
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ double cpoint_residual(const KArgs& a, int64_t j, int64_t idx)
-{
-    // r_0 = g_0 - u_0 = 0 (u_0 is never modified); r_j = Phi(u_{jm-1}) - u_{jm}
-    if (j == 0) return 0.0;
-    return a.y[j * a.n + idx] - a.u[(j * a.m) * a.n + idx];
-}
-
-// C-point value that starts interval j of a sweep
-__device__ __forceinline__ double sweep_start(const KArgs& a, int64_t j, int64_t idx)
-{
-    const double uc = a.u[(j * a.m) * a.n + idx];
-    if (a.mode == 1) return uc + a.aux[j * a.n + idx];
-    if (a.mode == 2) return j == 0 ? uc : a.aux[j * a.n + idx];
-    return uc;
-}
-
-__device__ __forceinline__ void count_cg(const KArgs& a, long long its)
-{
-    if (threadIdx.x == 0 && its) atomicAdd(a.cg_count, (unsigned long long)its);
-}
-
-// ---------------------------------------------------------------------------
 // 1D heat: PCR tridiagonal steps, one workgroup (nx rounded up to wave64) per task
 // ---------------------------------------------------------------------------
 
@@ -137,34 +112,13 @@ struct Strip2DState {
     double x[S], r[S], q[S];
 };
 
-// Strip offsets in global memory pass through an empty asm at every use, so
-// the compiler recomputes the per-row addresses instead of hoisting all of
-// them out of the time loop (which would cost a register pair per row).
-__device__ __forceinline__ int64_t opaque_off(int v)
-{
-    __asm__ volatile("" : "+v"(v));
-    return (int64_t)v;
-}
-
-template <int S, bool EX>
-__device__ __forceinline__ void strip_store(double* dst, const Strip& st, int nx, const double (&v)[S])
-{
-    const int64_t off = opaque_off(st.gbase);
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-        if (row_ok<EX, S>(st, s)) dst[off + (int64_t)s * nx] = v[s];
-}
-
 // One integrator step of size given by coefficients c, on the strip state.
 template <int S, bool EX, bool PER>
 __device__ __forceinline__ int step2d(const KArgs& a, const StepCoef& c, double rtol2, const Strip& st,
                                       Strip2DState<S>& v, double* lp, double* red, int& slot)
 {
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const double xs = v.x[s];
-        v.r[s] = c.react != 0.0 ? xs + c.react * (xs - xs * xs * xs) : xs;
-    }
+    for (int s = 0; s < S; ++s) v.r[s] = explicit_part(c, v.x[s]);
     return cg2d<double, S, EX, PER, true>(a.g, c, st, v.x, v.r, v.q, lp, red, slot, rtol2, a.maxit, a.fail);
 }
 

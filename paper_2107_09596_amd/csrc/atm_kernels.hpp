@@ -25,7 +25,7 @@ struct KArgs {
     double* y;          // sweep: out; coarse/tau/norm: in (Phi of the last F-point)
     double* e;          // coarse: out
     double* tau;        // FAS right-hand side, [N_T+1][n]
-    double* partials;   // [N_T+1] norm partial sums
+    double* partials;   // [max(N_T+1, kResidBlocks)] partial sums of norms
     Header* hdr;
     int* fail;
     unsigned long long* cg_count;
@@ -37,8 +37,59 @@ struct KArgs {
     StepCoef fine, coarse;
     double rtol2;         // squared CG tolerance of Phi
     double rtol2_coarse;  // squared CG tolerance of Psi
+    double rtol2_mixed;   // squared tolerance of the FP32 CG of the mixed-precision sweeps
     int maxit;
 };
+
+// ---------------------------------------------------------------------------
+// shared helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double cpoint_residual(const KArgs& a, int64_t j, int64_t idx)
+{
+    // r_0 = g_0 - u_0 = 0 (u_0 is never modified); r_j = Phi(u_{jm-1}) - u_{jm}
+    if (j == 0) return 0.0;
+    return a.y[j * a.n + idx] - a.u[(j * a.m) * a.n + idx];
+}
+
+// C-point value that starts interval j of a sweep
+__device__ __forceinline__ double sweep_start(const KArgs& a, int64_t j, int64_t idx)
+{
+    const double uc = a.u[(j * a.m) * a.n + idx];
+    if (a.mode == 1) return uc + a.aux[j * a.n + idx];
+    if (a.mode == 2) return j == 0 ? uc : a.aux[j * a.n + idx];
+    return uc;
+}
+
+__device__ __forceinline__ void count_cg(const KArgs& a, long long its)
+{
+    if (threadIdx.x == 0 && its) atomicAdd(a.cg_count, (unsigned long long)its);
+}
+
+// Explicit part of a step: psi(v) = v for heat, v + dt (v - v^3) / eps^2 for
+// Allen-Cahn (the right-hand side of the implicit solve M x = psi(v)).
+__device__ __forceinline__ double explicit_part(const StepCoef& c, double v)
+{
+    return c.react != 0.0 ? v + c.react * (v - v * v * v) : v;
+}
+
+// Strip offsets in global memory pass through an empty asm at every use, so
+// the compiler recomputes the per-row addresses instead of hoisting all of
+// them out of the time loop (which would cost a register pair per row).
+__device__ __forceinline__ int64_t opaque_off(int v)
+{
+    __asm__ volatile("" : "+v"(v));
+    return (int64_t)v;
+}
+
+template <int S, bool EX>
+__device__ __forceinline__ void strip_store(double* dst, const Strip& st, int nx, const double (&v)[S])
+{
+    const int64_t off = opaque_off(st.gbase);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if (row_ok<EX, S>(st, s)) dst[off + (int64_t)s * nx] = v[s];
+}
 
 void launch_reset(Header* h, hipStream_t s);
 void launch_sweep(const KArgs& a, int64_t n_tasks, hipStream_t s);
@@ -46,5 +97,12 @@ void launch_tau(const KArgs& a, hipStream_t s);
 void launch_coarse(const KArgs& a, hipStream_t s);
 void launch_norm(const KArgs& a, hipStream_t s);
 void launch_sequential(const KArgs& a, hipStream_t s);
+
+// mixed-precision form (atm_mixed.hip)
+constexpr int64_t kResidBlocks = 2048;  // most workgroups of the implicit-residual kernel
+int64_t implicit_residual_blocks(const KArgs& a);
+void launch_sweep_mixed(const KArgs& a, int64_t n_tasks, hipStream_t s);
+void launch_implicit_residual(const KArgs& a, hipStream_t s);
+void launch_step_residual(const KArgs& a, int64_t n_tasks, hipStream_t s);
 
 }  // namespace atm

@@ -1,0 +1,331 @@
+// Mixed-precision form of the hot path: FP32 fine solves, FP64 residual,
+// correction and iterate, so that the AT-MGRIT cycle acts as iterative
+// refinement.
+//
+// Every fine step of a mixed sweep updates u_i in defect-correction form:
+//     rho   = psi(u_{i-1}) - M u_i^old          FP64 stencil of the stored iterate
+//     M d   = rho                               FP32 CG to relative tolerance rtol_mixed
+//     u_i^new = u_i^old + d                     FP64
+// with M = I - dt nu L and psi(v) = v (heat) or v + dt (v - v^3) / eps^2
+// (Allen-Cahn), u_{i-1} the slice just produced.  In exact arithmetic this is
+// u_i = Phi(u_{i-1}); the FP32 error is a fraction rtol_mixed of |d|, so it
+// vanishes as the iteration converges and the fixed point is the FP64 one
+// (u_i = M^-1 psi(u_{i-1}) to FP64 rounding).
+//
+// The stopping test uses the FP64 implicit residual rho_i = psi(u_{i-1}) - M u_i
+// over all points: r_i = M^-1 rho_i and |M^-1| <= 1 (M = I - dt nu L, L <= 0),
+// so |r| <= |rho|.  The final paper-form residual |r| is formed by solving
+// M r_i = rho_i in FP64 (step_residual kernels), which avoids the cancellation
+// of Phi(u_{i-1}) - u_i.
+#include "atm_device.hpp"
+#include "atm_kernels.hpp"
+
+namespace atm {
+
+// Zero the halo cells of an LDS vector of a Dirichlet grid: columns -1 and nx
+// (rows -1..ny) and rows -1 and ny of every column.  The mixed sweep reuses one
+// LDS block for an FP64 and an FP32 vector, so each layout's halo is cleared
+// before that layout is written.
+template <typename T>
+__device__ __forceinline__ void lds_clear_halo(const Grid2D& g, T* lp)
+{
+    constexpr int H = Lds2D<T>::H, V = Lds2D<T>::V;
+    const int rows = g.ny + 2;
+    for (int i = threadIdx.x; i < 2 * rows; i += blockDim.x) {
+        const int col = (i < rows) ? 0 : g.nx + 1;
+        const int y = (i < rows) ? i : i - rows;
+        lp[col * H + V - 1 + y] = (T)0;
+    }
+    for (int i = threadIdx.x; i < 2 * g.nx; i += blockDim.x) {
+        const int col = 1 + (i >> 1);
+        lp[col * H + ((i & 1) ? V + g.ny : V - 1)] = (T)0;
+    }
+}
+
+// Mixed sweep over interval j (one workgroup per task, modes as in the FP64
+// sweep).  The starting value of the step that produces y_{j+1} = Phi(u_{jm+m-1})
+// is, by mode: 0 the C-point u_{(j+1)m}; 1 y_{j+1} on entry (y is in/out);
+// 2 aux_{j+1} (the Phi values of the previous sweep).
+template <int S, bool EX, bool PER>
+__global__ __launch_bounds__(kBlock2D) void sweep2d_mixed_kernel(KArgs a)
+{
+    // one LDS block holds the FP64 staging of u_i^old for the defect and then
+    // the FP32 search direction of the CG (the FP32 layout is the smaller one)
+    __shared__ __align__(16) double ldsd[Lds2D<double>::size];
+    __shared__ double red[4 * kWaves2D];
+    static_assert(Lds2D<float>::size * sizeof(float) <= Lds2D<double>::size * sizeof(double), "LDS alias");
+    float* lpf = reinterpret_cast<float*>(ldsd);
+    int slot = 0;
+    const int64_t j = blockIdx.x;
+    const Strip sd = make_strip<double>(a.g);
+    const Strip sf = make_strip<float>(a.g);
+    const int nx = a.g.nx;
+    lds_clear(ldsd);
+    double up[S];
+    float x[S], r[S], q[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        up[s] = 0.0;
+        if (row_ok<EX, S>(sd, s)) {
+            const int64_t idx = (int64_t)(sd.gbase + s * nx);
+            up[s] = sweep_start(a, j, idx);
+            if (a.mode != 0) a.u[(j * a.m) * a.n + idx] = up[s];
+        }
+    }
+    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
+    long long its = 0;
+    for (int64_t t = 1; t <= total; ++t) {
+        const bool ystep = (t == a.m);
+        const double* xo;
+        if (!ystep)
+            xo = a.u + (j * a.m + t) * a.n;
+        else
+            xo = (a.mode == 0 ? a.u + ((j + 1) * a.m) * a.n : (a.mode == 1 ? a.y : a.aux) + (j + 1) * a.n);
+        double* dst = ystep ? a.y + (j + 1) * a.n : a.u + (j * a.m + t) * a.n;
+        // defect of the starting value in FP64, rounded to FP32 as the CG right-hand side
+        if (!PER) lds_clear_halo(a.g, ldsd);
+        {
+            const int64_t off = opaque_off(sd.gbase);
+            lds_put_fn<double, S, EX, PER, false>(a.g, sd, ldsd,
+                                                  [&](int s, double) { return xo[off + (int64_t)s * nx]; });
+        }
+        __syncthreads();
+        if (EX || sd.nr > 0)
+            strip_stencil<double, S, EX>(sd, ldsd, [&](int s, double u_, double c_, double d_, double w_, double e_) {
+                const double res = explicit_part(a.fine, up[s]) - stencil_value(a.fine, u_, c_, d_, w_, e_);
+                r[s] = (float)res;
+                return res;
+            });
+        __syncthreads();  // every read of the FP64 staging precedes its reuse as FP32
+        if (!PER) lds_clear_halo(a.g, lpf);
+#pragma unroll
+        for (int s = 0; s < S; ++s) x[s] = 0.0f;
+        its += cg2d<float, S, EX, PER, true>(a.g, a.fine, sf, x, r, q, lpf, red, slot, a.rtol2_mixed, a.maxit,
+                                             a.fail);
+        {
+            const int64_t off = opaque_off(sd.gbase);
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (row_ok<EX, S>(sd, s)) {
+                    const double v = xo[off + (int64_t)s * nx] + (double)x[s];
+                    up[s] = v;
+                    dst[off + (int64_t)s * nx] = v;
+                }
+        }
+        __syncthreads();  // the next step's FP64 staging overwrites the FP32 direction
+    }
+    count_cg(a, its);
+}
+
+// FP64 implicit residual |rho|^2 = sum_i |psi(u_{i-1}) - M u_i|^2, i = 1..nt.
+// HBM-bound: each workgroup owns 256 consecutive points of a slice over a
+// chunk of consecutive time indices, keeps u_{i-1} in registers and reads the
+// stencil neighbours of u_i through the caches (each slice leaves HBM once).
+// Work units are numbered so that the tiles of one chunk run on one XCD (the
+// dispatcher deals workgroups to the 8 XCDs in turn) and share its L2.
+constexpr int kResidTile = 256;
+
+__global__ __launch_bounds__(kResidTile) void implicit_residual_kernel(KArgs a, int64_t ntile, int64_t chunk,
+                                                                       int64_t units)
+{
+    __shared__ double red[2 * 2 * (kResidTile / 64)];
+    int slot = 0;
+    const int64_t per_xcd = gridDim.x / 8;
+    const int64_t w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (w >= units) return;  // whole workgroup, before any barrier
+    const int64_t tile = w % ntile;
+    const int64_t i0 = 1 + (w / ntile) * chunk;
+    const int64_t i1 = (i0 + chunk - 1 < a.nt) ? i0 + chunk - 1 : a.nt;
+    const int64_t idx = tile * kResidTile + threadIdx.x;
+    const bool act = idx < a.n;
+    const int nx = a.nx;
+    const int ny = (int)(a.n / nx);
+    const int x = (int)(idx % nx), y = (int)(idx / nx);
+    const bool per = a.g.periodic != 0;
+    // neighbour offsets (Dirichlet: -1 marks the zero boundary)
+    const int64_t ow = x > 0 ? idx - 1 : (per ? idx + nx - 1 : -1);
+    const int64_t oe = x < nx - 1 ? idx + 1 : (per ? idx - (nx - 1) : -1);
+    const int64_t on = y > 0 ? idx - nx : (per ? idx + (int64_t)(ny - 1) * nx : -1);
+    const int64_t os = y < ny - 1 ? idx + nx : (per ? idx - (int64_t)(ny - 1) * nx : -1);
+    const StepCoef c = a.fine;
+    double acc = 0.0;
+    if (act) {
+        double prev = a.u[(i0 - 1) * a.n + idx];
+        for (int64_t i = i0; i <= i1; ++i) {
+            const double* ui = a.u + i * a.n;
+            const double cen = ui[idx];
+            const double wv = ow >= 0 ? ui[ow] : 0.0;
+            const double ev = oe >= 0 ? ui[oe] : 0.0;
+            const double nv = on >= 0 ? ui[on] : 0.0;
+            const double sv = os >= 0 ? ui[os] : 0.0;
+            const double rho = explicit_part(c, prev) - stencil_value(c, nv, cen, sv, wv, ev);
+            acc += rho * rho;
+            prev = cen;
+        }
+    }
+    double unused = 0.0;
+    block_sum2(acc, unused, red, slot, kResidTile / 64);
+    if (threadIdx.x == 0) a.partials[w] = acc;
+}
+
+// Paper-form residual of the exact step, |r|^2 = sum_i |M^-1 rho_i|^2, i = 1..nt,
+// one workgroup per interval (task N_T takes the ragged tail).  M r_i = rho_i is
+// solved in FP64 by CG from zero to the fine tolerance relative to |rho_i|.
+template <int S, bool EX, bool PER>
+__global__ __launch_bounds__(kBlock2D) void step_residual2d_kernel(KArgs a)
+{
+    __shared__ __align__(16) double lp[Lds2D<double>::size];
+    __shared__ double red[4 * kWaves2D];
+    int slot = 0;
+    const int64_t j = blockIdx.x;
+    const Strip st = make_strip<double>(a.g);
+    const int nx = a.g.nx;
+    lds_clear(lp);
+    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
+    double x[S], r[S], q[S];
+    double acc = 0.0;
+    long long its = 0;
+    for (int64_t t = 1; t <= total; ++t) {
+        const int64_t i = j * a.m + t;
+        {
+            const int64_t off = opaque_off(st.gbase);
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                r[s] = row_ok<EX, S>(st, s) ? explicit_part(a.fine, a.u[(i - 1) * a.n + off + (int64_t)s * nx]) : 0.0;
+        }
+        {
+            const int64_t off = opaque_off(st.gbase);
+            const double* ui = a.u + i * a.n;
+            lds_put_fn<double, S, EX, PER, false>(a.g, st, lp,
+                                                  [&](int s, double) { return ui[off + (int64_t)s * nx]; });
+        }
+        __syncthreads();
+        if (EX || st.nr > 0)
+            strip_stencil<double, S, EX>(st, lp, [&](int s, double u_, double c_, double d_, double w_, double e_) {
+                r[s] = r[s] - stencil_value(a.fine, u_, c_, d_, w_, e_);
+                return r[s];
+            });
+        __syncthreads();  // the CG overwrites the staged slice
+#pragma unroll
+        for (int s = 0; s < S; ++s) x[s] = 0.0;
+        its += cg2d<double, S, EX, PER, true>(a.g, a.fine, st, x, r, q, lp, red, slot, a.rtol2, a.maxit, a.fail);
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (row_ok<EX, S>(st, s)) acc += x[s] * x[s];
+    }
+    double unused = 0.0;
+    block_sum2(acc, unused, red, slot, kWaves2D);
+    if (threadIdx.x == 0) a.partials[j] = acc;
+    count_cg(a, its);
+}
+
+// 1D form: M = tridiag(-c, 1 + 2c, -c) solved directly by PCR.
+__global__ __launch_bounds__(1024) void step_residual1d_kernel(KArgs a)
+{
+    __shared__ double lds[3 * 1024];
+    __shared__ double red[2 * 2 * 16];
+    int slot = 0;
+    const int64_t j = blockIdx.x;
+    const int i = threadIdx.x;
+    const int nx = a.nx;
+    const bool act = i < nx;
+    Pcr1D f;
+    pcr_setup(f, nx, a.fine.cx, lds);
+    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
+    const double c = a.fine.cx;
+    double acc = 0.0;
+    for (int64_t t = 1; t <= total; ++t) {
+        const int64_t ti = j * a.m + t;
+        double rho = 0.0;
+        if (act) {
+            const double* ui = a.u + ti * a.n;
+            const double w = i > 0 ? ui[i - 1] : 0.0;
+            const double e = i < nx - 1 ? ui[i + 1] : 0.0;
+            rho = a.u[(ti - 1) * a.n + i] - (a.fine.d * ui[i] - c * (w + e));
+        }
+        const double z = pcr_solve(f, nx, rho, lds);
+        if (act) acc += z * z;
+    }
+    double unused = 0.0;
+    block_sum2(acc, unused, red, slot, (int)(blockDim.x / 64));
+    if (threadIdx.x == 0) a.partials[j] = acc;
+}
+
+// hdr->norm2 = sum of partials[0 .. count-1] in a fixed order
+__global__ __launch_bounds__(256) void sum_partials_kernel(KArgs a, int64_t count)
+{
+    __shared__ double red[2 * 2 * 4];
+    int slot = 0;
+    double acc = 0.0, unused = 0.0;
+    for (int64_t b = threadIdx.x; b < count; b += 256) acc += a.partials[b];
+    block_sum2(acc, unused, red, slot, 4);
+    if (threadIdx.x == 0) a.hdr->norm2 = acc;
+}
+
+#define ATM_MIXED_S(kernel, S, EX, PER, grid, stream, a) \
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(kernel<S, EX, PER>), dim3(grid), dim3(kBlock2D), 0, stream, a)
+
+#define ATM_MIXED_EP(kernel, S, grid, stream, a)                                      \
+    do {                                                                              \
+        if ((a).exact) {                                                              \
+            if ((a).g.periodic) ATM_MIXED_S(kernel, S, true, true, grid, stream, a);  \
+            else ATM_MIXED_S(kernel, S, true, false, grid, stream, a);                \
+        } else {                                                                      \
+            if ((a).g.periodic) ATM_MIXED_S(kernel, S, false, true, grid, stream, a); \
+            else ATM_MIXED_S(kernel, S, false, false, grid, stream, a);               \
+        }                                                                             \
+    } while (0)
+
+#define ATM_MIXED_2D(kernel, grid, stream, a)                                \
+    do {                                                                     \
+        switch ((a).s_tmpl) {                                                \
+            case 8: ATM_MIXED_EP(kernel, 8, grid, stream, a); break;         \
+            case 16: ATM_MIXED_EP(kernel, 16, grid, stream, a); break;       \
+            default: ATM_MIXED_EP(kernel, 32, grid, stream, a); break;       \
+        }                                                                    \
+    } while (0)
+
+void launch_sweep_mixed(const KArgs& a, int64_t n_tasks, hipStream_t s)
+{
+    ATM_MIXED_2D(sweep2d_mixed_kernel, n_tasks, s, a);
+}
+
+namespace {
+struct ResidGrid {
+    int64_t ntile, chunk, units, blocks;
+};
+ResidGrid resid_grid(const KArgs& a)
+{
+    ResidGrid r;
+    r.ntile = (a.n + kResidTile - 1) / kResidTile;
+    int64_t nchunk = kResidBlocks / r.ntile;
+    if (nchunk < 1) nchunk = 1;
+    if (nchunk > a.nt) nchunk = a.nt;
+    r.chunk = (a.nt + nchunk - 1) / nchunk;
+    nchunk = (a.nt + r.chunk - 1) / r.chunk;
+    r.units = r.ntile * nchunk;
+    r.blocks = (r.units + 7) / 8 * 8;
+    return r;
+}
+}  // namespace
+
+int64_t implicit_residual_blocks(const KArgs& a) { return resid_grid(a).units; }
+
+void launch_implicit_residual(const KArgs& a, hipStream_t s)
+{
+    const ResidGrid r = resid_grid(a);
+    hipLaunchKernelGGL(implicit_residual_kernel, dim3(r.blocks), dim3(kResidTile), 0, s, a, r.ntile, r.chunk,
+                       r.units);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, a, r.units);
+}
+
+void launch_step_residual(const KArgs& a, int64_t n_tasks, hipStream_t s)
+{
+    if (a.is1d)
+        hipLaunchKernelGGL(step_residual1d_kernel, dim3(n_tasks), dim3(((a.nx + 63) / 64) * 64), 0, s, a);
+    else
+        ATM_MIXED_2D(step_residual2d_kernel, n_tasks, s, a);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, a, n_tasks);
+}
+
+}  // namespace atm

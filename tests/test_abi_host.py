@@ -56,7 +56,8 @@ def test_num_intervals_and_workspace(abi):
 
 @pytest.mark.parametrize("field,value,status", [
     ("m", 1, -1), ("k", 0, -1), ("relax", 2, -1), ("coarse_substeps", 0, -1), ("max_iter", -1, -1),
-    ("precision", 3, -2),
+    ("precision", 3, -1), ("mixed_cg_rtol", -1.0, -1), ("mixed_cg_rtol", 1.0, -1),
+    ("precision", 1, -2),  # the FP32 fine form is built for the 2D kinds only
 ])
 def test_invalid_options_rejected_before_launch(abi, field, value, status):
     p, o, _ = W.config("c1")
@@ -108,6 +109,7 @@ def test_strip_layout_rule_accepts_all_grids_up_to_128(abi):
     """Every 2D grid up to 128 x 128 passes the host's LDS-bounds rule (it is validated, not launched)."""
     for nx in (1, 3, 17, 63, 64, 65, 100, 127, 128):
         for ny in (1, 2, 31, 64, 97, 128):
-            p = W.Problem(W.HEAT2D, nx=nx, ny=ny, nt=8)
-            o = W.Options(m=2, k=2)
-            assert abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(o))) > 0
+            for precision in (0, 1):
+                p = W.Problem(W.HEAT2D, nx=nx, ny=ny, nt=8)
+                o = W.Options(m=2, k=2, precision=precision)
+                assert abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(o))) > 0

@@ -69,6 +69,7 @@ class Options:
     precision: int = 0      # 0 FP64 throughout, 1 FP32 fine sweeps + FP64 residual/correction
     profile: int = 0        # 1: the GPU solve times every kernel launch with HIP events
     coarse_cg_rtol: float = 0.0  # CG tolerance inside Psi; 0 = the problem's cg_rtol
+    mixed_cg_rtol: float = 0.0   # precision 1: FP32 CG tolerance of the fine correction solves; 0 = 1e-6
 
     def n_intervals(self, nt: int) -> int:
         return nt // self.m
