@@ -97,10 +97,13 @@ typedef struct atm_stats {
     double ms_sweep;       /* summed device time of the relaxation sweeps (profile = 1, else 0) */
     double ms_coarse;      /* summed device time of the local coarse solves incl. FAS tau (profile = 1) */
     double ms_norm;        /* summed device time of the residual-norm kernels (profile = 1) */
-    int64_t fine_steps;    /* Phi applications (all intervals, all sweeps) */
+    int64_t fine_steps;    /* Phi applications computed (all intervals, all sweeps) */
     int64_t coarse_steps;  /* Psi applications (all windows) */
     int64_t cg_fine;       /* CG iterations inside the sweeps' Phi steps (2D kinds) */
     int64_t cg_coarse;     /* CG iterations inside Psi (windows and FAS tau; 2D kinds) */
+    int64_t fine_steps_skipped; /* precision 0: Phi applications not recomputed because the
+                              interval's C-point value was unchanged since its last sweep (the
+                              F-points would come out bit for bit the same) */
     int32_t iterations;    /* cycles applied (number of coarse corrections) */
     int32_t n_sweeps;      /* sweep launches */
 } atm_stats;

@@ -48,7 +48,8 @@ class AtmStats(ctypes.Structure):
         ("final_residual", ctypes.c_double), ("ms_total", ctypes.c_double), ("ms_sweep", ctypes.c_double),
         ("ms_coarse", ctypes.c_double), ("ms_norm", ctypes.c_double),
         ("fine_steps", ctypes.c_int64), ("coarse_steps", ctypes.c_int64), ("cg_fine", ctypes.c_int64),
-        ("cg_coarse", ctypes.c_int64), ("iterations", ctypes.c_int32), ("n_sweeps", ctypes.c_int32),
+        ("cg_coarse", ctypes.c_int64), ("fine_steps_skipped", ctypes.c_int64),
+        ("iterations", ctypes.c_int32), ("n_sweeps", ctypes.c_int32),
     ]
 
 

@@ -213,9 +213,11 @@ atm_status read_header(const atm::KArgs& a, hipStream_t s, atm::Header* out)
 }
 
 atm_status do_sweep(atm::KArgs a, const atm_problem* p, const atm_options* o, int mode, double* u, const double* aux,
-                    double* y, hipStream_t s)
+                    double* y, hipStream_t s, bool skip_unchanged = false, const double* skip_y_src = nullptr)
 {
     a.mode = mode;
+    a.skip_unchanged = skip_unchanged ? 1 : 0;
+    a.skip_y_src = skip_y_src;
     a.u = u;
     a.aux = aux;
     a.y = y;
@@ -511,6 +513,10 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
         if ((st = T.end(s))) break;                   \
     } while (0)
     const bool mixed = (opts->precision == 1);
+    // After the first sweep every interval's F-points are the relaxation of its stored C-point, so a
+    // later FP64 sweep that starts an interval from the same value (bit for bit) would recompute
+    // them identically: it is skipped.  (FP32 sweeps refine their F-points and never skip.)
+    const bool skip = !mixed;
     // stopping norm: the C-point residual (FP64 form) or the FP64 implicit residual (mixed form)
     auto stop_norm = [&](double* yv, double* out) {
         return mixed ? do_implicit_norm(a, u, s, out, &h) : do_norm(a, u, yv, s, out, &h);
@@ -540,7 +546,7 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
         if (opts->relax == 1) {
             // CF: C-points take Phi of their preceding F-point (held in yprev), then F-relax
             ycur = (yprev == ya) ? yb : ya;
-            ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 2, u, yprev, ycur, s));
+            ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 2, u, yprev, ycur, s, skip, yprev));
             if (st) break;
             S.fine_steps += prob->nt;
             S.n_sweeps += 1;
@@ -550,7 +556,7 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
         S.coarse_steps += window_psi_count(NT, opts->k) + (a.fas ? NT : 0);
         // correction u_{pm} += e_p and F-interpolation; ycur receives Phi of every
         // last F-point (in the mixed form its entries also start those steps)
-        ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 1, u, e, ycur, s));
+        ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 1, u, e, ycur, s, skip, nullptr));
         if (st) break;
         S.fine_steps += prob->nt;
         S.n_sweeps += 1;
@@ -575,6 +581,8 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
     S.final_residual = final_res;
     S.cg_fine = (int64_t)h.cg_fine;
     S.cg_coarse = (int64_t)h.cg_coarse;
+    S.fine_steps_skipped = (int64_t)h.skipped;
+    S.fine_steps -= S.fine_steps_skipped;
     S.ms_sweep = T.ms[kPhSweep];
     S.ms_coarse = T.ms[kPhCoarse];
     S.ms_norm = T.ms[kPhNorm];

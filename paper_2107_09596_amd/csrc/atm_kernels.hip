@@ -23,11 +23,17 @@ __global__ __launch_bounds__(1024) void sweep1d_kernel(KArgs a)
     Pcr1D f;
     pcr_setup(f, a.nx, a.fine.cx, lds);
     double x = 0.0;
+    bool same = true;
     if (act) {
         x = sweep_start(a, j, i);
+        same = !(x != a.u[(j * a.m) * a.n + i]);
         if (a.mode != 0) a.u[(j * a.m) * a.n + i] = x;
     }
     const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
+    if (a.skip_unchanged && __syncthreads_and(same)) {
+        skip_interval(a, j, total, i, 0, act ? 1 : 0);
+        return;
+    }
     for (int64_t t = 1; t <= total; ++t) {
         x = pcr_solve(f, a.nx, x, lds);
         if (act) {
@@ -133,16 +139,23 @@ __global__ __launch_bounds__(kBlock2D) void sweep2d_kernel(KArgs a)
     lds_clear(lp);
     Strip2DState<S> v;
     const int nx = a.g.nx;
+    bool same = true;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         v.x[s] = 0.0;
         if (row_ok<EX, S>(st, s)) {
             const int64_t idx = (int64_t)(st.gbase + s * nx);
             v.x[s] = sweep_start(a, j, idx);
+            const double old = a.u[(j * a.m) * a.n + idx];
+            same = same && !(v.x[s] != old);
             if (a.mode != 0) a.u[(j * a.m) * a.n + idx] = v.x[s];
         }
     }
     const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
+    if (a.skip_unchanged && __syncthreads_and(same)) {
+        skip_interval(a, j, total, st.gbase, nx, EX ? S : st.nr);
+        return;
+    }
     long long its = 0;
     for (int64_t t = 1; t <= total; ++t) {
         its += step2d<S, EX, PER>(a, a.fine, a.rtol2, st, v, lp, red, slot);
@@ -289,6 +302,7 @@ __global__ void reset_header_kernel(Header* h)
         h->fail = 0;
         h->cg_fine = 0ull;
         h->cg_coarse = 0ull;
+        h->skipped = 0ull;
     }
 }
 

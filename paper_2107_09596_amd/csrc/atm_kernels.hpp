@@ -16,6 +16,7 @@ struct Header {
     int pad;
     unsigned long long cg_fine;    // CG iterations inside Phi since the last reset
     unsigned long long cg_coarse;  // CG iterations inside Psi since the last reset
+    unsigned long long skipped;    // fine steps not recomputed by sweeps with an unchanged C-point
 };
 
 struct KArgs {
@@ -39,6 +40,11 @@ struct KArgs {
     double rtol2_coarse;  // squared CG tolerance of Psi
     double rtol2_mixed;   // squared tolerance of the FP32 CG of the mixed-precision sweeps
     int maxit;
+    // FP64 sweeps inside a solve: an interval whose starting C-value equals the stored u_{jm}
+    // bit for bit keeps its F-points (they are the relaxation of that value from the previous
+    // sweep) and only provides y_{j+1}, copied from skip_y_src when that is not y itself
+    int skip_unchanged;
+    const double* skip_y_src;
 };
 
 // ---------------------------------------------------------------------------
@@ -64,6 +70,18 @@ __device__ __forceinline__ double sweep_start(const KArgs& a, int64_t j, int64_t
 __device__ __forceinline__ void count_cg(const KArgs& a, long long its)
 {
     if (threadIdx.x == 0 && its) atomicAdd(a.cg_count, (unsigned long long)its);
+}
+
+// Interval j of a skipped sweep: provide y_{j+1} and count its steps.
+__device__ __forceinline__ void skip_interval(const KArgs& a, int64_t j, int64_t total, int64_t idx0, int64_t stride,
+                                              int64_t count)
+{
+    if (a.skip_y_src && j < a.NT)
+        for (int64_t q = 0; q < count; ++q) {
+            const int64_t idx = idx0 + q * stride;
+            a.y[(j + 1) * a.n + idx] = a.skip_y_src[(j + 1) * a.n + idx];
+        }
+    if (threadIdx.x == 0 && total > 0) atomicAdd(&a.hdr->skipped, (unsigned long long)total);
 }
 
 // Explicit part of a step: psi(v) = v for heat, v + dt (v - v^3) / eps^2 for

@@ -182,6 +182,7 @@ def test_mixed_solve_converges_to_fp64_solution(atm, orc, case):
     o64 = W.Options(**{**o.__dict__, "precision": 0})
     _, h64, st64 = atm.atm_solve(p, o64, dev(W.initial_guess(p, u0)))
     assert st["iterations"] <= st64["iterations"] + 2
+    assert st["fine_steps_skipped"] == 0  # FP32 sweeps refine their F-points every time
 
 
 def test_mixed_deterministic_bitwise(atm):
