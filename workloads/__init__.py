@@ -187,3 +187,46 @@ def small_problem(kind: int, seed: int = 0, nt: int = 48, nx: int = 7, ny: int =
     else:
         raise KeyError(kind)
     return p, u0
+
+
+# ---------------------------------------------------------------------------
+# learned coarse propagator: seeded initial weights and training-data recipe
+# ---------------------------------------------------------------------------
+
+CNN_CHANNELS = 32
+# flat parameter layout: W1[9][32] (tap, out), b1[32], W2[9][32][32] (tap, out, in), b2[32],
+# W3[9][32][32], b3[32], W4[9][32] (tap, in), b4[1]
+CNN_SIZES = [(9 * 32, 9), (32, 0), (9 * 32 * 32, 9 * 32), (32, 0), (9 * 32 * 32, 9 * 32), (32, 0), (9 * 32, 9 * 32),
+             (1, 0)]
+CNN_N_PARAMS = sum(n for n, _ in CNN_SIZES)
+
+
+def cnn_init(seed: int, last_scale: float = 0.1) -> np.ndarray:
+    """He-normal initial weights (std sqrt(2 / fan_in)), zero biases, as one float32 vector.
+
+    The last layer is scaled by last_scale so that Psi = u + f(u) starts close
+    to the identity.
+    """
+    rng = np.random.default_rng(seed)
+    parts = []
+    for i, (n, fan_in) in enumerate(CNN_SIZES):
+        if fan_in == 0:
+            parts.append(np.zeros(n))
+        else:
+            w = rng.normal(0.0, math.sqrt(2.0 / fan_in), size=n)
+            parts.append(w * (last_scale if i == 6 else 1.0))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def cnn_training_recipe():
+    """Training trajectories of the learned-Psi workload: 40 fields U[-0.05, 0.05] drawn in turn from
+    default_rng(5), pairs (u_n, u_{n+32}) at n = 0, 8, 16, ... of each trajectory, the first 20000 pairs;
+    2 validation trajectories from default_rng(6)."""
+    return {"n_train_traj": 40, "train_seed": 5, "n_val_traj": 2, "val_seed": 6, "stride": 8, "lag": 32,
+            "n_pairs": 20000}
+
+
+def ac2d_fields(n_fields: int, nx: int, ny: int, seed: int, amp: float = 0.05) -> np.ndarray:
+    """n_fields i.i.d. U[-amp, amp] fields drawn in turn from one generator, [n_fields, nx*ny]."""
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.uniform(-amp, amp, size=nx * ny) for _ in range(n_fields)])
