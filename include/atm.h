@@ -210,6 +210,55 @@ size_t atm_sequential_workspace_bytes(const atm_problem* prob);
 atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u, void* ws,
                      size_t ws_bytes, double* hist, int32_t hist_cap, atm_stats* stats, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Learned coarse propagator (section 2.1 lets the coarse propagator be any
+ * approximation of Phi over a coarse step).  Psi(u) = u + f(u), f a four-layer
+ * 3x3 convolutional network on the periodic h x w grid: 1 -> 32 -> 32 -> 32 -> 1
+ * channels, ReLU after the first three layers, circular padding.  Weights and
+ * activations BF16, FP32 accumulation (BF16 MFMA for the 32 -> 32 layers);
+ * biases FP32.  Parameters are one FP32 vector of atm_cnn_param_count() entries
+ * (device), in this order: W1[9][32] (tap, out channel), b1[32],
+ * W2[9][32][32] (tap, out, in), b2[32], W3[9][32][32], b3[32], W4[9][32]
+ * (tap, in channel), b4[1]; tap t = (dy + 1) * 3 + (dx + 1) weighs the input at
+ * (y + dy, x + dx).  Fields are [batch][h][w] FP32 (device), row-major.
+ * All calls enqueue on `stream` and return; results are valid after a sync.
+ * Limits: w a multiple of 16 in [16, 128]; h >= 1.  Errors: INVALID_ARG,
+ * UNSUPPORTED, WORKSPACE, DEVICE.
+ * ------------------------------------------------------------------------ */
+
+/* 19105: the length of the parameter vector. */
+int32_t atm_cnn_param_count(void);
+
+/* Workspace bytes for a batch of that many h x w fields (0 if invalid). */
+size_t atm_cnn_workspace_bytes(int32_t batch, int32_t h, int32_t w);
+
+/* f_out[b] = f(x[b]) for b < batch (the network output; Psi(x) = x + f(x)). */
+atm_status atm_cnn_forward(const float* params, const float* x, int32_t batch, int32_t h, int32_t w,
+                           float* f_out, void* ws, size_t ws_bytes, void* stream);
+
+/* out[b] = e[b] + J_f(v[b]) e[b]: the derivative of Psi at v applied to e (the
+   ReLU masks of the forward pass at v; no biases). */
+atm_status atm_cnn_jvp(const float* params, const float* v, const float* e, int32_t batch, int32_t h,
+                       int32_t w, float* out, void* ws, size_t ws_bytes, void* stream);
+
+/* Mean squared error L = mean over the batch of (x + f(x) - y)^2 with
+   x = frames[idx_x[b]], y = frames[idx_y[b]] (frames: [n_frames][h][w] FP32,
+   device; idx_x, idx_y: host arrays of batch indices in [0, n_frames)), and
+   its gradient by back-propagation.  grad_out (device) receives
+   atm_cnn_param_count() floats; loss_out (device, nullable) one float. */
+atm_status atm_cnn_gradients(const float* params, const float* frames, int32_t n_frames, const int32_t* idx_x,
+                             const int32_t* idx_y, int32_t batch, int32_t h, int32_t w, float* grad_out,
+                             float* loss_out, void* ws, size_t ws_bytes, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on
+   params (device, in/out) with the moments adam_m, adam_v (device, in/out,
+   zero before step 1) and the gradient of the batch above.  loss_out (device,
+   nullable) receives the batch loss before the step. */
+atm_status atm_cnn_train_step(float* params, float* adam_m, float* adam_v, int32_t step, float lr,
+                              const float* frames, int32_t n_frames, const int32_t* idx_x, const int32_t* idx_y,
+                              int32_t batch, int32_t h, int32_t w, float* loss_out, void* ws, size_t ws_bytes,
+                              void* stream);
+
 /* Human-readable name of a status code (static string). */
 const char* atm_status_string(atm_status status);
 

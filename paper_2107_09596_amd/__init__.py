@@ -17,7 +17,8 @@ from ._abi import (ATM_AC2D, ATM_ERR_DEVICE, ATM_ERR_DIVERGED, ATM_ERR_INNER_SOL
 __all__ = [
     "atm_num_intervals", "atm_window_start", "atm_workspace_bytes", "atm_sweep", "atm_coarse_solve",
     "atm_residual_norm", "atm_implicit_residual_norm", "atm_step_residual_norm", "atm_sequential", "atm_sequential_workspace_bytes", "atm_solve", "atm_status_string",
-    "atm_last_error", "workspace", "AtmError", "ATM_OK", "ATM_NOT_CONVERGED", "ATM_ERR_INVALID_ARG",
+    "atm_last_error", "workspace", "atm_cnn_param_count", "atm_cnn_workspace_bytes", "atm_cnn_forward",
+    "atm_cnn_jvp", "atm_cnn_gradients", "atm_cnn_train_step", "AtmError", "ATM_OK", "ATM_NOT_CONVERGED", "ATM_ERR_INVALID_ARG",
     "ATM_ERR_UNSUPPORTED", "ATM_ERR_DEVICE", "ATM_ERR_DIVERGED", "ATM_ERR_INNER_SOLVE", "ATM_ERR_WORKSPACE",
     "ATM_HEAT1D", "ATM_HEAT2D", "ATM_AC2D",
 ]
@@ -145,3 +146,73 @@ def atm_status_string(status: int) -> str:
 
 def atm_last_error() -> str:
     return _abi.lib().atm_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# learned coarse propagator (CNN): marshalling only
+# ---------------------------------------------------------------------------
+
+def _f32():
+    return _torch().float32
+
+
+def _int32_host(a):
+    import numpy as np
+    arr = np.ascontiguousarray(a, dtype=np.int32)
+    return arr, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def atm_cnn_param_count() -> int:
+    return int(_abi.lib().atm_cnn_param_count())
+
+
+def atm_cnn_workspace_bytes(batch: int, h: int, w: int) -> int:
+    return int(_abi.lib().atm_cnn_workspace_bytes(int(batch), int(h), int(w)))
+
+
+def _nbytes(t):
+    return t.numel() * t.element_size()
+
+
+def atm_cnn_forward(params, x, f_out, ws, stream=None) -> None:
+    """f_out[b] = f(x[b]); x, f_out: [batch, h, w] float32 device tensors."""
+    b, h, w = x.shape
+    st = _abi.lib().atm_cnn_forward(_ptr(params, _f32(), "params"), _ptr(x, _f32(), "x"), b, h, w,
+                                    _ptr(f_out, _f32(), "f_out"), _ptr(ws, None, "ws"), _nbytes(ws), _stream(stream))
+    _abi.check(st, "atm_cnn_forward")
+
+
+def atm_cnn_jvp(params, v, e, out, ws, stream=None) -> None:
+    b, h, w = v.shape
+    st = _abi.lib().atm_cnn_jvp(_ptr(params, _f32(), "params"), _ptr(v, _f32(), "v"), _ptr(e, _f32(), "e"), b, h, w,
+                                _ptr(out, _f32(), "out"), _ptr(ws, None, "ws"), _nbytes(ws), _stream(stream))
+    _abi.check(st, "atm_cnn_jvp")
+
+
+def atm_cnn_gradients(params, frames, idx_x, idx_y, grad_out, ws, loss_out=None, stream=None) -> None:
+    """frames: [n_frames, h, w] float32 device; idx_x, idx_y: host integer sequences of equal length."""
+    n, h, w = frames.shape
+    ax, px = _int32_host(idx_x)
+    ay, py = _int32_host(idx_y)
+    if ax.shape != ay.shape:
+        raise ValueError("idx_x and idx_y must have the same length")
+    st = _abi.lib().atm_cnn_gradients(_ptr(params, _f32(), "params"), _ptr(frames, _f32(), "frames"), n, px, py,
+                                      len(ax), h, w, _ptr(grad_out, _f32(), "grad_out"),
+                                      _ptr(loss_out, _f32(), "loss_out"), _ptr(ws, None, "ws"), _nbytes(ws),
+                                      _stream(stream))
+    _abi.check(st, "atm_cnn_gradients")
+
+
+def atm_cnn_train_step(params, adam_m, adam_v, step: int, lr: float, frames, idx_x, idx_y, ws, loss_out=None,
+                       stream=None) -> None:
+    n, h, w = frames.shape
+    ax, px = _int32_host(idx_x)
+    ay, py = _int32_host(idx_y)
+    if ax.shape != ay.shape:
+        raise ValueError("idx_x and idx_y must have the same length")
+    st = _abi.lib().atm_cnn_train_step(_ptr(params, _f32(), "params"), _ptr(adam_m, _f32(), "adam_m"),
+                                       _ptr(adam_v, _f32(), "adam_v"), int(step), float(lr),
+                                       _ptr(frames, _f32(), "frames"), n, px, py, len(ax), h, w,
+                                       _ptr(loss_out, _f32(), "loss_out"), _ptr(ws, None, "ws"), _nbytes(ws),
+                                       _stream(stream))
+    _abi.check(st, "atm_cnn_train_step")

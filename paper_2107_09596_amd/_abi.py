@@ -58,6 +58,7 @@ _O = ctypes.POINTER(AtmOptions)
 _S = ctypes.POINTER(AtmStats)
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
 
 # name -> (restype, argtypes); every symbol include/atm.h declares
 SIGNATURES = {
@@ -72,6 +73,17 @@ SIGNATURES = {
     "atm_sequential": (ctypes.c_int32, [_P, _vp, _vp, ctypes.c_size_t, _vp]),
     "atm_sequential_workspace_bytes": (ctypes.c_size_t, [_P]),
     "atm_solve": (ctypes.c_int32, [_P, _O, _vp, _vp, ctypes.c_size_t, _dp, ctypes.c_int32, _S, _vp]),
+    "atm_cnn_param_count": (ctypes.c_int32, []),
+    "atm_cnn_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "atm_cnn_forward": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                                         ctypes.c_size_t, _vp]),
+    "atm_cnn_jvp": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                                     ctypes.c_size_t, _vp]),
+    "atm_cnn_gradients": (ctypes.c_int32, [_vp, _vp, ctypes.c_int32, _ip, _ip, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "atm_cnn_train_step": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, _vp, ctypes.c_int32,
+                                            _ip, _ip, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                                            ctypes.c_size_t, _vp]),
     "atm_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "atm_last_error": (ctypes.c_char_p, []),
 }

@@ -15,6 +15,12 @@ namespace {
 
 thread_local std::string g_last_error;
 
+}  // namespace
+
+void atm::set_last_error(const char* msg) { g_last_error = msg; }
+
+namespace {
+
 atm_status fail(atm_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 atm_status fail(atm_status st, const char* fmt, ...)
 {

@@ -109,6 +109,9 @@ __device__ __forceinline__ void strip_store(double* dst, const Strip& st, int nx
         if (row_ok<EX, S>(st, s)) dst[off + (int64_t)s * nx] = v[s];
 }
 
+// the message returned by atm_last_error() on this thread
+void set_last_error(const char* msg);
+
 void launch_reset(Header* h, hipStream_t s);
 void launch_sweep(const KArgs& a, int64_t n_tasks, hipStream_t s);
 void launch_tau(const KArgs& a, hipStream_t s);
