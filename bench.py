@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--coarse-rtol", type=float, default=1e-6,
                     help="CG tolerance inside the coarse propagator (0 = the fine cg_rtol)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-coarse-propagator comparison")
+    ap.add_argument("--learned-epochs", type=int, default=15)
     ap.add_argument("--cpu-steps", type=int, default=4096,
                     help="time steps of the oracle's sequential stepping timed for cpu_baseline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -81,6 +83,59 @@ def cpu_baseline(p, u0, steps):
         "sample": f"oracle sequential time stepping (exact forward solve, residual 0) of the first {steps} "
                   f"of {p.nt} steps of the same workload, 1 thread, {dt:.2f} s",
     }
+
+
+def learned_leg(epochs):
+    """Learned vs plain coarse propagator on 2D Allen-Cahn 128x128 periodic, eps 0.03, Nt 4096, m 32: train the
+    CNN on the GPU (pairs of the fine propagator), then time both solves to the same 1e-8 residual."""
+    import torch
+
+    import paper_2107_09596_amd as atm
+    import workloads as W
+    from paper_2107_09596_amd import learned
+
+    p, o, u0 = W.config("c5")
+    rc = W.cnn_training_recipe()
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    frames = learned.trajectory_frames(p, W.ac2d_fields(rc["n_train_traj"], p.nx, p.ny, rc["train_seed"]),
+                                       stride=rc["stride"], device=dev)
+    vframes = learned.trajectory_frames(p, W.ac2d_fields(rc["n_val_traj"], p.nx, p.ny, rc["val_seed"]),
+                                        stride=rc["stride"], device=dev)
+    gen_s = time.perf_counter() - t0
+    per = p.nt // rc["stride"] + 1
+    lag = rc["lag"] // rc["stride"]
+    ix, iy = learned.pair_indices(rc["n_train_traj"], per, lag, rc["n_pairs"])
+    vx, vy = learned.pair_indices(rc["n_val_traj"], per, lag, rc["n_val_traj"] * (per - lag))
+    params = torch.from_numpy(W.cnn_init(rc["train_seed"])).to(dev)
+    losses, train_s = learned.train(params, frames, ix, iy, W.cnn_epoch_orders(rc["train_seed"], len(ix), epochs))
+    val_loss = learned.mean_loss(params, vframes, vx, vy)
+    guess = torch.from_numpy(W.initial_guess(p, u0)).to(dev)
+    o.profile = 1
+    res = {}
+    for name, opts in (("plain", o), ("learned", W.Options(**{**o.__dict__, "coarse_form": 3, "cnn_params": params}))):
+        ws = atm.workspace(atm.atm_workspace_bytes(p, opts), device=dev)
+        runs = []
+        for _ in range(2):  # the first run warms up
+            u = guess.clone()
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            status, hist, st = atm.atm_solve(p, opts, u, ws=ws, allow=(atm.ATM_OK, atm.ATM_NOT_CONVERGED))
+            torch.cuda.synchronize()
+            runs.append(((time.perf_counter() - ts) * 1e3, status, hist, st))
+        ms, status, hist, st = runs[-1]
+        res[name] = {"ms": ms, "status": int(status), "cycles": st["iterations"], "final_residual": st["final_residual"],
+                     "learned_cycles": st["learned_cycles"], "ms_coarse": st["ms_coarse"], "ms_sweep": st["ms_sweep"],
+                     "value": p.n * p.nt / (ms / 1e3)}
+        del ws
+    res["speedup_learned_over_plain"] = res["plain"]["ms"] / res["learned"]["ms"]
+    res["speedup_with_training_amortised_over_one_solve"] = res["plain"]["ms"] / (res["learned"]["ms"] + train_s * 1e3)
+    res["training"] = {"pairs": len(ix), "epochs": epochs, "batch": 64, "lr": 1e-3, "seconds": train_s,
+                       "data_generation_seconds": gen_s, "final_train_loss": losses[-1], "validation_loss": val_loss}
+    res["workload"] = ("2D Allen-Cahn 128x128 periodic, eps=0.03, dt=1e-5, Nt=4096, m=32, k=%d, FCF, precision %d, "
+                       "tol 1e-8; learned = CNN 1-32-32-32-1 (BF16, FP32 accumulate) linearised in the windows" %
+                       (o.k, o.precision))
+    return res
 
 
 def main():
@@ -201,6 +256,8 @@ def main():
                            "speedup_of_atmgrit": seq_s * 1e3 / ms_per_step,
                            "max_abs_diff_to_atmgrit": max_diff},
     }
+    if not args.no_learned:
+        out["learned_coarse"] = learned_leg(args.learned_epochs)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, u0, min(args.cpu_steps, p.nt))
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

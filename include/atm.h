@@ -78,12 +78,24 @@ typedef struct atm_options {
                               fixed point */
     double mixed_cg_rtol;  /* precision 1: relative tolerance of the FP32 CG of each fine step's
                               correction solve; 0 = 1e-6.  The FP64 fixed point does not depend on it */
+    double fallback_ratio; /* coarse_form 3: once the residual has decreased in some cycle, two
+                              consecutive cycles with ||r_i|| > fallback_ratio ||r_{i-1}|| (or, at any
+                              time, ||r_i|| > 1e6 ||r_0||) switch the remaining cycles to the plain
+                              coarse propagator, keeping the iterate; 0 = 0.95 */
+    const float* cnn_params; /* coarse_form 3: the learned propagator's parameters (device, see
+                              atm_cnn_param_count); read during the call only */
     int32_t m;             /* coarsening factor, >= 2 (section 2.1) */
     int32_t k;             /* C-points per local coarse grid, >= 1; k >= N_T+1 is Parareal */
     int32_t relax;         /* 0: F-relaxation, 1: FCF-relaxation (section 2.2) */
     int32_t max_iter;      /* maximum number of cycles */
     int32_t coarse_substeps; /* Psi = s steps of size m dt / s, s >= 1 */
-    int32_t coarse_form;   /* 0 auto (linear for heat, FAS for Allen-Cahn), 1 linear, 2 FAS */
+    int32_t coarse_form;   /* 0 auto (linear for heat, FAS for Allen-Cahn), 1 linear, 2 FAS,
+                              3 learned: the FAS form with the learned propagator Psi(v) = v + f(v)
+                              (see atm_cnn_forward) in place of the re-discretised one (ATM_AC2D, nx a
+                              multiple of 16 up to 128).  A BF16 network is not a smooth function of its
+                              input, so FAS differences Psi(w) - Psi(v) of nearby states carry rounding
+                              jumps that stall the residual at some level: the fallback below then
+                              finishes with the plain propagator */
     int32_t precision;     /* 0: FP64 throughout; 1 (2D kinds): FP32 fine solves in defect-correction
                               form with the residual, coarse correction and iterate in FP64
                               (see atm_sweep and atm_solve) */
@@ -106,6 +118,7 @@ typedef struct atm_stats {
                               F-points would come out bit for bit the same) */
     int32_t iterations;    /* cycles applied (number of coarse corrections) */
     int32_t n_sweeps;      /* sweep launches */
+    int32_t learned_cycles; /* coarse_form 3: cycles whose correction came from the learned propagator */
 } atm_stats;
 
 /* Number of coarse intervals N_T = floor(nt / m); C-points are 0..N_T. */
@@ -155,6 +168,7 @@ atm_status atm_sweep(const atm_problem* prob, const atm_options* opts, int32_t m
      linear form: e = r_s; e = Psi(e) + r_j for j = s+1..p; e_p = e.
      FAS form (Alg. 2, coarsest level): v_j = u_{jm}; w = v_s + r_s;
        w = Psi(w) + (v_j - Psi(v_{j-1}) + r_j) for j = s+1..p; e_p = w - v_p.
+   learned form (coarse_form 3): the FAS form with Psi = the learned propagator.
    u (device) [nt+1][n] in; y (device) [N_T+1][n] in; e (device) [N_T+1][n] out. */
 atm_status atm_coarse_solve(const atm_problem* prob, const atm_options* opts, const double* u,
                             const double* y, double* e, void* ws, size_t ws_bytes, void* stream);

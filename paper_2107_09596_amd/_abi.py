@@ -37,6 +37,7 @@ class AtmProblem(ctypes.Structure):
 class AtmOptions(ctypes.Structure):
     _fields_ = [
         ("tol", ctypes.c_double), ("coarse_cg_rtol", ctypes.c_double), ("mixed_cg_rtol", ctypes.c_double),
+        ("fallback_ratio", ctypes.c_double), ("cnn_params", ctypes.c_void_p),
         ("m", ctypes.c_int32), ("k", ctypes.c_int32), ("relax", ctypes.c_int32),
         ("max_iter", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32), ("coarse_form", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("profile", ctypes.c_int32),
@@ -49,7 +50,7 @@ class AtmStats(ctypes.Structure):
         ("ms_coarse", ctypes.c_double), ("ms_norm", ctypes.c_double),
         ("fine_steps", ctypes.c_int64), ("coarse_steps", ctypes.c_int64), ("cg_fine", ctypes.c_int64),
         ("cg_coarse", ctypes.c_int64), ("fine_steps_skipped", ctypes.c_int64),
-        ("iterations", ctypes.c_int32), ("n_sweeps", ctypes.c_int32),
+        ("iterations", ctypes.c_int32), ("n_sweeps", ctypes.c_int32), ("learned_cycles", ctypes.c_int32),
     ]
 
 
@@ -128,7 +129,12 @@ def problem(p) -> AtmProblem:
 
 def options(o) -> AtmOptions:
     """AtmOptions from any object with the fields of workloads.Options."""
+    cnn = getattr(o, "cnn_params", None)
+    if cnn is not None and not isinstance(cnn, int):
+        cnn = cnn.data_ptr()  # a device tensor
     return AtmOptions(tol=o.tol, coarse_cg_rtol=float(getattr(o, "coarse_cg_rtol", 0.0)),
-                      mixed_cg_rtol=float(getattr(o, "mixed_cg_rtol", 0.0)), m=o.m, k=o.k, relax=o.relax,
+                      mixed_cg_rtol=float(getattr(o, "mixed_cg_rtol", 0.0)),
+                      fallback_ratio=float(getattr(o, "fallback_ratio", 0.0)), cnn_params=cnn,
+                      m=o.m, k=o.k, relax=o.relax,
                       max_iter=o.max_iter, coarse_substeps=o.coarse_substeps, coarse_form=o.coarse_form,
                       precision=getattr(o, "precision", 0), profile=int(getattr(o, "profile", 0)))

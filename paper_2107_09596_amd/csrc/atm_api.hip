@@ -9,6 +9,7 @@
 #include <string>
 
 #include "../../include/atm.h"
+#include "atm_cnn.hpp"
 #include "atm_kernels.hpp"
 
 namespace {
@@ -41,21 +42,25 @@ atm_status fail(atm_status st, const char* fmt, ...)
 
 constexpr size_t kAlign = 256;
 constexpr double kMixedRtolDefault = 1e-6;  // FP32 CG tolerance of the mixed sweeps
+constexpr double kLearnedGrowthLimit = 1e6;  // learned coarse solve: give up beyond this growth of the residual
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t header, partials, ya, yb, e, tau, total;
+    size_t header, partials, ya, yb, e, tau, pk, d1, d2, total;
 };
 
 int64_t n_intervals(const atm_problem* p, const atm_options* o) { return p->nt / o->m; }
 int64_t n_space(const atm_problem* p) { return (int64_t)p->nx * p->ny; }
 
+// the plain coarse propagator's form (coarse_form 3 falls back to the automatic choice)
 bool use_fas(const atm_problem* p, const atm_options* o)
 {
     if (o->coarse_form == 1) return false;
     if (o->coarse_form == 2) return true;
     return p->kind == ATM_AC2D;
 }
+
+bool learned(const atm_options* o) { return o->coarse_form == 3; }
 
 Layout layout(const atm_problem* p, const atm_options* o)
 {
@@ -75,6 +80,14 @@ Layout layout(const atm_problem* p, const atm_options* o)
     off += align_up(slab);
     L.tau = off;
     off += use_fas(p, o) ? align_up(slab) : 0;
+    // learned coarse solve: BF16 weights and two BF16 activation buffers for N_T + 1 fields
+    const size_t act = learned(o) ? (size_t)n_space(p) * atm::cnn::C * 2 : 0;
+    L.pk = off;
+    off += learned(o) ? align_up(atm::cnn::PK_N * 2) : 0;
+    L.d1 = off;
+    off += align_up((NT + 1) * act);
+    L.d2 = off;
+    off += align_up((NT + 1) * act);
     L.total = off;
     return L;
 }
@@ -97,7 +110,15 @@ atm_status validate(const atm_problem* p, const atm_options* o)
     if (o->k < 1) return fail(ATM_ERR_INVALID_ARG, "k must be >= 1");
     if (o->relax != 0 && o->relax != 1) return fail(ATM_ERR_INVALID_ARG, "relax must be 0 (F) or 1 (FCF)");
     if (o->coarse_substeps < 1) return fail(ATM_ERR_INVALID_ARG, "coarse_substeps must be >= 1");
-    if (o->coarse_form < 0 || o->coarse_form > 2) return fail(ATM_ERR_INVALID_ARG, "coarse_form must be 0, 1 or 2");
+    if (o->coarse_form < 0 || o->coarse_form > 3) return fail(ATM_ERR_INVALID_ARG, "coarse_form must be 0, 1, 2 or 3");
+    if (o->coarse_form == 3) {
+        if (p->kind != ATM_AC2D)
+            return fail(ATM_ERR_UNSUPPORTED, "the learned coarse propagator is built for the periodic ATM_AC2D grid");
+        if (p->nx % 16 != 0 || p->nx > 128)
+            return fail(ATM_ERR_UNSUPPORTED, "the learned coarse propagator needs nx a multiple of 16, at most 128");
+        if (!o->cnn_params) return fail(ATM_ERR_INVALID_ARG, "coarse_form 3 needs cnn_params");
+        if (!(o->fallback_ratio >= 0.0)) return fail(ATM_ERR_INVALID_ARG, "fallback_ratio must be >= 0");
+    }
     if (o->max_iter < 0) return fail(ATM_ERR_INVALID_ARG, "max_iter must be >= 0");
     if (!(o->tol >= 0.0)) return fail(ATM_ERR_INVALID_ARG, "tol must be >= 0");
     if (o->precision != 0 && o->precision != 1) return fail(ATM_ERR_INVALID_ARG, "precision must be 0 or 1");
@@ -311,6 +332,102 @@ atm_status after_standalone_norm(const atm::KArgs& a, atm_status st, double norm
     return st;
 }
 
+// one batched forward pass f of the learned propagator over nb FP64 fields x + map(b) * stride,
+// ending in the layer-4 epilogue l4 (whose nb/h/w/in/w4/b4 are filled here)
+void learned_forward(const float* params, const __bf16* pk, __bf16* d1, __bf16* d2, int64_t nb, int h, int w,
+                     const double* x, int64_t stride, atm::cnn::FieldMap xmap, atm::cnn::L4Args l4, hipStream_t s)
+{
+    using namespace atm::cnn;
+    L1Args l1;
+    memset(&l1, 0, sizeof(l1));
+    l1.nb = nb;
+    l1.h = h;
+    l1.w = w;
+    l1.x = x;
+    l1.x_f64 = 1;
+    l1.x_stride = stride;
+    l1.xmap = xmap;
+    l1.w1 = pk + PK_W1;
+    l1.b1 = params + OFF_B1;
+    l1.out = d1;
+    launch_l1(l1, s);
+    ConvArgs cv;
+    memset(&cv, 0, sizeof(cv));
+    cv.nb = nb;
+    cv.h = h;
+    cv.w = w;
+    cv.in = d1;
+    cv.out = d2;
+    cv.wpk = pk + PK_W2F;
+    cv.bias = params + OFF_B2;
+    launch_conv32(cv, s);
+    cv.in = d2;
+    cv.out = d1;
+    cv.wpk = pk + PK_W3F;
+    cv.bias = params + OFF_B3;
+    launch_conv32(cv, s);
+    l4.nb = nb;
+    l4.h = h;
+    l4.w = w;
+    l4.in = d1;
+    l4.w4 = pk + PK_W4;
+    l4.b4 = params + OFF_B4;
+    launch_l4(l4, s);
+}
+
+// Learned coarse solve in FAS form (Alg. 2, coarsest level) with Psi(v) = v + f(v):
+// tau_j = (v_j - Psi(v_{j-1})) + r_j, then every window w_s = v_s + r_s,
+// w_j = Psi(w_{j-1}) + tau_j, e_p = w_p - v_p; the windows active at a step are one batch.
+atm_status do_coarse_learned(atm::KArgs a, const Layout& L, void* ws, const atm_problem* p, const atm_options* o,
+                             double* u, double* y, double* e, hipStream_t s)
+{
+    using namespace atm::cnn;
+    char* base = (char*)ws;
+    __bf16* pk = (__bf16*)(base + L.pk);
+    __bf16* d1 = (__bf16*)(base + L.d1);
+    __bf16* d2 = (__bf16*)(base + L.d2);
+    const int64_t NT = a.NT, n = a.n;
+    const int h = p->ny, w = p->nx;
+    const float* params = o->cnn_params;
+    launch_pack(params, pk, s);
+    if (NT >= 1) {
+        // tau_j, j = 1..N_T, from Psi at the states v_{j-1}
+        L4Args l4;
+        memset(&l4, 0, sizeof(l4));
+        l4.epi = EPI_TAU;
+        l4.tau = a.tau;
+        l4.ysol = y;
+        l4.usol = u;
+        l4.m = a.m;
+        FieldMap xm;
+        memset(&xm, 0, sizeof(xm));
+        learned_forward(params, pk, d1, d2, NT, h, w, u, (int64_t)a.m * n, xm, l4, s);
+    }
+    launch_window_init(e, y, u, NT, n, a.m, a.k, s);
+    const int64_t steps = (a.k - 1 < NT) ? a.k - 1 : NT;
+    for (int64_t t = 1; t <= steps; ++t) {
+        // windows p = t..N_T take step t towards C-point s_p + t
+        FieldMap sm;
+        memset(&sm, 0, sizeof(sm));
+        sm.mode = 2;
+        sm.t = (int)t;
+        sm.k = a.k;
+        FieldMap em;
+        memset(&em, 0, sizeof(em));
+        em.off = t;
+        L4Args l4;
+        memset(&l4, 0, sizeof(l4));
+        l4.epi = EPI_WINDOW;
+        l4.e = e;
+        l4.emap = em;
+        l4.smap = sm;
+        l4.tau = a.tau;
+        learned_forward(params, pk, d1, d2, NT + 1 - t, h, w, e, n, em, l4, s);
+    }
+    launch_window_final(e, u, NT, n, a.m, s);
+    return check_launch();
+}
+
 // Options used by atm_sequential (only the workspace header is needed).
 atm_options sequential_options()
 {
@@ -419,6 +536,8 @@ atm_status atm_coarse_solve(const atm_problem* prob, const atm_options* opts, co
     if (st) return st;
     if (!u || !y || !e) return fail(ATM_ERR_INVALID_ARG, "null u, y or e");
     if (e == y) return fail(ATM_ERR_INVALID_ARG, "e and y must not alias");
+    if (learned(opts))
+        return do_coarse_learned(a, layout(prob, opts), ws, prob, opts, (double*)u, (double*)y, e, as_stream(stream));
     return do_coarse(a, (double*)u, (double*)y, e, as_stream(stream));
 }
 
@@ -539,6 +658,11 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
     // yprev holds Phi of every last F-point from the latest sweep
     double* yprev = ya;
     int it = 0;
+    bool use_learned = learned(opts);
+    const double fb_ratio = opts->fallback_ratio > 0.0 ? opts->fallback_ratio : 0.95;
+    const double res0 = res;
+    bool descent_seen = false;
+    int stagnant = 0;
     while (st == ATM_OK && !(res <= opts->tol)) {
         if (!isfinite(res)) {
             st = fail(ATM_ERR_DIVERGED, "non-finite residual norm after %d cycles", it);
@@ -557,9 +681,16 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
             S.fine_steps += prob->nt;
             S.n_sweeps += 1;
         }
-        ATM_TIMED(kPhCoarse, do_coarse(a, u, ycur, e, s));
-        if (st) break;
-        S.coarse_steps += window_psi_count(NT, opts->k) + (a.fas ? NT : 0);
+        if (use_learned) {
+            ATM_TIMED(kPhCoarse, do_coarse_learned(a, L, ws, prob, opts, u, ycur, e, s));
+            if (st) break;
+            S.coarse_steps += window_psi_count(NT, opts->k) + NT;
+            S.learned_cycles += 1;
+        } else {
+            ATM_TIMED(kPhCoarse, do_coarse(a, u, ycur, e, s));
+            if (st) break;
+            S.coarse_steps += window_psi_count(NT, opts->k) + (a.fas ? NT : 0);
+        }
         // correction u_{pm} += e_p and F-interpolation; ycur receives Phi of every
         // last F-point (in the mixed form its entries also start those steps)
         ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 1, u, e, ycur, s, skip, nullptr));
@@ -568,9 +699,17 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
         S.n_sweeps += 1;
         yprev = ycur;
         ++it;
+        const double prev_res = res;
         ATM_TIMED(kPhNorm, stop_norm(yprev, &res));
         if (st == ATM_OK) st = T.collect();
         if (st == ATM_OK && hist && it < hist_cap) hist[it] = res;
+        if (use_learned) {
+            // fallback: stagnation after the residual has started to decrease, or growth far beyond
+            // the transient of the truncated method
+            if (res < prev_res) descent_seen = true;
+            stagnant = (descent_seen && !(res <= fb_ratio * prev_res)) ? stagnant + 1 : 0;
+            if (stagnant >= 2 || !(res <= kLearnedGrowthLimit * res0)) use_learned = false;
+        }
     }
     if (st == ATM_OK && !isfinite(res)) st = fail(ATM_ERR_DIVERGED, "non-finite residual norm");
     double final_res = res;

@@ -181,11 +181,15 @@ __global__ __launch_bounds__(256) void l4_kernel(L4Args a)
             const float d = xv + f - yv;
             a.g4[gid] = a.two_over_n * d;
             d2 = d * d;
-        } else {
+        } else if (a.epi == EPI_WINDOW) {
             const int64_t j = map_field(a.smap, b) + 1;
             const int64_t ei = map_field(a.emap, b) * npix + p;
-            const double r = a.ysol[j * npix + p] - a.usol[(j * a.m) * npix + p];
-            a.e[ei] = a.e[ei] + (double)f + r;
+            a.e[ei] = (a.e[ei] + (double)f) + a.tau[j * npix + p];
+        } else {
+            const int64_t j = b + 1;
+            const double vj = a.usol[(j * a.m) * npix + p];
+            const double psi = a.usol[((j - 1) * a.m) * npix + p] + (double)f;
+            a.tau[j * npix + p] = (vj - psi) + (a.ysol[j * npix + p] - vj);
         }
     }
     if (a.epi == EPI_TRAIN) {
@@ -426,9 +430,43 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* params, __bf16* 
     pk[k] = (__bf16)v;
 }
 
+// FAS windows of the learned coarse solve start at w_p = v_s + r_s, s = max(0, p - k + 1), v_s = u_{sm},
+// r_0 = 0, r_s = y_s - u_{sm}; they end with e_p = w_p - v_p
+__global__ __launch_bounds__(256) void window_init_kernel(double* e, const double* y, const double* u, int64_t NT,
+                                                          int64_t n, int m, int k)
+{
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= (NT + 1) * n) return;
+    const int64_t p = gid / n, i = gid % n;
+    const int64_t s = p - k + 1 > 0 ? p - k + 1 : 0;
+    const double vs = u[(s * m) * n + i];
+    e[gid] = (s == 0) ? vs : vs + (y[s * n + i] - vs);
+}
+
+__global__ __launch_bounds__(256) void window_final_kernel(double* e, const double* u, int64_t NT, int64_t n, int m)
+{
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= (NT + 1) * n) return;
+    const int64_t p = gid / n, i = gid % n;
+    e[gid] = e[gid] - u[(p * m) * n + i];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+
+void launch_window_init(double* e, const double* y, const double* u, int64_t NT, int64_t n, int m, int k,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(window_init_kernel, dim3((unsigned)(((NT + 1) * n + 255) / 256)), dim3(256), 0, s, e, y, u, NT,
+                       n, m, k);
+}
+
+void launch_window_final(double* e, const double* u, int64_t NT, int64_t n, int m, hipStream_t s)
+{
+    hipLaunchKernelGGL(window_final_kernel, dim3((unsigned)(((NT + 1) * n + 255) / 256)), dim3(256), 0, s, e, u, NT, n,
+                       m);
+}
 
 static unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
 

@@ -54,7 +54,7 @@ __host__ __device__ inline int64_t map_field(const FieldMap& m, int64_t b)
 
 // kernel arguments (atm_cnn.hip)
 
-enum { EPI_F32 = 0, EPI_TRAIN = 1, EPI_WINDOW = 2 };
+enum { EPI_F32 = 0, EPI_TRAIN = 1, EPI_WINDOW = 2, EPI_TAU = 3 };
 
 struct L1Args {
     int64_t nb;
@@ -97,9 +97,11 @@ struct L4Args {
     float* g4;
     float* loss_part;
     float two_over_n;
-    // EPI_WINDOW: window states e (FP64, in/out) += f + (y_j - u_{jm}), j = state(b) + 1
+    // EPI_WINDOW (FAS window step): w (FP64, in/out) = (w + f) + tau_j, w = e[emap(b)], j = smap(b) + 1
+    // EPI_TAU: tau_j = (v_j - (v_{j-1} + f)) + (y_j - v_j), v_j = u_{jm}, j = b + 1
     double* e;
     FieldMap emap, smap;
+    double* tau;
     const double* ysol;
     const double* usol;
     int m;
@@ -136,6 +138,9 @@ void launch_dw4(const DWArgs& a, hipStream_t s);
 void launch_grad_reduce(const float* part, float* grad, hipStream_t s);
 void launch_loss_reduce(const float* part, int64_t n, float inv_n, float* loss, hipStream_t s);
 void launch_adam(float* params, const float* grad, float* m, float* v, int step, float lr, hipStream_t s);
+void launch_window_init(double* e, const double* y, const double* u, int64_t NT, int64_t n, int m, int k,
+                        hipStream_t s);
+void launch_window_final(double* e, const double* u, int64_t NT, int64_t n, int m, hipStream_t s);
 
 }  // namespace cnn
 }  // namespace atm

@@ -1,0 +1,174 @@
+"""The learned coarse propagator inside AT-MGRIT (coarse_form 3), through the C-ABI, against the oracles.
+
+Windows: the GPU's corrections equal the CPU oracle's FAS local solves with the learned Psi (bf16 mode)
+up to FP32-versus-FP64 summation.  A whole cycle equals the C oracle's relaxation and correction around those
+windows.  A solve converges to the FP64 fixed point (the coarse propagator only changes the rate), with
+the fallback to the plain propagator exercised.  A small network trained on the GPU is compared with
+the plain coarse step on held-out pairs and on the cycle count of the same solve.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import cnn_oracle as CO
+from tests.conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def atm():
+    import paper_2107_09596_amd as atm
+    return atm
+
+
+def dev(a, dtype=np.float64):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=dtype)).to("cuda")
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def ac_problem(nx=32, ny=16, nt=24, seed=5):
+    p = W.Problem(W.AC2D, nx=nx, ny=ny, nu=1.0, eps=0.1, tf=nt * 2e-3, nt=nt, cg_rtol=1e-14)
+    u0 = W.ac2d_fields(1, nx, ny, seed=seed, amp=0.5)[0]
+    return p, u0
+
+
+def net(seed=3, scale=1.0):
+    return (W.cnn_init(seed, last_scale=0.1) * scale).astype(np.float32)
+
+
+def y_of(orc, p, o, u):
+    NT = p.nt // o.m
+    y = np.zeros((NT + 1, p.n))
+    for j in range(1, NT + 1):
+        y[j] = orc.step(p, p.dt, u[j * o.m - 1])
+    return y
+
+
+def oracle_windows(p, o, u, y, pv):
+    NT = p.nt // o.m
+    states = np.stack([u[j * o.m] for j in range(NT + 1)]).reshape(NT + 1, p.ny, p.nx)
+    r = np.zeros((NT + 1, p.n))
+    for j in range(1, NT + 1):
+        r[j] = y[j] - u[j * o.m]
+    e = CO.learned_local_solves(pv.astype(np.float64), states, r.reshape(NT + 1, p.ny, p.nx), o.k)
+    return e.reshape(NT + 1, p.n)
+
+
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_learned_windows_match_oracle(atm, orc, k):
+    p, u0 = ac_problem()
+    o = W.Options(m=4, k=k, coarse_form=3)
+    pv = net()
+    o.cnn_params = dev(pv, np.float32)
+    u = W.initial_guess(p, u0, "random", seed=2) * 0.5
+    u[0] = u0
+    u = orc.f_relax(p, o, u)
+    y = y_of(orc, p, o, u)
+    NT = p.nt // o.m
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o))
+    e = dev(np.zeros((NT + 1, p.n)))
+    atm.atm_coarse_solve(p, o, dev(u), dev(y), e, ws)
+    ref = oracle_windows(p, o, u, y, pv)
+    got = host(e)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert err <= 1e-3, err
+
+
+def test_learned_cycle_matches_oracle(atm, orc):
+    """One FCF cycle: C oracle relaxation, oracle learned windows, C oracle correction."""
+    p, u0 = ac_problem()
+    o = W.Options(m=4, k=3, relax=1, coarse_form=3, tol=0.0, max_iter=1)
+    pv = net(4)
+    o.cnn_params = dev(pv, np.float32)
+    g = W.initial_guess(p, u0)
+    ud = dev(g)
+    status, hist, st = atm.atm_solve(p, o, ud, allow=(atm.ATM_NOT_CONVERGED,))
+    assert st["learned_cycles"] == 1
+    u = orc.f_relax(p, o, g)
+    u = orc.f_relax(p, o, orc.c_relax(p, o, u))
+    e = oracle_windows(p, o, u, y_of(orc, p, o, u), pv)
+    ref = orc.correct(p, o, u, e)
+    got = host(ud)
+    assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
+def test_learned_solve_reaches_the_fp64_fixed_point(atm, orc):
+    p, u0 = ac_problem(nt=48)
+    o = W.Options(m=4, k=4, relax=1, coarse_form=3, tol=1e-10, max_iter=80)
+    o.cnn_params = dev(net(5), np.float32)
+    ud = dev(W.initial_guess(p, u0))
+    status, hist, st = atm.atm_solve(p, o, ud)
+    assert status == atm.ATM_OK and hist[-1] <= 1e-10
+    seq = orc.sequential(p, u0)
+    assert np.linalg.norm(host(ud) - seq) <= (p.nt + 1) * 1e-10 + 1e-12 * np.linalg.norm(seq)
+    print(f"cycles {st['iterations']}, learned cycles {st['learned_cycles']}")
+
+
+def test_learned_fallback_to_plain(atm, orc):
+    """A fallback ratio that no cycle can meet hands over to the plain propagator two cycles after the
+    first decrease; the solve still converges, and agrees with the plain solve's fixed point."""
+    p, u0 = ac_problem(nt=48)
+    o = W.Options(m=4, k=4, relax=1, coarse_form=3, tol=1e-10, max_iter=80, fallback_ratio=1e-9)
+    o.cnn_params = dev(net(6), np.float32)
+    ud = dev(W.initial_guess(p, u0))
+    status, hist, st = atm.atm_solve(p, o, ud)
+    assert status == atm.ATM_OK and hist[-1] <= 1e-10
+    assert 1 <= st["learned_cycles"] < st["iterations"]
+    first_drop = next(i for i in range(1, len(hist)) if hist[i] < hist[i - 1])
+    # cycle first_drop arms the test (stagnant once), cycle first_drop + 1 is the second stagnant one
+    assert st["learned_cycles"] == min(first_drop + 1, st["iterations"])
+    plain = W.Options(m=4, k=4, relax=1, tol=1e-10, max_iter=80)
+    up = dev(W.initial_guess(p, u0))
+    atm.atm_solve(p, plain, up)
+    assert np.max(np.abs(host(ud) - host(up))) <= 1e-9
+
+
+def test_trained_network_learns_the_coarse_map(atm, orc):
+    """Train on the GPU on pairs of the fine propagator (32 x 32 periodic Allen-Cahn, lag m = 8).  On
+    held-out pairs the learned Psi must be far closer to Phi^m than the identity; its error against the
+    plain coarse step's is printed.  The learned solve reaches the plain solve's fixed point, and the
+    cycle counts of both are printed (what the trained network gains or costs)."""
+    import torch
+    from paper_2107_09596_amd import learned
+    p = W.Problem(W.AC2D, nx=32, ny=32, nu=1.0, eps=0.06, tf=256 * 1e-4, nt=256, cg_rtol=1e-12)
+    m = 8
+    fields = W.ac2d_fields(10, 32, 32, seed=21)
+    frames = learned.trajectory_frames(p, fields, stride=2)
+    per = p.nt // 2 + 1
+    ix, iy = learned.pair_indices(8, per, m // 2, 8 * (per - m // 2))
+    vx, vy = learned.pair_indices(10, per, m // 2, 10 * (per - m // 2))
+    vx, vy = vx[8 * (per - m // 2):], vy[8 * (per - m // 2):]
+    params = dev(W.cnn_init(31), np.float32)
+    orders = W.cnn_epoch_orders(32, len(ix), 50)
+    hist, secs = learned.train(params, frames, ix, iy, orders, batch=32, lr=1e-3)
+    assert hist[-1] < 0.1 * hist[0]
+    o = W.Options(m=m, k=4, relax=1, tol=1e-9, max_iter=80)
+    f_host = frames.cpu().numpy().astype(np.float64)
+    sel = np.arange(0, len(vx), 37)[:12]
+    x = f_host[vx[sel]].reshape(len(sel), -1)
+    yref = f_host[vy[sel]].reshape(len(sel), -1)
+    fout = torch.zeros((len(sel), 32, 32), dtype=torch.float32, device="cuda")
+    ws = atm.workspace(atm.atm_cnn_workspace_bytes(len(sel), 32, 32))
+    atm.atm_cnn_forward(params, dev(x.reshape(len(sel), 32, 32), np.float32), fout, ws)
+    err_learned = np.linalg.norm(x + host(fout).reshape(len(sel), -1) - yref)
+    err_plain = np.linalg.norm(np.stack([orc.coarse_step(p, o, xi) for xi in x]) - yref)
+    err_identity = np.linalg.norm(x - yref)
+    print(f"held-out error: learned {err_learned:.3e}, plain {err_plain:.3e}, identity {err_identity:.3e}; "
+          f"training {secs:.2f} s")
+    assert err_learned < 0.2 * err_identity
+    u0 = W.ac2d_fields(1, 32, 32, seed=77)[0]
+    ul = dev(W.initial_guess(p, u0))
+    o_l = W.Options(**{**o.__dict__, "coarse_form": 3, "cnn_params": params})
+    _, hl, sl = atm.atm_solve(p, o_l, ul)
+    up = dev(W.initial_guess(p, u0))
+    _, hp, sp = atm.atm_solve(p, o, up)
+    print(f"cycles: learned {sl['iterations']} ({sl['learned_cycles']} learned), plain {sp['iterations']}")
+    assert hl[-1] <= o.tol and hp[-1] <= o.tol
+    assert np.max(np.abs(host(ul) - host(up))) <= 1e-7

@@ -65,11 +65,13 @@ class Options:
     tol: float = 1e-8       # absolute 2-norm of the space-time residual
     max_iter: int = 100
     coarse_substeps: int = 1
-    coarse_form: int = 0    # 0 auto (linear for heat, FAS for Allen-Cahn), 1 linear, 2 FAS
+    coarse_form: int = 0    # 0 auto (linear for heat, FAS for Allen-Cahn), 1 linear, 2 FAS, 3 learned
     precision: int = 0      # 0 FP64 throughout, 1 FP32 fine sweeps + FP64 residual/correction
     profile: int = 0        # 1: the GPU solve times every kernel launch with HIP events
     coarse_cg_rtol: float = 0.0  # CG tolerance inside Psi; 0 = the problem's cg_rtol
     mixed_cg_rtol: float = 0.0   # precision 1: FP32 CG tolerance of the fine correction solves; 0 = 1e-6
+    fallback_ratio: float = 0.0  # coarse_form 3: stagnation ratio that switches to the plain Psi; 0 = 0.95
+    cnn_params: object = None    # coarse_form 3: device tensor of the learned propagator's parameters
 
     def n_intervals(self, nt: int) -> int:
         return nt // self.m
@@ -230,3 +232,9 @@ def ac2d_fields(n_fields: int, nx: int, ny: int, seed: int, amp: float = 0.05) -
     """n_fields i.i.d. U[-amp, amp] fields drawn in turn from one generator, [n_fields, nx*ny]."""
     rng = np.random.default_rng(seed)
     return np.stack([rng.uniform(-amp, amp, size=nx * ny) for _ in range(n_fields)])
+
+
+def cnn_epoch_orders(seed: int, n_pairs: int, epochs: int):
+    """One seeded permutation of the training pairs per epoch."""
+    rng = np.random.default_rng(seed)
+    return [rng.permutation(n_pairs) for _ in range(epochs)]
