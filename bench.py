@@ -36,6 +36,9 @@ PEAK_HBM_GBS = 8000.0
 #   per solve (initial residual r = b - M x, (b,b), (r,r), (r,z), p = z)       = 14
 FLOPS_PER_CG_ITER_POINT = 20
 FLOPS_PER_SOLVE_POINT = 14
+# HBM bytes per launch of the FP64 sweep kernel on this workload (read, written), from rocprofv3
+# FETCH_SIZE and WRITE_SIZE counters scaled by the same counters of a plain 1 GiB copy (x2.0, x1.0)
+SWEEP_TRAFFIC_BYTES = (37.4e6, 318.4e6)
 
 
 def parse():
@@ -190,7 +193,8 @@ def main():
     roofline = {
         "kernel": "sweep2d_kernel (FCF/F relaxation + correction sweeps)",
         "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-        "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None,
+        "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": sum(SWEEP_TRAFFIC_BYTES),
+        "traffic_read_write": list(SWEEP_TRAFFIC_BYTES),
         "avg_launch_ms": agg["ms_sweep"] / max(agg["n_sweeps"], 1),
         "launches": agg["n_sweeps"],
     }
