@@ -46,11 +46,17 @@ constexpr double kLearnedGrowthLimit = 1e6;  // learned coarse solve: give up be
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t header, partials, ya, yb, e, tau, pk, d1, d2, total;
+    size_t header, partials, ya, yb, e, tau, pk, d1, d2, large, total;
 };
 
 int64_t n_intervals(const atm_problem* p, const atm_options* o) { return p->nt / o->m; }
 int64_t n_space(const atm_problem* p) { return (int64_t)p->nx * p->ny; }
+
+// 2D grids beyond the on-chip strip layout run the global-scratch kernels
+bool large_grid(const atm_problem* p)
+{
+    return p->kind != ATM_HEAT1D && (p->nx > atm::kMaxSide2D || p->ny > atm::kMaxSide2D);
+}
 
 // the plain coarse propagator's form (coarse_form 3 falls back to the automatic choice)
 bool use_fas(const atm_problem* p, const atm_options* o)
@@ -88,6 +94,8 @@ Layout layout(const atm_problem* p, const atm_options* o)
     off += align_up((NT + 1) * act);
     L.d2 = off;
     off += align_up((NT + 1) * act);
+    L.large = off;
+    off += large_grid(p) ? align_up((NT + 1) * 5 * (size_t)n_space(p) * sizeof(double)) : 0;
     L.total = off;
     return L;
 }
@@ -131,8 +139,8 @@ atm_status validate(const atm_problem* p, const atm_options* o)
     if (p->kind == ATM_HEAT1D) {
         if (p->nx > 1024) return fail(ATM_ERR_UNSUPPORTED, "1D grids are limited to nx <= 1024");
     } else {
-        if (p->nx > atm::kMaxSide2D || p->ny > atm::kMaxSide2D)
-            return fail(ATM_ERR_UNSUPPORTED, "2D FP64 grids are limited to %d x %d", atm::kMaxSide2D, atm::kMaxSide2D);
+        if (p->nx > atm::kMaxSideLarge)
+            return fail(ATM_ERR_UNSUPPORTED, "2D grids are limited to %d points per row", atm::kMaxSideLarge);
         if (p->kind == ATM_AC2D && (p->nx < 3 || p->ny < 3))
             return fail(ATM_ERR_UNSUPPORTED, "periodic grids need at least 3 points per side");
     }
@@ -188,7 +196,13 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
     const double mrtol = o->mixed_cg_rtol > 0.0 ? o->mixed_cg_rtol : kMixedRtolDefault;
     a.rtol2_mixed = mrtol * mrtol;
     a.maxit = p->cg_max_iter;
-    if (!a.is1d) {
+    if (large_grid(p)) {
+        a.large = 1;
+        a.large_scratch = (double*)(base + L.large);
+        a.g.nx = p->nx;
+        a.g.ny = p->ny;
+        a.g.periodic = (p->kind == ATM_AC2D);
+    } else if (!a.is1d) {
         // strips: TX = 64 or 128 threads along x, TY = 512 / TX strips along y,
         // rows a multiple of 2 (16-byte LDS accesses of doubles), of 4 for the
         // mixed-precision sweeps (16-byte accesses of floats)
@@ -248,7 +262,9 @@ atm_status do_sweep(atm::KArgs a, const atm_problem* p, const atm_options* o, in
     a.u = u;
     a.aux = aux;
     a.y = y;
-    if (o->precision == 1)
+    if (a.large)
+        atm::launch_sweep_large(a, sweep_tasks(p, o), o->precision == 1, s);
+    else if (o->precision == 1)
         atm::launch_sweep_mixed(a, sweep_tasks(p, o), s);
     else
         atm::launch_sweep(a, sweep_tasks(p, o), s);
@@ -261,6 +277,10 @@ atm_status do_coarse(atm::KArgs a, double* u, double* y, double* e, hipStream_t 
     a.u = u;
     a.y = y;
     a.e = e;
+    if (a.large) {
+        atm::launch_coarse_large(a, s);
+        return check_launch();
+    }
     if (a.fas) {
         atm::launch_tau(a, s);
         atm_status st = check_launch();
@@ -315,7 +335,10 @@ atm_status do_step_norm(atm::KArgs a, const atm_problem* p, const atm_options* o
                         double* norm_out, atm::Header* hdr)
 {
     a.u = (double*)u;
-    atm::launch_step_residual(a, sweep_tasks(p, o), s);
+    if (a.large)
+        atm::launch_step_residual_large(a, sweep_tasks(p, o), s);
+    else
+        atm::launch_step_residual(a, sweep_tasks(p, o), s);
     return finish_norm(a, s, norm_out, hdr);
 }
 
@@ -429,11 +452,12 @@ atm_status do_coarse_learned(atm::KArgs a, const Layout& L, void* ws, const atm_
 }
 
 // Options used by atm_sequential (only the workspace header is needed).
-atm_options sequential_options()
+atm_options sequential_options(const atm_problem* p)
 {
     atm_options o;
     memset(&o, 0, sizeof(o));
-    o.m = 2;
+    // one coarse interval: the workspace holds one task's buffers
+    o.m = (p->nt >= 2 && p->nt <= INT32_MAX) ? (int32_t)p->nt : 2;
     o.k = 1;
     o.max_iter = 1;
     o.coarse_substeps = 1;
@@ -581,7 +605,7 @@ atm_status atm_sequential(const atm_problem* prob, double* u, void* ws, size_t w
 {
     if (!prob) return fail(ATM_ERR_INVALID_ARG, "null problem");
     if (prob->nt < 2) return fail(ATM_ERR_INVALID_ARG, "atm_sequential needs nt >= 2");
-    const atm_options o = sequential_options();
+    const atm_options o = sequential_options(prob);
     atm::KArgs a;
     atm_status st = make_args(prob, &o, ws, ws_bytes, a);
     if (st) return st;
@@ -589,7 +613,10 @@ atm_status atm_sequential(const atm_problem* prob, double* u, void* ws, size_t w
     a.u = u;
     hipStream_t s = as_stream(stream);
     atm::launch_reset(a.hdr, s);
-    atm::launch_sequential(a, s);
+    if (a.large)
+        atm::launch_sequential_large(a, s);
+    else
+        atm::launch_sequential(a, s);
     st = check_launch();
     if (st) return st;
     atm::Header h;
@@ -602,7 +629,7 @@ atm_status atm_sequential(const atm_problem* prob, double* u, void* ws, size_t w
 size_t atm_sequential_workspace_bytes(const atm_problem* prob)
 {
     if (!prob || prob->nt < 2) return 0;
-    const atm_options o = sequential_options();
+    const atm_options o = sequential_options(prob);
     return atm_workspace_bytes(prob, &o);
 }
 

@@ -45,6 +45,10 @@ struct KArgs {
     // sweep) and only provides y_{j+1}, copied from skip_y_src when that is not y itself
     int skip_unchanged;
     const double* skip_y_src;
+    // grids beyond the on-chip strip layout: vectors of the step solves in a per-task scratch
+    // (five n-vectors of doubles per interval or window)
+    int large;
+    double* large_scratch;
 };
 
 // ---------------------------------------------------------------------------
@@ -125,5 +129,12 @@ int64_t implicit_residual_blocks(const KArgs& a);
 void launch_sweep_mixed(const KArgs& a, int64_t n_tasks, hipStream_t s);
 void launch_implicit_residual(const KArgs& a, hipStream_t s);
 void launch_step_residual(const KArgs& a, int64_t n_tasks, hipStream_t s);
+
+// large 2D grids (atm_large.hip)
+constexpr int kMaxSideLarge = 1024;
+void launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t s);
+void launch_coarse_large(const KArgs& a, hipStream_t s);
+void launch_sequential_large(const KArgs& a, hipStream_t s);
+void launch_step_residual_large(const KArgs& a, int64_t n_tasks, hipStream_t s);
 
 }  // namespace atm

@@ -1,0 +1,417 @@
+// Kernels for 2D grids larger than the on-chip strip layout (up to 1024 points per row).
+//
+// One 1024-thread workgroup per interval or window, as for the small grids, but
+// the Krylov vectors of the step's linear solve live in a per-task scratch in
+// global memory (they stay in L2 / the MALL: 65536 points x 4 vectors is 1 MB
+// in FP32).  A thread owns column x = tid % nx of rows ty, ty + TY, ... (TY =
+// 1024 / nx rows per pass): row accesses are coalesced, and the west/east
+// neighbours of a thread are fixed for the whole kernel.  Reductions go through
+// LDS in a fixed order (bitwise reproducible).  The same step forms as the
+// small grids: FP64 direct steps (x0 = previous slice), FP32 defect-correction
+// steps with FP64 update (precision 1), FP64 coarse steps.
+#include "atm_device.hpp"
+#include "atm_kernels.hpp"
+
+namespace atm {
+
+constexpr int kBlockL = 1024;
+constexpr int kWavesL = kBlockL / 64;
+
+struct LCol {
+    int x, ty, TY;
+    bool act;
+    int xw, xe;  // west / east neighbour columns (-1: zero boundary)
+};
+
+__device__ __forceinline__ LCol make_col(const Grid2D& g)
+{
+    LCol c;
+    const int TY = kBlockL / g.nx;
+    c.TY = TY;
+    c.x = threadIdx.x % g.nx;
+    c.ty = threadIdx.x / g.nx;
+    c.act = c.ty < TY;
+    c.xw = c.x > 0 ? c.x - 1 : (g.periodic ? g.nx - 1 : -1);
+    c.xe = c.x < g.nx - 1 ? c.x + 1 : (g.periodic ? 0 : -1);
+    return c;
+}
+
+// M v at (x, y), v a full field in global memory
+template <typename T>
+__device__ __forceinline__ T stencil_g(const Grid2D& g, const StepCoef& c, const LCol& col, const T* v, int y)
+{
+    const int64_t row = (int64_t)y * g.nx;
+    const int yn = y > 0 ? y - 1 : (g.periodic ? g.ny - 1 : -1);
+    const int ys = y < g.ny - 1 ? y + 1 : (g.periodic ? 0 : -1);
+    const T cen = v[row + col.x];
+    const T w = col.xw >= 0 ? v[row + col.xw] : (T)0;
+    const T e = col.xe >= 0 ? v[row + col.xe] : (T)0;
+    const T up = yn >= 0 ? v[(int64_t)yn * g.nx + col.x] : (T)0;
+    const T dn = ys >= 0 ? v[(int64_t)ys * g.nx + col.x] : (T)0;
+    return stencil_value(c, up, cen, dn, w, e);
+}
+
+#define FOR_ROWS(col, g, y) for (int y = (col).ty; (col).act && y < (g).ny; y += (col).TY)
+
+// Jacobi-preconditioned CG (constant diagonal: plain CG on the scaled direction) for M x = b with
+// the vectors in global memory.  On entry x = x0, r = b.  Same stopping rule and failure flag as
+// the on-chip solver.  Returns the iteration count.
+template <typename T>
+__device__ int cg_large(const Grid2D& g, const StepCoef& c, const LCol& col, T* x, T* r, T* p, T* q, double* red,
+                        int& slot, double rtol2, int maxit, int* fail)
+{
+    double bb = 0.0, rr = 0.0;
+    FOR_ROWS(col, g, y)
+    {
+        // the stencil reads x at neighbours; r and p are only touched at the thread's own points
+        const int64_t i = (int64_t)y * g.nx + col.x;
+        const T b = r[i];
+        bb += (double)b * (double)b;
+        const T ri = b - stencil_g(g, c, col, x, y);
+        rr += (double)ri * (double)ri;
+        r[i] = ri;
+        p[i] = ri;
+    }
+    block_sum2(bb, rr, red, slot, kWavesL);
+    const bool bzero = (bb == 0.0);
+    const double thresh = rtol2 * bb;
+    double gamma = rr;
+    int it = 0;
+    while (!bzero && rr > thresh && it < maxit) {
+        double pq = 0.0;
+        FOR_ROWS(col, g, y)
+        {
+            const int64_t i = (int64_t)y * g.nx + col.x;
+            const T v = stencil_g(g, c, col, p, y);
+            q[i] = v;
+            pq += (double)p[i] * (double)v;
+        }
+        pq = block_sum1(pq, red, slot, kWavesL);
+        const T alpha = (T)(gamma / pq);
+        rr = 0.0;
+        FOR_ROWS(col, g, y)
+        {
+            const int64_t i = (int64_t)y * g.nx + col.x;
+            x[i] = x[i] + alpha * p[i];
+            const T ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            rr += (double)ri * (double)ri;
+        }
+        rr = block_sum1(rr, red, slot, kWavesL);
+        const T beta = (T)(rr / gamma);
+        gamma = rr;
+        FOR_ROWS(col, g, y)
+        {
+            const int64_t i = (int64_t)y * g.nx + col.x;
+            p[i] = r[i] + beta * p[i];
+        }
+        __syncthreads();
+        ++it;
+    }
+    if (!bzero && rr > thresh && threadIdx.x == 0) atomicOr(fail, 1);
+    if (bzero) {
+        FOR_ROWS(col, g, y) x[(int64_t)y * g.nx + col.x] = (T)0;
+        __syncthreads();
+    }
+    return it;
+}
+
+// per-task scratch: five n-vectors of doubles (FP32 solves use the first halves)
+struct LScratch {
+    double* base;
+    int64_t n;
+    __device__ double* vec(int64_t task, int k) const { return base + (task * 5 + k) * n; }
+};
+
+// one FP64 step v <- Phi_c(v) in place (v global), using CG vectors x, r, p, q
+__device__ __forceinline__ long long step_large64(const KArgs& a, const StepCoef& c, double rtol2, const LCol& col,
+                                                  double* v, double* x, double* r, double* p, double* q, double* red,
+                                                  int& slot)
+{
+    const Grid2D& g = a.g;
+    FOR_ROWS(col, g, y)
+    {
+        const int64_t i = (int64_t)y * g.nx + col.x;
+        x[i] = v[i];
+        r[i] = explicit_part(c, v[i]);
+    }
+    __syncthreads();
+    const int its = cg_large<double>(g, c, col, x, r, p, q, red, slot, rtol2, a.maxit, a.fail);
+    FOR_ROWS(col, g, y)
+    {
+        const int64_t i = (int64_t)y * g.nx + col.x;
+        v[i] = x[i];
+    }
+    __syncthreads();
+    return its;
+}
+
+// FP64 sweep (precision 0) over interval j; the state of the step is the slice just written to u (or y)
+__global__ __launch_bounds__(kBlockL) void sweep_large_kernel(KArgs a, LScratch sc)
+{
+    __shared__ double red[4 * kWavesL];
+    int slot = 0;
+    const int64_t j = blockIdx.x;
+    const Grid2D& g = a.g;
+    const LCol col = make_col(g);
+    const int64_t n = a.n;
+    double* v = sc.vec(j, 4);
+    bool same = true;
+    FOR_ROWS(col, g, y)
+    {
+        const int64_t i = (int64_t)y * g.nx + col.x;
+        const double c0 = sweep_start(a, j, i);
+        same = same && !(c0 != a.u[(j * a.m) * n + i]);
+        if (a.mode != 0) a.u[(j * a.m) * n + i] = c0;
+        v[i] = c0;
+    }
+    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
+    if (a.skip_unchanged && __syncthreads_and(same)) {
+        if (a.skip_y_src && j < a.NT) FOR_ROWS(col, g, y)
+            {
+                const int64_t i = (int64_t)y * g.nx + col.x;
+                a.y[(j + 1) * n + i] = a.skip_y_src[(j + 1) * n + i];
+            }
+        if (threadIdx.x == 0 && total > 0) atomicAdd(&a.hdr->skipped, (unsigned long long)total);
+        return;
+    }
+    __syncthreads();
+    long long its = 0;
+    for (int64_t t = 1; t <= total; ++t) {
+        its += step_large64(a, a.fine, a.rtol2, col, v, sc.vec(j, 0), sc.vec(j, 1), sc.vec(j, 2), sc.vec(j, 3), red,
+                            slot);
+        double* dst = (t < a.m) ? a.u + (j * a.m + t) * n : a.y + (j + 1) * n;
+        FOR_ROWS(col, g, y)
+        {
+            const int64_t i = (int64_t)y * g.nx + col.x;
+            dst[i] = v[i];
+        }
+    }
+    count_cg(a, its);
+}
+
+// FP32 defect-correction sweep (precision 1): rho = psi(v_{i-1}) - M s_i (FP64), M d = rho by FP32 CG,
+// v_i = s_i + d (FP64); starting values as in the on-chip mixed sweep
+__global__ __launch_bounds__(kBlockL) void sweep_large_mixed_kernel(KArgs a, LScratch sc)
+{
+    __shared__ double red[4 * kWavesL];
+    int slot = 0;
+    const int64_t j = blockIdx.x;
+    const Grid2D& g = a.g;
+    const LCol col = make_col(g);
+    const int64_t n = a.n;
+    float* x = reinterpret_cast<float*>(sc.vec(j, 0));
+    float* r = reinterpret_cast<float*>(sc.vec(j, 1));
+    float* p = reinterpret_cast<float*>(sc.vec(j, 2));
+    float* q = reinterpret_cast<float*>(sc.vec(j, 3));
+    double* prev = sc.vec(j, 4);
+    FOR_ROWS(col, g, y)
+    {
+        const int64_t i = (int64_t)y * g.nx + col.x;
+        const double c0 = sweep_start(a, j, i);
+        if (a.mode != 0) a.u[(j * a.m) * n + i] = c0;
+        prev[i] = c0;
+    }
+    __syncthreads();
+    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
+    long long its = 0;
+    for (int64_t t = 1; t <= total; ++t) {
+        const bool ystep = (t == a.m);
+        const double* xo;
+        if (!ystep)
+            xo = a.u + (j * a.m + t) * n;
+        else
+            xo = (a.mode == 0 ? a.u + ((j + 1) * a.m) * n : (a.mode == 1 ? a.y : a.aux) + (j + 1) * n);
+        double* dst = ystep ? a.y + (j + 1) * n : a.u + (j * a.m + t) * n;
+        FOR_ROWS(col, g, y)
+        {
+            const int64_t i = (int64_t)y * g.nx + col.x;
+            const double rho = explicit_part(a.fine, prev[i]) - stencil_g(g, a.fine, col, xo, y);
+            r[i] = (float)rho;
+            x[i] = 0.0f;
+        }
+        __syncthreads();
+        its += cg_large<float>(g, a.fine, col, x, r, p, q, red, slot, a.rtol2_mixed, a.maxit, a.fail);
+        FOR_ROWS(col, g, y)
+        {
+            const int64_t i = (int64_t)y * g.nx + col.x;
+            const double vnew = xo[i] + (double)x[i];
+            prev[i] = vnew;
+            dst[i] = vnew;
+        }
+        __syncthreads();
+    }
+    count_cg(a, its);
+}
+
+__device__ __forceinline__ long long psi_large(const KArgs& a, const LCol& col, double* w, const LScratch& sc,
+                                               int64_t task, double* red, int& slot)
+{
+    long long its = 0;
+    for (int q = 0; q < a.substeps; ++q)
+        its += step_large64(a, a.coarse, a.rtol2_coarse, col, w, sc.vec(task, 0), sc.vec(task, 1), sc.vec(task, 2),
+                            sc.vec(task, 3), red, slot);
+    return its;
+}
+
+// window p (linear or FAS form), FP64
+__global__ __launch_bounds__(kBlockL) void coarse_large_kernel(KArgs a, LScratch sc)
+{
+    __shared__ double red[4 * kWavesL];
+    int slot = 0;
+    const int64_t p = blockIdx.x;
+    const int64_t s0 = p - a.k + 1 > 0 ? p - a.k + 1 : 0;
+    const Grid2D& g = a.g;
+    const LCol col = make_col(g);
+    const int64_t n = a.n;
+    double* w = sc.vec(p, 4);
+    FOR_ROWS(col, g, y)
+    {
+        const int64_t i = (int64_t)y * g.nx + col.x;
+        const double r = cpoint_residual(a, s0, i);
+        w[i] = a.fas ? a.u[(s0 * a.m) * n + i] + r : r;
+    }
+    __syncthreads();
+    long long its = 0;
+    for (int64_t jj = s0 + 1; jj <= p; ++jj) {
+        its += psi_large(a, col, w, sc, p, red, slot);
+        FOR_ROWS(col, g, y)
+        {
+            const int64_t i = (int64_t)y * g.nx + col.x;
+            w[i] = w[i] + (a.fas ? a.tau[jj * n + i] : cpoint_residual(a, jj, i));
+        }
+        __syncthreads();
+    }
+    FOR_ROWS(col, g, y)
+    {
+        const int64_t i = (int64_t)y * g.nx + col.x;
+        a.e[p * n + i] = a.fas ? w[i] - a.u[(p * a.m) * n + i] : w[i];
+    }
+    count_cg(a, its);
+}
+
+// tau_j = (v_j - Psi(v_{j-1})) + r_j, one workgroup per j = 1..N_T
+__global__ __launch_bounds__(kBlockL) void tau_large_kernel(KArgs a, LScratch sc)
+{
+    __shared__ double red[4 * kWavesL];
+    int slot = 0;
+    const int64_t j = blockIdx.x + 1;
+    const Grid2D& g = a.g;
+    const LCol col = make_col(g);
+    const int64_t n = a.n;
+    double* w = sc.vec(j, 4);
+    FOR_ROWS(col, g, y)
+    {
+        const int64_t i = (int64_t)y * g.nx + col.x;
+        w[i] = a.u[((j - 1) * a.m) * n + i];
+    }
+    __syncthreads();
+    const long long its = psi_large(a, col, w, sc, j, red, slot);
+    FOR_ROWS(col, g, y)
+    {
+        const int64_t i = (int64_t)y * g.nx + col.x;
+        const double vj = a.u[(j * a.m) * n + i];
+        a.tau[j * n + i] = (vj - w[i]) + cpoint_residual(a, j, i);
+    }
+    count_cg(a, its);
+}
+
+// sequential stepping in one workgroup
+__global__ __launch_bounds__(kBlockL) void seq_large_kernel(KArgs a, LScratch sc)
+{
+    __shared__ double red[4 * kWavesL];
+    int slot = 0;
+    const Grid2D& g = a.g;
+    const LCol col = make_col(g);
+    const int64_t n = a.n;
+    double* v = sc.vec(0, 4);
+    FOR_ROWS(col, g, y) v[(int64_t)y * g.nx + col.x] = a.u[(int64_t)y * g.nx + col.x];
+    __syncthreads();
+    long long its = 0;
+    for (int64_t t = 1; t <= a.nt; ++t) {
+        its += step_large64(a, a.fine, a.rtol2, col, v, sc.vec(0, 0), sc.vec(0, 1), sc.vec(0, 2), sc.vec(0, 3), red,
+                            slot);
+        FOR_ROWS(col, g, y)
+        {
+            const int64_t i = (int64_t)y * g.nx + col.x;
+            a.u[t * n + i] = v[i];
+        }
+    }
+    count_cg(a, its);
+}
+
+// ||M^-1 rho||^2 per interval (the paper-form residual of the exact step), FP64
+__global__ __launch_bounds__(kBlockL) void step_residual_large_kernel(KArgs a, LScratch sc)
+{
+    __shared__ double red[4 * kWavesL];
+    int slot = 0;
+    const int64_t j = blockIdx.x;
+    const Grid2D& g = a.g;
+    const LCol col = make_col(g);
+    const int64_t n = a.n;
+    double* x = sc.vec(j, 0);
+    double* r = sc.vec(j, 1);
+    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
+    double acc = 0.0;
+    long long its = 0;
+    for (int64_t t = 1; t <= total; ++t) {
+        const int64_t i0 = j * a.m + t;
+        FOR_ROWS(col, g, y)
+        {
+            const int64_t i = (int64_t)y * g.nx + col.x;
+            r[i] = explicit_part(a.fine, a.u[(i0 - 1) * n + i]) - stencil_g(g, a.fine, col, a.u + i0 * n, y);
+            x[i] = 0.0;
+        }
+        __syncthreads();
+        its += cg_large<double>(g, a.fine, col, x, r, sc.vec(j, 2), sc.vec(j, 3), red, slot, a.rtol2, a.maxit, a.fail);
+        FOR_ROWS(col, g, y)
+        {
+            const int64_t i = (int64_t)y * g.nx + col.x;
+            acc += x[i] * x[i];
+        }
+        __syncthreads();
+    }
+    double unused = 0.0;
+    block_sum2(acc, unused, red, slot, kWavesL);
+    if (threadIdx.x == 0) a.partials[j] = acc;
+    count_cg(a, its);
+}
+
+static LScratch scratch_of(const KArgs& a) { return LScratch{a.large_scratch, a.n}; }
+
+__global__ __launch_bounds__(256) void sum_partials_large_kernel(KArgs a, int64_t count)
+{
+    __shared__ double red[2 * 2 * 4];
+    int slot = 0;
+    double acc = 0.0, unused = 0.0;
+    for (int64_t b = threadIdx.x; b < count; b += 256) acc += a.partials[b];
+    block_sum2(acc, unused, red, slot, 4);
+    if (threadIdx.x == 0) a.hdr->norm2 = acc;
+}
+
+void launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t s)
+{
+    if (mixed)
+        hipLaunchKernelGGL(sweep_large_mixed_kernel, dim3(n_tasks), dim3(kBlockL), 0, s, a, scratch_of(a));
+    else
+        hipLaunchKernelGGL(sweep_large_kernel, dim3(n_tasks), dim3(kBlockL), 0, s, a, scratch_of(a));
+}
+
+void launch_coarse_large(const KArgs& a, hipStream_t s)
+{
+    if (a.fas && a.NT >= 1) hipLaunchKernelGGL(tau_large_kernel, dim3(a.NT), dim3(kBlockL), 0, s, a, scratch_of(a));
+    hipLaunchKernelGGL(coarse_large_kernel, dim3(a.NT + 1), dim3(kBlockL), 0, s, a, scratch_of(a));
+}
+
+void launch_sequential_large(const KArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(seq_large_kernel, dim3(1), dim3(kBlockL), 0, s, a, scratch_of(a));
+}
+
+void launch_step_residual_large(const KArgs& a, int64_t n_tasks, hipStream_t s)
+{
+    hipLaunchKernelGGL(step_residual_large_kernel, dim3(n_tasks), dim3(kBlockL), 0, s, a, scratch_of(a));
+    hipLaunchKernelGGL(sum_partials_large_kernel, dim3(1), dim3(256), 0, s, a, n_tasks);
+}
+
+}  // namespace atm

@@ -80,8 +80,19 @@ def test_invalid_problem_rejected(abi, field, value, status):
     assert st == status
 
 
+def test_large_grids_take_the_scratch_layout(abi):
+    """Grids beyond 128 points per side are accepted (global-scratch kernels) with five FP64 n-vectors per
+    interval or window in the workspace."""
+    o = W.Options(m=4, k=2)
+    small = W.Problem(W.HEAT2D, nx=128, ny=128, nt=64)
+    big = W.Problem(W.HEAT2D, nx=256, ny=256, nt=64)
+    ws_small = abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(small)), ctypes.byref(abi.options(o)))
+    ws_big = abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(big)), ctypes.byref(abi.options(o)))
+    assert ws_small > 0 and ws_big >= 4 * (ws_small - 64 * 1024) + 17 * 5 * 256 * 256 * 8
+
+
 def test_unsupported_sizes(abi):
-    p = W.Problem(W.HEAT2D, nx=256, ny=256, nt=64)
+    p = W.Problem(W.HEAT2D, nx=2000, ny=16, nt=64)
     o = W.Options(m=4, k=2)
     P, O = abi.problem(p), abi.options(o)
     st = abi.lib().atm_solve(ctypes.byref(P), ctypes.byref(O), None, None, 0, None, 0, None, None)

@@ -1,0 +1,114 @@
+"""GPU parity of the large-grid kernels (more than 128 points per side: Krylov vectors in a global
+scratch) through the C-ABI, against the CPU oracle, and the 2D Allen-Cahn 256x256 workload at full size."""
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.conftest import gpu_available
+from tests.test_gpu_parity import assert_close, dev, host, small, y_of
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+LARGE = [
+    # (kind, nx, ny, nt, m, k)
+    (W.HEAT2D, 160, 136, 16, 4, 2),
+    (W.HEAT2D, 130, 257, 9, 4, 3),      # odd rows per pass, ragged tail
+    (W.AC2D, 144, 132, 12, 4, 2),
+    (W.AC2D, 256, 256, 8, 4, 2),
+]
+
+
+def ids(c):
+    return f"k{c[0]}-{c[1]}x{c[2]}-nt{c[3]}-m{c[4]}-k{c[5]}"
+
+
+@pytest.fixture(scope="module")
+def atm():
+    import paper_2107_09596_amd as atm
+    return atm
+
+
+@pytest.mark.parametrize("case", LARGE, ids=ids)
+def test_large_sweeps_match_oracle(atm, orc, case):
+    kind, nx, ny, nt, m, k = case
+    p, u0 = small(kind, nx, ny, nt)
+    o = W.Options(m=m, k=k, relax=1)
+    NT = p.nt // m
+    u = W.initial_guess(p, u0, "random", seed=3) * (0.3 if kind == W.AC2D else 1.0)
+    u[0] = u0
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o))
+    ud, yd = dev(u), dev(np.zeros((NT + 1, p.n)))
+    atm.atm_sweep(p, o, 0, ud, None, yd, ws)
+    u_f = orc.f_relax(p, o, u)
+    assert_close(host(ud), u_f, what="F-relaxation u")
+    assert_close(host(yd)[1:], y_of(orc, p, o, u_f)[1:], what="F-relaxation y")
+    y2 = dev(np.zeros((NT + 1, p.n)))
+    atm.atm_sweep(p, o, 2, ud, yd, y2, ws)
+    u_cf = orc.f_relax(p, o, orc.c_relax(p, o, u_f))
+    assert_close(host(ud), u_cf, what="CF-relaxation u")
+    e = np.random.default_rng(11).standard_normal((NT + 1, p.n)) * 0.1
+    e[0] = 0.0
+    y3 = dev(np.zeros((NT + 1, p.n)))
+    atm.atm_sweep(p, o, 1, ud, dev(e), y3, ws)
+    u_c = orc.correct(p, o, u_cf, e)
+    assert_close(host(ud), u_c, what="correction u")
+    assert_close(host(y3)[1:], y_of(orc, p, o, u_c)[1:], what="correction y")
+
+
+@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("case", LARGE, ids=ids)
+def test_large_coarse_solves_match_oracle(atm, orc, case, form):
+    kind, nx, ny, nt, m, k = case
+    p, u0 = small(kind, nx, ny, nt)
+    o = W.Options(m=m, k=k, coarse_form=form, coarse_substeps=2 if kind == W.AC2D else 1)
+    NT = p.nt // m
+    g = W.initial_guess(p, u0, "random", seed=4) * 0.5
+    g[0] = u0
+    u = orc.f_relax(p, o, g)
+    y = y_of(orc, p, o, u)
+    rc = np.zeros((NT + 1, p.n))
+    vc = np.stack([u[j * m] for j in range(NT + 1)])
+    for j in range(1, NT + 1):
+        rc[j] = y[j] - u[j * m]
+    ref = orc.local_solves(p, o, rc, vc)
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o))
+    e = dev(np.zeros((NT + 1, p.n)))
+    atm.atm_coarse_solve(p, o, dev(u), dev(y), e, ws)
+    assert_close(host(e), ref, what=f"coarse form {form}")
+
+
+@pytest.mark.parametrize("case", LARGE[::2], ids=ids)
+def test_large_sequential_and_solve(atm, orc, case):
+    kind, nx, ny, nt, m, k = case
+    p, u0 = small(kind, nx, ny, nt)
+    seq = orc.sequential(p, u0)
+    us = np.zeros((p.nt + 1, p.n))
+    us[0] = u0
+    usd = dev(us)
+    atm.atm_sequential(p, usd)
+    assert_close(host(usd), seq, what="sequential")
+    for precision in (0, 1):
+        o = W.Options(m=m, k=k, relax=1, tol=1e-11, precision=precision, coarse_substeps=2 if kind == W.AC2D else 1)
+        ud = dev(W.initial_guess(p, u0))
+        status, hist, st = atm.atm_solve(p, o, ud)
+        assert status == atm.ATM_OK and st["final_residual"] <= 1e-11
+        assert np.linalg.norm(host(ud) - seq) <= (p.nt + 1) * 1e-11 + 1e-12 * np.linalg.norm(seq)
+
+
+def test_ac256_full_size(atm, orc):
+    """2D Allen-Cahn 256x256 periodic, eps 0.02, dt 1e-5, Nt 8192, m 64, k 13, FCF, 4 coarse substeps, FP32 fine
+    solves: converge to 1e-8 on the GPU; the stopping norm equals the oracle's implicit residual of the result,
+    and the first 64 steps match the oracle's sequential stepping."""
+    p, o, u0 = W.config("c3")
+    ud = dev(W.initial_guess(p, u0))
+    status, hist, st = atm.atm_solve(p, o, ud)
+    print(f"cycles {st['iterations']}, residual {hist[-1]:.3e}, final {st['final_residual']:.3e}, "
+          f"{st['ms_total']:.0f} ms")
+    assert status == atm.ATM_OK and hist[-1] <= o.tol and st["final_residual"] <= hist[-1] * (1 + 1e-9)
+    u = host(ud)
+    rho = float(np.linalg.norm(orc.implicit_residual(p, u)))
+    assert abs(hist[-1] - rho) <= 1e-9 * rho + 1e-12
+    q = W.Problem(**{**p.__dict__, "nt": 64, "tf": p.t0 + 64 * p.dt, "cg_rtol": 1e-14})
+    ref = orc.sequential(q, u0)
+    err = float(np.max(np.abs(u[:65] - ref)))
+    assert err <= 1e-8, f"max error against the FP64 oracle on the first 64 steps: {err:.2e}"
