@@ -225,6 +225,52 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
                      size_t ws_bytes, double* hist, int32_t hist_cap, atm_stats* stats, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Batched solves: many independent instances (ATM_HEAT1D with nx <= 512, 2D
+ * kinds up to 128 x 128, plain coarse propagator) advance together, one cycle
+ * per replay of a captured hipGraph.  Each phase of a cycle is one launch per
+ * instance class (1D heat, 2D heat, 2D Allen-Cahn; concurrent graph branches)
+ * over a table of (instance, interval / window) tasks; an autotuner picks the
+ * task order (as given or longest first) and the strip tile (one 32-row tile
+ * for all 2D instances, or each instance's own) by timing the window phase,
+ * and can keep its choice in a cache file.  Every instance runs Alg. 1 as
+ * atm_solve does with its own options (precision 1 for the FP32-fine form);
+ * an instance stops when its own test is met, its later tasks are skipped.
+ * The stopping decision is taken on the device; the host reads the instance
+ * states every check_every cycles.
+ * ------------------------------------------------------------------------ */
+typedef struct atm_batch atm_batch;
+
+/* Workspace bytes for the batch (0 if an instance is invalid or unsupported). */
+size_t atm_batch_workspace_bytes(int32_t n, const atm_problem* probs, const atm_options* opts);
+
+/* Plan a batch of n instances: probs[i], opts[i] (host arrays), u[i] (host array of device
+   pointers, each [nt_i+1][n_i] FP64 holding u_0 and the initial guess, updated in place by
+   atm_batch_run).  ws (device) of atm_batch_workspace_bytes() bytes, 256-byte aligned, owned by
+   the caller and used by the plan until atm_batch_destroy.  tune_cache (host path, nullable): a
+   text file where the autotuner's choice is read and appended, keyed by the instances' shapes.
+   The plan holds HIP streams, events and a graph (host-side objects); it allocates no device
+   memory. */
+atm_status atm_batch_create(atm_batch** out, int32_t n, const atm_problem* probs, const atm_options* opts,
+                            double* const* u, void* ws, size_t ws_bytes, const char* tune_cache);
+
+/* Solve every instance: the initial F-relaxation, the autotuner on the first call, then cycles
+   until every instance has stopped.  use_graph 1 replays one captured cycle (captured on the
+   first call), 0 enqueues the same launches directly.  status[i], stats[i] (host, nullable; the
+   ms_* fields hold the batch's time), hist (host, nullable, [n][hist_cap], up to 256 norms per
+   instance) are filled.  ms_solve (host, nullable): wall time without the autotuner; ms_tune
+   (host, nullable): the autotuner's time (0 once tuned).  Work is ordered after `stream` and
+   `stream` waits for the batch.  Returns OK if every instance converged, NOT_CONVERGED if one
+   reached max_iter, else the first error status of an instance. */
+atm_status atm_batch_run(atm_batch* b, int32_t use_graph, int32_t check_every, atm_status* status, atm_stats* stats,
+                         double* hist, int32_t hist_cap, double* ms_solve, double* ms_tune, void* stream);
+
+/* The autotuner's choice: *order 0 as given / 1 longest task first; *tiles 0 one 32-row strip
+   tile / 1 each instance's own.  Returns 1 once tuned. */
+int32_t atm_batch_tuning(const atm_batch* b, int32_t* order, int32_t* tiles);
+
+void atm_batch_destroy(atm_batch* b);
+
+/* ------------------------------------------------------------------------
  * Learned coarse propagator (section 2.1 lets the coarse propagator be any
  * approximation of Phi over a coarse step).  Psi(u) = u + f(u), f a four-layer
  * 3x3 convolutional network on the periodic h x w grid: 1 -> 32 -> 32 -> 32 -> 1

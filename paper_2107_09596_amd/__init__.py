@@ -18,7 +18,7 @@ __all__ = [
     "atm_num_intervals", "atm_window_start", "atm_workspace_bytes", "atm_sweep", "atm_coarse_solve",
     "atm_residual_norm", "atm_implicit_residual_norm", "atm_step_residual_norm", "atm_sequential", "atm_sequential_workspace_bytes", "atm_solve", "atm_status_string",
     "atm_last_error", "workspace", "atm_cnn_param_count", "atm_cnn_workspace_bytes", "atm_cnn_forward",
-    "atm_cnn_jvp", "atm_cnn_gradients", "atm_cnn_train_step", "AtmError", "ATM_OK", "ATM_NOT_CONVERGED", "ATM_ERR_INVALID_ARG",
+    "atm_cnn_jvp", "atm_cnn_gradients", "atm_cnn_train_step", "Batch", "AtmError", "ATM_OK", "ATM_NOT_CONVERGED", "ATM_ERR_INVALID_ARG",
     "ATM_ERR_UNSUPPORTED", "ATM_ERR_DEVICE", "ATM_ERR_DIVERGED", "ATM_ERR_INNER_SOLVE", "ATM_ERR_WORKSPACE",
     "ATM_HEAT1D", "ATM_HEAT2D", "ATM_AC2D",
 ]
@@ -216,3 +216,61 @@ def atm_cnn_train_step(params, adam_m, adam_v, step: int, lr: float, frames, idx
                                        _ptr(loss_out, _f32(), "loss_out"), _ptr(ws, None, "ws"), _nbytes(ws),
                                        _stream(stream))
     _abi.check(st, "atm_cnn_train_step")
+
+
+# ---------------------------------------------------------------------------
+# batched solves: marshalling only
+# ---------------------------------------------------------------------------
+
+class Batch:
+    """A planned batch (atm_batch_create); run() solves every instance in place."""
+
+    def __init__(self, probs, opts, us, tune_cache=None):
+        n = len(probs)
+        if not (len(opts) == len(us) == n):
+            raise ValueError("probs, opts and us must have the same length")
+        self.n = n
+        self._P = (_abi.AtmProblem * n)(*[_abi.problem(p) for p in probs])
+        self._O = (_abi.AtmOptions * n)(*[_abi.options(o) for o in opts])
+        self._us = list(us)  # keep the tensors alive
+        ptrs = (ctypes.c_void_p * n)(*[_ptr(u, _f64(), "u").value for u in us])
+        nbytes = int(_abi.lib().atm_batch_workspace_bytes(n, self._P, self._O))
+        if nbytes == 0:
+            raise AtmError(ATM_ERR_INVALID_ARG, "atm_batch_workspace_bytes")
+        self.ws = workspace(nbytes, device=us[0].device)
+        self._h = ctypes.c_void_p(0)
+        cache = tune_cache.encode() if tune_cache else None
+        st = _abi.lib().atm_batch_create(ctypes.byref(self._h), n, self._P, self._O, ptrs, _ptr(self.ws, None, "ws"),
+                                         nbytes, cache)
+        _abi.check(st, "atm_batch_create")
+
+    def run(self, use_graph=True, check_every=4, hist_cap=64, stream=None, allow=(ATM_OK, ATM_NOT_CONVERGED)):
+        """Returns (overall status, per-instance statuses, stats dicts, histories, ms_solve, ms_tune)."""
+        n = self.n
+        status = (ctypes.c_int32 * n)()
+        stats = (_abi.AtmStats * n)()
+        hist = (ctypes.c_double * (n * hist_cap))()
+        ms = ctypes.c_double(0.0)
+        mt = ctypes.c_double(0.0)
+        st = _abi.lib().atm_batch_run(self._h, int(bool(use_graph)), int(check_every), status, stats, hist,
+                                      int(hist_cap), ctypes.byref(ms), ctypes.byref(mt), _stream(stream))
+        _abi.check(st, "atm_batch_run", allow=allow)
+        sts = [{name: getattr(stats[i], name) for name, _ in _abi.AtmStats._fields_} for i in range(n)]
+        hs = [[hist[i * hist_cap + j] for j in range(min(sts[i]["iterations"] + 1, hist_cap))] for i in range(n)]
+        return st, [status[i] for i in range(n)], sts, hs, ms.value, mt.value
+
+    def tuning(self):
+        o, t = ctypes.c_int32(0), ctypes.c_int32(0)
+        tuned = _abi.lib().atm_batch_tuning(self._h, ctypes.byref(o), ctypes.byref(t))
+        return bool(tuned), o.value, t.value
+
+    def close(self):
+        if self._h:
+            _abi.lib().atm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -85,6 +85,13 @@ SIGNATURES = {
     "atm_cnn_train_step": (ctypes.c_int32, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_float, _vp, ctypes.c_int32,
                                             _ip, _ip, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                                             ctypes.c_size_t, _vp]),
+    "atm_batch_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32, _P, _O]),
+    "atm_batch_create": (ctypes.c_int32, [ctypes.POINTER(_vp), ctypes.c_int32, _P, _O, ctypes.POINTER(_vp), _vp,
+                                          ctypes.c_size_t, ctypes.c_char_p]),
+    "atm_batch_run": (ctypes.c_int32, [_vp, ctypes.c_int32, ctypes.c_int32, _ip, _S, _dp, ctypes.c_int32, _dp, _dp,
+                                       _vp]),
+    "atm_batch_tuning": (ctypes.c_int32, [_vp, _ip, _ip]),
+    "atm_batch_destroy": (None, [_vp]),
     "atm_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "atm_last_error": (ctypes.c_char_p, []),
 }

@@ -5,10 +5,13 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <string>
+#include <vector>
 
 #include "../../include/atm.h"
+#include "atm_batch.hpp"
 #include "atm_cnn.hpp"
 #include "atm_kernels.hpp"
 
@@ -523,6 +526,442 @@ int64_t window_psi_count(int64_t NT, int64_t k)
 
 }  // namespace
 
+
+// ---------------------------------------------------------------------------
+// batched solves
+// ---------------------------------------------------------------------------
+
+namespace batchhost {
+
+using atm::batch::Body;
+using atm::batch::InstCtl;
+using atm::batch::Task;
+
+constexpr int kHistCap = 256;  // stopping norms kept per instance
+constexpr int kNormChunks = 64;  // implicit-residual pieces of a 2D instance (at most nt)
+enum { PH_S0, PH_N0, PH_NF0, PH_S2, PH_TAU, PH_C, PH_S1, PH_N, PH_NF, NPH };
+enum { CLS_1D, CLS_2D, CLS_2DP, NCLS };
+
+struct Inst {
+    atm_problem p;
+    atm_options o;
+    double* u;  // the instance's iterate (device)
+    Layout L;
+    size_t off;  // of the instance's region in the workspace
+    int cls, S, nchunk;
+    bool mixed;
+};
+
+struct Group {
+    int phase, cls, S;
+    Body body;
+    size_t task_off;
+    int ntasks;
+};
+
+size_t control_bytes(int n, size_t ntasks)
+{
+    return align_up((size_t)NPH * n * sizeof(atm::KArgs)) + align_up(n * sizeof(InstCtl)) + align_up(n * sizeof(int)) +
+           align_up((size_t)n * kHistCap * sizeof(double)) + align_up(ntasks * sizeof(Task));
+}
+
+int phase_tasks(const Inst& in, int ph)
+{
+    const int64_t NT = n_intervals(&in.p, &in.o);
+    const bool fas = use_fas(&in.p, &in.o) && in.cls != CLS_1D;
+    switch (ph) {
+        case PH_S0:
+        case PH_S1: return (int)(NT + 1);
+        case PH_S2: return in.o.relax == 1 ? (int)(NT + 1) : 0;
+        case PH_TAU: return fas ? (int)NT : 0;
+        case PH_C: return (int)(NT + 1);
+        case PH_N0:
+        case PH_N: return in.mixed ? in.nchunk : (int)NT;
+        default: return 1;  // sums
+    }
+}
+
+Body phase_body(const Inst& in, int ph)
+{
+    using namespace atm::batch;
+    switch (ph) {
+        case PH_S0:
+        case PH_S2:
+        case PH_S1: return in.cls == CLS_1D ? kSweep1D : (in.mixed ? kSweep2D : kSweep2D64);
+        case PH_TAU: return kTau2D;
+        case PH_C: return in.cls == CLS_1D ? kCoarse1D : kCoarse2D;
+        case PH_N0:
+        case PH_N: return in.mixed ? kNormI : kNormC;
+        default: return in.mixed ? kNormFinalI : kNormFinalC;
+    }
+}
+
+// relative cost of one task, for longest-first ordering
+double task_cost(const Inst& in, int ph, int idx)
+{
+    const double n = (double)in.p.nx * in.p.ny;
+    switch (ph) {
+        case PH_S0:
+        case PH_S2:
+        case PH_S1: return n * in.o.m;
+        case PH_TAU: return n * in.o.coarse_substeps;
+        case PH_C: return n * in.o.coarse_substeps * std::min(idx, in.o.k - 1);
+        case PH_N0:
+        case PH_N: return in.mixed ? n * (double)in.p.nt / in.nchunk : n;
+        default: return 1.0;
+    }
+}
+
+}  // namespace batchhost
+
+struct atm_batch {
+    int n = 0;
+    std::vector<batchhost::Inst> inst;
+    char* ws = nullptr;
+    size_t ctl_off = 0;
+    atm::KArgs* args_dev = nullptr;  // [NPH][n]
+    batchhost::InstCtl* ctl_dev = nullptr;
+    int* nchunk_dev = nullptr;
+    double* hist_dev = nullptr;
+    batchhost::Task* tasks_dev = nullptr;
+    size_t max_tasks = 0;
+    std::vector<batchhost::Group> groups;
+    int order = 1, tiles = 1;  // chosen by the autotuner: 0 natural / 1 longest first; 0 one tile / 1 per instance
+    bool tuned = false;
+    std::string cache;
+    hipStream_t main = nullptr;
+    hipStream_t br[batchhost::NCLS] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[batchhost::NCLS] = {nullptr, nullptr, nullptr};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double ms_tune = 0.0;
+    ~atm_batch()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (int c = 0; c < batchhost::NCLS; ++c) {
+            if (br[c]) (void)hipStreamDestroy(br[c]);
+            if (join[c]) (void)hipEventDestroy(join[c]);
+        }
+        if (fork) (void)hipEventDestroy(fork);
+        if (main) (void)hipStreamDestroy(main);
+    }
+};
+
+namespace batchhost {
+
+size_t count_tasks(const std::vector<Inst>& v)
+{
+    size_t t = 0;
+    for (const Inst& in : v)
+        for (int ph = 0; ph < NPH; ++ph) t += phase_tasks(in, ph);
+    return t;
+}
+
+atm_status describe(int32_t n, const atm_problem* probs, const atm_options* opts, std::vector<Inst>& v, size_t& total)
+{
+    if (n < 1) return fail(ATM_ERR_INVALID_ARG, "a batch needs at least one instance");
+    if (!probs || !opts) return fail(ATM_ERR_INVALID_ARG, "null problems or options");
+    v.resize(n);
+    size_t off = 0;
+    for (int i = 0; i < n; ++i) {
+        Inst& in = v[i];
+        in.p = probs[i];
+        in.o = opts[i];
+        atm_status st = validate(&in.p, &in.o);
+        if (st) return fail(st, "instance %d: %s", i, g_last_error.c_str());
+        if (learned(&in.o)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches use the plain coarse propagator", i);
+        if (large_grid(&in.p)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take grids up to 128 x 128", i);
+        in.cls = in.p.kind == ATM_HEAT1D ? CLS_1D : (in.p.kind == ATM_AC2D ? CLS_2DP : CLS_2D);
+        if (in.cls == CLS_1D && in.p.nx > 512)
+            return fail(ATM_ERR_UNSUPPORTED, "instance %d: 1D batch instances take nx <= 512", i);
+        in.mixed = in.o.precision == 1;
+        in.nchunk = (int)std::min<int64_t>(kNormChunks, in.p.nt);
+        in.L = layout(&in.p, &in.o);
+        in.off = off;
+        off += align_up(in.L.total);
+    }
+    total = off + control_bytes(n, count_tasks(v));
+    return ATM_OK;
+}
+
+// the instance's arguments for each phase
+atm_status phase_args(atm_batch* B, int i, atm::KArgs* out)
+{
+    Inst& in = B->inst[i];
+    atm::KArgs a;
+    atm_status st = make_args(&in.p, &in.o, B->ws + in.off, in.L.total, a);
+    if (st) return st;
+    char* base = B->ws + in.off;
+    double* ya = (double*)(base + in.L.ya);
+    double* yb = (double*)(base + in.L.yb);
+    double* e = (double*)(base + in.L.e);
+    const bool fcf = in.o.relax == 1;
+    const bool skip = !in.mixed;
+    in.S = a.s_tmpl;
+    for (int ph = 0; ph < NPH; ++ph) {
+        atm::KArgs k = a;
+        k.u = in.u;
+        k.cg_count = &k.hdr->cg_fine;
+        switch (ph) {
+            case PH_S0:
+                k.mode = 0;
+                k.y = ya;
+                break;
+            case PH_S2:
+                k.mode = 2;
+                k.aux = ya;
+                k.y = yb;
+                k.skip_unchanged = skip;
+                k.skip_y_src = ya;
+                break;
+            case PH_TAU:
+            case PH_C:
+                k.y = fcf ? yb : ya;
+                k.e = e;
+                k.cg_count = &k.hdr->cg_coarse;
+                break;
+            case PH_S1:
+                k.mode = 1;
+                k.aux = e;
+                k.y = ya;
+                k.skip_unchanged = skip;
+                k.skip_y_src = fcf ? yb : nullptr;
+                break;
+            default:
+                k.y = ya;
+                break;
+        }
+        out[ph * B->n + i] = k;
+    }
+    return ATM_OK;
+}
+
+// task tables (host), grouped by phase, class and strip template, in the chosen order
+void build_tables(atm_batch* B, std::vector<Task>& tasks)
+{
+    tasks.clear();
+    B->groups.clear();
+    for (int ph = 0; ph < NPH; ++ph)
+        for (int cls = 0; cls < NCLS; ++cls) {
+            // distinct (body, S) of this phase and class
+            std::vector<std::pair<int, int>> keys;
+            for (int i = 0; i < B->n; ++i) {
+                const Inst& in = B->inst[i];
+                if (in.cls != cls || phase_tasks(in, ph) == 0) continue;
+                const int S = (cls == CLS_1D) ? 0 : (B->tiles ? in.S : 32);
+                const std::pair<int, int> key((int)phase_body(in, ph), S);
+                if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
+            }
+            for (const auto& key : keys) {
+                std::vector<std::pair<double, Task>> g;
+                for (int i = 0; i < B->n; ++i) {
+                    const Inst& in = B->inst[i];
+                    if (in.cls != cls || (int)phase_body(in, ph) != key.first) continue;
+                    const int S = (cls == CLS_1D) ? 0 : (B->tiles ? in.S : 32);
+                    if (S != key.second) continue;
+                    const int nt = phase_tasks(in, ph);
+                    const int first = (ph == PH_TAU || ((ph == PH_N0 || ph == PH_N) && !in.mixed)) ? 1 : 0;
+                    for (int t = 0; t < nt; ++t) g.push_back({task_cost(in, ph, t + first), Task{i, t + first}});
+                }
+                if (B->order == 1)
+                    std::stable_sort(g.begin(), g.end(),
+                                     [](const std::pair<double, Task>& x, const std::pair<double, Task>& y) {
+                                         return x.first > y.first;
+                                     });
+                Group gr;
+                gr.phase = ph;
+                gr.cls = cls;
+                gr.S = key.second;
+                gr.body = (Body)key.first;
+                gr.task_off = tasks.size();
+                gr.ntasks = (int)g.size();
+                for (const auto& x : g) tasks.push_back(x.second);
+                B->groups.push_back(gr);
+            }
+        }
+}
+
+atm_status upload_tables(atm_batch* B)
+{
+    std::vector<Task> tasks;
+    build_tables(B, tasks);
+    if (tasks.size() > B->max_tasks) return fail(ATM_ERR_WORKSPACE, "batch task tables exceed their reserved space");
+    ATM_HIP(hipMemcpyAsync(B->tasks_dev, tasks.data(), tasks.size() * sizeof(Task), hipMemcpyHostToDevice, B->main));
+    ATM_HIP(hipStreamSynchronize(B->main));
+    return ATM_OK;
+}
+
+// launches of the given phases, one branch stream per class, joined on the main stream
+atm_status enqueue_phases(atm_batch* B, const int* phases, int nphases)
+{
+    ATM_HIP(hipEventRecord(B->fork, B->main));
+    for (int c = 0; c < NCLS; ++c) ATM_HIP(hipStreamWaitEvent(B->br[c], B->fork, 0));
+    for (int q = 0; q < nphases; ++q)
+        for (const Group& g : B->groups) {
+            if (g.phase != phases[q]) continue;
+            atm::batch::Launch l;
+            l.args = B->args_dev + (size_t)g.phase * B->n;
+            l.tasks = B->tasks_dev + g.task_off;
+            l.ntasks = g.ntasks;
+            l.ctl = B->ctl_dev;
+            l.nchunk = B->nchunk_dev;
+            const Inst& any = B->inst[0];
+            (void)any;
+            const bool per = g.cls == CLS_2DP;
+            atm::batch::launch_tasks(g.body, g.S, per, l, B->br[g.cls]);
+        }
+    for (int c = 0; c < NCLS; ++c) {
+        ATM_HIP(hipEventRecord(B->join[c], B->br[c]));
+        ATM_HIP(hipStreamWaitEvent(B->main, B->join[c], 0));
+    }
+    return check_launch();
+}
+
+atm_status enqueue_cycle(atm_batch* B)
+{
+    static const int phases[] = {PH_S2, PH_TAU, PH_C, PH_S1, PH_N, PH_NF};
+    atm_status st = enqueue_phases(B, phases, 6);
+    if (st) return st;
+    atm::batch::launch_decide(B->args_dev + (size_t)PH_NF * B->n, B->ctl_dev, B->hist_dev, kHistCap, B->n, false,
+                              B->main);
+    return check_launch();
+}
+
+uint64_t batch_key(const atm_batch* B)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t v) {
+        for (int q = 0; q < 8; ++q) {
+            h ^= (uint64_t)((v >> (8 * q)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    for (const Inst& in : B->inst) {
+        mix(in.p.kind);
+        mix(in.p.nx);
+        mix(in.p.ny);
+        mix(in.p.nt);
+        mix(in.o.m);
+        mix(in.o.k);
+        mix(in.o.relax);
+        mix(in.o.precision);
+        mix(in.o.coarse_substeps);
+    }
+    return h;
+}
+
+bool cache_lookup(const atm_batch* B, uint64_t key, int& order, int& tiles)
+{
+    if (B->cache.empty()) return false;
+    FILE* f = fopen(B->cache.c_str(), "r");
+    if (!f) return false;
+    unsigned long long k;
+    int o, t;
+    double ms;
+    bool found = false;
+    while (fscanf(f, "%llx %d %d %lf", &k, &o, &t, &ms) == 4)
+        if (k == key) {
+            order = o;
+            tiles = t;
+            found = true;
+        }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const atm_batch* B, uint64_t key, int order, int tiles, double ms)
+{
+    if (B->cache.empty()) return;
+    FILE* f = fopen(B->cache.c_str(), "a");
+    if (!f) return;
+    fprintf(f, "%016llx %d %d %.4f\n", (unsigned long long)key, order, tiles, ms);
+    fclose(f);
+}
+
+// Autotuner: time the window phase (it reads the iterate and writes only corrections, so it can be
+// repeated) for every (task order, strip tile) choice; keep the fastest.  Needs the initial phase done.
+atm_status autotune(atm_batch* B)
+{
+    const uint64_t key = batch_key(B);
+    int order = 1, tiles = 1;
+    if (cache_lookup(B, key, order, tiles)) {
+        B->order = order;
+        B->tiles = tiles;
+        return upload_tables(B);
+    }
+    // the window phase reading the initial sweep's y (ya), so that its inputs are defined
+    std::vector<atm::KArgs> probe(B->n);
+    for (int i = 0; i < B->n; ++i) {
+        ATM_HIP(hipMemcpy(&probe[i], B->args_dev + (size_t)PH_C * B->n + i, sizeof(atm::KArgs), hipMemcpyDeviceToHost));
+        atm::KArgs k = probe[i];
+        k.y = (double*)(B->ws + B->inst[i].off + B->inst[i].L.ya);
+        probe[i] = k;
+    }
+    // a spare KArgs row: PH_TAU's slot is rewritten below and restored after
+    std::vector<atm::KArgs> saved(B->n);
+    ATM_HIP(hipMemcpy(saved.data(), B->args_dev + (size_t)PH_TAU * B->n, B->n * sizeof(atm::KArgs),
+                      hipMemcpyDeviceToHost));
+    // the timed windows add CG counts (and on stale data possibly a failure flag) to the headers:
+    // keep the headers as the initial phase left them
+    std::vector<atm::Header> hdrs(B->n);
+    for (int i = 0; i < B->n; ++i)
+        ATM_HIP(hipMemcpy(&hdrs[i], saved[i].hdr, sizeof(atm::Header), hipMemcpyDeviceToHost));
+    hipEvent_t e0, e1;
+    ATM_HIP(hipEventCreate(&e0));
+    ATM_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    int best_o = 1, best_t = 1;
+    const auto t_start = std::chrono::steady_clock::now();
+    for (int o = 0; o < 2; ++o)
+        for (int t = 0; t < 2; ++t) {
+            B->order = o;
+            B->tiles = t;
+            atm_status st = upload_tables(B);
+            if (st) return st;
+            // run the window groups with the probe arguments placed in the PH_C row
+            ATM_HIP(hipMemcpy(B->args_dev + (size_t)PH_C * B->n, probe.data(), B->n * sizeof(atm::KArgs),
+                              hipMemcpyHostToDevice));
+            double ms_min = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {
+                static const int phases[] = {PH_C};
+                ATM_HIP(hipEventRecord(e0, B->main));
+                if ((st = enqueue_phases(B, phases, 1))) return st;
+                ATM_HIP(hipEventRecord(e1, B->main));
+                ATM_HIP(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                ATM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                ms_min = std::min(ms_min, (double)ms);
+            }
+            if (ms_min < best) {
+                best = ms_min;
+                best_o = o;
+                best_t = t;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // restore the cycle's window arguments
+    std::vector<atm::KArgs> all((size_t)NPH * B->n);  // phase_args fills [phase][instance]
+    for (int i = 0; i < B->n; ++i) {
+        atm_status st = phase_args(B, i, all.data());
+        if (st) return st;
+    }
+    ATM_HIP(hipMemcpy(B->args_dev + (size_t)PH_C * B->n, all.data() + (size_t)PH_C * B->n, B->n * sizeof(atm::KArgs),
+                      hipMemcpyHostToDevice));
+    ATM_HIP(hipMemcpy(B->args_dev + (size_t)PH_TAU * B->n, saved.data(), B->n * sizeof(atm::KArgs),
+                      hipMemcpyHostToDevice));
+    for (int i = 0; i < B->n; ++i)
+        ATM_HIP(hipMemcpy(saved[i].hdr, &hdrs[i], sizeof(atm::Header), hipMemcpyHostToDevice));
+    B->order = best_o;
+    B->tiles = best_t;
+    B->ms_tune = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    cache_store(B, key, best_o, best_t, best);
+    return upload_tables(B);
+}
+
+}  // namespace batchhost
+
 extern "C" {
 
 int64_t atm_num_intervals(const atm_problem* prob, const atm_options* opts)
@@ -682,8 +1121,9 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
     ATM_TIMED(kPhNorm, stop_norm(ya, &res));
     if (st == ATM_OK) st = T.collect();
     if (st == ATM_OK && hist && hist_cap > 0) hist[0] = res;
-    // yprev holds Phi of every last F-point from the latest sweep
-    double* yprev = ya;
+    // Buffers: the initial and every correction sweep write y_a (Phi of every last F-point); the
+    // CF sweep reads y_a and writes y_b, which the windows then read.  The FP32 form's correction
+    // sweep starts its y-steps from y_a's previous contents (y is in/out there).
     int it = 0;
     bool use_learned = learned(opts);
     const double fb_ratio = opts->fallback_ratio > 0.0 ? opts->fallback_ratio : 0.95;
@@ -699,11 +1139,11 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
             st = ATM_NOT_CONVERGED;
             break;
         }
-        double* ycur = yprev;
+        double* ycur = ya;
         if (opts->relax == 1) {
-            // CF: C-points take Phi of their preceding F-point (held in yprev), then F-relax
-            ycur = (yprev == ya) ? yb : ya;
-            ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 2, u, yprev, ycur, s, skip, yprev));
+            // CF: C-points take Phi of their preceding F-point (held in y_a), then F-relax
+            ycur = yb;
+            ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 2, u, ya, yb, s, skip, ya));
             if (st) break;
             S.fine_steps += prob->nt;
             S.n_sweeps += 1;
@@ -718,16 +1158,15 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
             if (st) break;
             S.coarse_steps += window_psi_count(NT, opts->k) + (a.fas ? NT : 0);
         }
-        // correction u_{pm} += e_p and F-interpolation; ycur receives Phi of every
-        // last F-point (in the mixed form its entries also start those steps)
-        ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 1, u, e, ycur, s, skip, nullptr));
+        // correction u_{pm} += e_p and F-interpolation; y_a receives Phi of every last F-point
+        // (intervals that are skipped take theirs from y_b, the CF sweep's output)
+        ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 1, u, e, ya, s, skip, opts->relax == 1 ? yb : nullptr));
         if (st) break;
         S.fine_steps += prob->nt;
         S.n_sweeps += 1;
-        yprev = ycur;
         ++it;
         const double prev_res = res;
-        ATM_TIMED(kPhNorm, stop_norm(yprev, &res));
+        ATM_TIMED(kPhNorm, stop_norm(ya, &res));
         if (st == ATM_OK) st = T.collect();
         if (st == ATM_OK && hist && it < hist_cap) hist[it] = res;
         if (use_learned) {
@@ -738,6 +1177,7 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
             if (stagnant >= 2 || !(res <= kLearnedGrowthLimit * res0)) use_learned = false;
         }
     }
+#undef ATM_TIMED
     if (st == ATM_OK && !isfinite(res)) st = fail(ATM_ERR_DIVERGED, "non-finite residual norm");
     double final_res = res;
     if (mixed && (st == ATM_OK || st == ATM_NOT_CONVERGED)) {
@@ -748,7 +1188,6 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
             st2 = T.collect();
         if (st2 != ATM_OK) st = st2;
     }
-#undef ATM_TIMED
     S.iterations = it;
     S.final_residual = final_res;
     S.cg_fine = (int64_t)h.cg_fine;
@@ -762,6 +1201,195 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
     if (stats) *stats = S;
     return st;
 }
+
+size_t atm_batch_workspace_bytes(int32_t n, const atm_problem* probs, const atm_options* opts)
+{
+    std::vector<batchhost::Inst> v;
+    size_t total = 0;
+    if (batchhost::describe(n, probs, opts, v, total) != ATM_OK) return 0;
+    return total;
+}
+
+atm_status atm_batch_create(atm_batch** out, int32_t n, const atm_problem* probs, const atm_options* opts,
+                            double* const* u, void* ws, size_t ws_bytes, const char* tune_cache)
+{
+    using namespace batchhost;
+    if (!out) return fail(ATM_ERR_INVALID_ARG, "null out");
+    *out = nullptr;
+    std::vector<Inst> v;
+    size_t total = 0;
+    atm_status st = describe(n, probs, opts, v, total);
+    if (st) return st;
+    if (!u) return fail(ATM_ERR_INVALID_ARG, "null iterate array");
+    for (int i = 0; i < n; ++i)
+        if (!u[i]) return fail(ATM_ERR_INVALID_ARG, "instance %d: null iterate", i);
+    if (!ws) return fail(ATM_ERR_INVALID_ARG, "null workspace");
+    if (((uintptr_t)ws) % kAlign) return fail(ATM_ERR_INVALID_ARG, "workspace must be %zu-byte aligned", kAlign);
+    if (ws_bytes < total)
+        return fail(ATM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, total);
+    atm_batch* B = new atm_batch;
+    B->n = n;
+    B->inst = std::move(v);
+    B->ws = (char*)ws;
+    B->cache = tune_cache ? tune_cache : "";
+    for (int i = 0; i < n; ++i) B->inst[i].u = u[i];
+    size_t off = B->inst.back().off + align_up(B->inst.back().L.total);
+    B->args_dev = (atm::KArgs*)(B->ws + off);
+    off += align_up((size_t)NPH * n * sizeof(atm::KArgs));
+    B->ctl_dev = (InstCtl*)(B->ws + off);
+    off += align_up(n * sizeof(InstCtl));
+    B->nchunk_dev = (int*)(B->ws + off);
+    off += align_up(n * sizeof(int));
+    B->hist_dev = (double*)(B->ws + off);
+    off += align_up((size_t)n * kHistCap * sizeof(double));
+    B->tasks_dev = (Task*)(B->ws + off);
+    B->max_tasks = count_tasks(B->inst);
+    auto cleanup = [&](atm_status s2) {
+        delete B;
+        return s2;
+    };
+    hipError_t he = hipStreamCreateWithFlags(&B->main, hipStreamNonBlocking);
+    for (int c = 0; c < NCLS && he == hipSuccess; ++c) he = hipStreamCreateWithFlags(&B->br[c], hipStreamNonBlocking);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&B->fork, hipEventDisableTiming);
+    for (int c = 0; c < NCLS && he == hipSuccess; ++c) he = hipEventCreateWithFlags(&B->join[c], hipEventDisableTiming);
+    if (he != hipSuccess) return cleanup(fail(ATM_ERR_DEVICE, "batch streams: %s", hipGetErrorString(he)));
+    std::vector<atm::KArgs> args((size_t)NPH * n);
+    std::vector<InstCtl> ctl(n);
+    std::vector<int> nchunk(n);
+    for (int i = 0; i < n; ++i) {
+        if ((st = phase_args(B, i, args.data()))) return cleanup(st);
+        ctl[i].active = 1;
+        ctl[i].it = 0;
+        ctl[i].status = ATM_NOT_CONVERGED;
+        ctl[i].max_iter = B->inst[i].o.max_iter;
+        ctl[i].tol = B->inst[i].o.tol;
+        ctl[i].res = 0.0;
+        nchunk[i] = B->inst[i].nchunk;
+    }
+    he = hipMemcpy(B->args_dev, args.data(), args.size() * sizeof(atm::KArgs), hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(B->ctl_dev, ctl.data(), n * sizeof(InstCtl), hipMemcpyHostToDevice);
+    if (he == hipSuccess) he = hipMemcpy(B->nchunk_dev, nchunk.data(), n * sizeof(int), hipMemcpyHostToDevice);
+    if (he != hipSuccess) return cleanup(fail(ATM_ERR_DEVICE, "batch arguments: %s", hipGetErrorString(he)));
+    if ((st = upload_tables(B))) return cleanup(st);
+    *out = B;
+    return ATM_OK;
+}
+
+atm_status atm_batch_run(atm_batch* B, int32_t use_graph, int32_t check_every, atm_status* status, atm_stats* stats,
+                         double* hist, int32_t hist_cap, double* ms_solve, double* ms_tune, void* stream)
+{
+    using namespace batchhost;
+    if (!B) return fail(ATM_ERR_INVALID_ARG, "null batch");
+    if (check_every < 1) return fail(ATM_ERR_INVALID_ARG, "check_every must be >= 1");
+    if (hist_cap < 0) return fail(ATM_ERR_INVALID_ARG, "hist_cap must be >= 0");
+    atm_status st;
+    hipStream_t caller = as_stream(stream);
+    ATM_HIP(hipEventRecord(B->fork, caller));
+    ATM_HIP(hipStreamWaitEvent(B->main, B->fork, 0));
+    const auto t0 = std::chrono::steady_clock::now();
+    // initial F-relaxation, its residual and the first decision
+    atm::batch::launch_reset_headers(B->args_dev, B->ctl_dev, B->n, B->main);
+    {
+        static const int phases[] = {PH_S0, PH_N0, PH_NF0};
+        if ((st = enqueue_phases(B, phases, 3))) return st;
+        atm::batch::launch_decide(B->args_dev + (size_t)PH_NF0 * B->n, B->ctl_dev, B->hist_dev, kHistCap, B->n, true,
+                                  B->main);
+        if ((st = check_launch())) return st;
+    }
+    double tune = 0.0;
+    if (!B->tuned) {
+        ATM_HIP(hipStreamSynchronize(B->main));
+        if ((st = autotune(B))) return st;
+        B->tuned = true;
+        tune = B->ms_tune;
+    }
+    if (use_graph && !B->exec) {
+        ATM_HIP(hipStreamBeginCapture(B->main, hipStreamCaptureModeGlobal));
+        st = enqueue_cycle(B);
+        hipGraph_t g = nullptr;
+        hipError_t he = hipStreamEndCapture(B->main, &g);
+        if (st) return st;
+        if (he != hipSuccess) return fail(ATM_ERR_DEVICE, "graph capture: %s", hipGetErrorString(he));
+        B->graph = g;
+        ATM_HIP(hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0));
+    }
+    int max_cycles = 0;
+    for (const Inst& in : B->inst) max_cycles = std::max(max_cycles, in.o.max_iter);
+    std::vector<InstCtl> ctl(B->n);
+    int cycles = 0;
+    for (;;) {
+        ATM_HIP(hipMemcpyAsync(ctl.data(), B->ctl_dev, B->n * sizeof(InstCtl), hipMemcpyDeviceToHost, B->main));
+        ATM_HIP(hipStreamSynchronize(B->main));
+        bool any = false;
+        for (const InstCtl& c : ctl) any = any || c.active;
+        if (!any || cycles >= max_cycles) break;
+        for (int r = 0; r < check_every && cycles < max_cycles; ++r, ++cycles) {
+            if (use_graph) {
+                ATM_HIP(hipGraphLaunch(B->exec, B->main));
+            } else if ((st = enqueue_cycle(B))) {
+                return st;
+            }
+        }
+    }
+    // paper-form residual of the precision-1 instances' results
+    std::vector<double> final_res(B->n);
+    for (int i = 0; i < B->n; ++i) {
+        final_res[i] = ctl[i].res;
+        const Inst& in = B->inst[i];
+        if (in.mixed && (ctl[i].status == ATM_OK || ctl[i].status == ATM_NOT_CONVERGED)) {
+            atm::KArgs a;
+            if ((st = make_args(&in.p, &in.o, B->ws + in.off, in.L.total, a))) return st;
+            atm::Header h;
+            if ((st = do_step_norm(a, &in.p, &in.o, in.u, B->main, &final_res[i], &h))) return st;
+        }
+    }
+    ATM_HIP(hipStreamSynchronize(B->main));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() - tune;
+    atm_status worst = ATM_OK;
+    for (int i = 0; i < B->n; ++i) {
+        const Inst& in = B->inst[i];
+        if (status) status[i] = ctl[i].status;
+        if (ctl[i].status < 0) worst = ctl[i].status;
+        else if (ctl[i].status == ATM_NOT_CONVERGED && worst == ATM_OK) worst = ATM_NOT_CONVERGED;
+        if (stats) {
+            atm::Header h;
+            ATM_HIP(hipMemcpy(&h, B->ws + in.off + in.L.header, sizeof(h), hipMemcpyDeviceToHost));
+            atm_stats S;
+            memset(&S, 0, sizeof(S));
+            S.iterations = ctl[i].it;
+            S.final_residual = final_res[i];
+            S.ms_total = ms;
+            S.cg_fine = (int64_t)h.cg_fine;
+            S.cg_coarse = (int64_t)h.cg_coarse;
+            S.fine_steps_skipped = (int64_t)h.skipped;
+            const int sweeps = 1 + ctl[i].it * (in.o.relax == 1 ? 2 : 1);
+            S.n_sweeps = sweeps;
+            S.fine_steps = (int64_t)sweeps * in.p.nt - S.fine_steps_skipped;
+            S.coarse_steps = (int64_t)ctl[i].it * window_psi_count(n_intervals(&in.p, &in.o), in.o.k);
+            stats[i] = S;
+        }
+        if (hist && hist_cap > 0) {
+            const int cnt = std::min(std::min(hist_cap, kHistCap), ctl[i].it + 1);
+            ATM_HIP(hipMemcpy(hist + (size_t)i * hist_cap, B->hist_dev + (size_t)i * kHistCap, cnt * sizeof(double),
+                              hipMemcpyDeviceToHost));
+        }
+    }
+    if (ms_solve) *ms_solve = ms;
+    if (ms_tune) *ms_tune = tune;
+    ATM_HIP(hipEventRecord(B->fork, B->main));
+    ATM_HIP(hipStreamWaitEvent(caller, B->fork, 0));
+    return worst;
+}
+
+int32_t atm_batch_tuning(const atm_batch* B, int32_t* order, int32_t* tiles)
+{
+    if (!B) return 0;
+    if (order) *order = B->order;
+    if (tiles) *tiles = B->tiles;
+    return B->tuned ? 1 : 0;
+}
+
+void atm_batch_destroy(atm_batch* B) { delete B; }
 
 const char* atm_status_string(atm_status status)
 {

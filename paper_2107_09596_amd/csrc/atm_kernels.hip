@@ -7,6 +7,7 @@
 // fine point written once per sweep and never re-read by the sweep.
 #include "atm_device.hpp"
 #include "atm_kernels.hpp"
+#include "atm_bodies.hpp"
 
 namespace atm {
 
@@ -17,64 +18,13 @@ namespace atm {
 __global__ __launch_bounds__(1024) void sweep1d_kernel(KArgs a)
 {
     __shared__ double lds[3 * 1024];
-    const int64_t j = blockIdx.x;
-    const int i = threadIdx.x;
-    const bool act = i < a.nx;
-    Pcr1D f;
-    pcr_setup(f, a.nx, a.fine.cx, lds);
-    double x = 0.0;
-    bool same = true;
-    if (act) {
-        x = sweep_start(a, j, i);
-        same = !(x != a.u[(j * a.m) * a.n + i]);
-        if (a.mode != 0) a.u[(j * a.m) * a.n + i] = x;
-    }
-    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
-    if (a.skip_unchanged && __syncthreads_and(same)) {
-        skip_interval(a, j, total, i, 0, act ? 1 : 0);
-        return;
-    }
-    for (int64_t t = 1; t <= total; ++t) {
-        x = pcr_solve(f, a.nx, x, lds);
-        if (act) {
-            if (t < a.m)
-                a.u[(j * a.m + t) * a.n + i] = x;
-            else
-                a.y[(j + 1) * a.n + i] = x;
-        }
-    }
-}
-
-// Psi: s substeps with the coarse factors
-__device__ __forceinline__ double psi1d(const KArgs& a, const Pcr1D& fc, double x, double* lds)
-{
-    for (int q = 0; q < a.substeps; ++q) x = pcr_solve(fc, a.nx, x, lds);
-    return x;
+    sweep1d_body(a, blockIdx.x, lds);
 }
 
 __global__ __launch_bounds__(1024) void coarse1d_kernel(KArgs a)
 {
     __shared__ double lds[3 * 1024];
-    const int64_t p = blockIdx.x;
-    const int i = threadIdx.x;
-    const bool act = i < a.nx;
-    Pcr1D fc;
-    pcr_setup(fc, a.nx, a.coarse.cx, lds);
-    const int64_t s = p - a.k + 1 > 0 ? p - a.k + 1 : 0;
-    double w = 0.0, vs = 0.0;
-    if (act) {
-        if (a.fas) {
-            vs = a.u[(s * a.m) * a.n + i];
-            w = vs + cpoint_residual(a, s, i);
-        } else {
-            w = cpoint_residual(a, s, i);
-        }
-    }
-    for (int64_t jj = s + 1; jj <= p; ++jj) {
-        w = psi1d(a, fc, w, lds);
-        if (act) w = w + (a.fas ? a.tau[jj * a.n + i] : cpoint_residual(a, jj, i));
-    }
-    if (act) a.e[p * a.n + i] = a.fas ? w - a.u[(p * a.m) * a.n + i] : w;
+    coarse1d_body(a, blockIdx.x, lds);
 }
 
 // tau_j = (v_j - Psi(v_{j-1})) + r_j, j = 1..N_T (FAS right-hand side, shared by all windows)
@@ -113,65 +63,12 @@ __global__ __launch_bounds__(1024) void seq1d_kernel(KArgs a)
 // ---------------------------------------------------------------------------
 
 
-template <int S>
-struct Strip2DState {
-    double x[S], r[S], q[S];
-};
-
-// One integrator step of size given by coefficients c, on the strip state.
-template <int S, bool EX, bool PER>
-__device__ __forceinline__ int step2d(const KArgs& a, const StepCoef& c, double rtol2, const Strip& st,
-                                      Strip2DState<S>& v, double* lp, double* red, int& slot)
-{
-#pragma unroll
-    for (int s = 0; s < S; ++s) v.r[s] = explicit_part(c, v.x[s]);
-    return cg2d<double, S, EX, PER, true>(a.g, c, st, v.x, v.r, v.q, lp, red, slot, rtol2, a.maxit, a.fail);
-}
-
 template <int S, bool EX, bool PER>
 __global__ __launch_bounds__(kBlock2D) void sweep2d_kernel(KArgs a)
 {
     __shared__ __align__(16) double lp[Lds2D<double>::size];
     __shared__ double red[4 * kWaves2D];
-    int slot = 0;
-    const int64_t j = blockIdx.x;
-    const Strip st = make_strip<double>(a.g);
-    lds_clear(lp);
-    Strip2DState<S> v;
-    const int nx = a.g.nx;
-    bool same = true;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        v.x[s] = 0.0;
-        if (row_ok<EX, S>(st, s)) {
-            const int64_t idx = (int64_t)(st.gbase + s * nx);
-            v.x[s] = sweep_start(a, j, idx);
-            const double old = a.u[(j * a.m) * a.n + idx];
-            same = same && !(v.x[s] != old);
-            if (a.mode != 0) a.u[(j * a.m) * a.n + idx] = v.x[s];
-        }
-    }
-    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
-    if (a.skip_unchanged && __syncthreads_and(same)) {
-        skip_interval(a, j, total, st.gbase, nx, EX ? S : st.nr);
-        return;
-    }
-    long long its = 0;
-    for (int64_t t = 1; t <= total; ++t) {
-        its += step2d<S, EX, PER>(a, a.fine, a.rtol2, st, v, lp, red, slot);
-        double* dst = (t < a.m) ? a.u + (j * a.m + t) * a.n : a.y + (j + 1) * a.n;
-        strip_store<S, EX>(dst, st, nx, v.x);
-    }
-    count_cg(a, its);
-}
-
-template <int S, bool EX, bool PER>
-__device__ __forceinline__ long long psi2d(const KArgs& a, const Strip& st, Strip2DState<S>& v, double* lp,
-                                           double* red, int& slot)
-{
-    long long its = 0;
-    for (int q = 0; q < a.substeps; ++q) its += step2d<S, EX, PER>(a, a.coarse, a.rtol2_coarse, st, v, lp, red, slot);
-    return its;
+    sweep2d_body<S, EX, PER>(a, blockIdx.x, lp, red);
 }
 
 template <int S, bool EX, bool PER>
@@ -179,40 +76,7 @@ __global__ __launch_bounds__(kBlock2D) void coarse2d_kernel(KArgs a)
 {
     __shared__ __align__(16) double lp[Lds2D<double>::size];
     __shared__ double red[4 * kWaves2D];
-    int slot = 0;
-    const int64_t p = blockIdx.x;
-    const int64_t s0 = p - a.k + 1 > 0 ? p - a.k + 1 : 0;
-    const Strip st = make_strip<double>(a.g);
-    lds_clear(lp);
-    const int nx = a.g.nx;
-    Strip2DState<S> v;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        v.x[s] = 0.0;
-        if (row_ok<EX, S>(st, s)) {
-            const int64_t idx = (int64_t)(st.gbase + s * nx);
-            const double r = cpoint_residual(a, s0, idx);
-            v.x[s] = a.fas ? a.u[(s0 * a.m) * a.n + idx] + r : r;
-        }
-    }
-    long long its = 0;
-    for (int64_t jj = s0 + 1; jj <= p; ++jj) {
-        its += psi2d<S, EX, PER>(a, st, v, lp, red, slot);
-        const int64_t off = opaque_off(st.gbase);
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-            if (row_ok<EX, S>(st, s)) {
-                const int64_t idx = off + (int64_t)s * nx;
-                v.x[s] = v.x[s] + (a.fas ? a.tau[jj * a.n + idx] : cpoint_residual(a, jj, idx));
-            }
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-        if (row_ok<EX, S>(st, s)) {
-            const int64_t idx = (int64_t)(st.gbase + s * nx);
-            a.e[p * a.n + idx] = a.fas ? v.x[s] - a.u[(p * a.m) * a.n + idx] : v.x[s];
-        }
-    count_cg(a, its);
+    coarse2d_body<S, EX, PER>(a, blockIdx.x, lp, red);
 }
 
 template <int S, bool EX, bool PER>
@@ -220,26 +84,7 @@ __global__ __launch_bounds__(kBlock2D) void tau2d_kernel(KArgs a)
 {
     __shared__ __align__(16) double lp[Lds2D<double>::size];
     __shared__ double red[4 * kWaves2D];
-    int slot = 0;
-    const int64_t j = blockIdx.x + 1;
-    const Strip st = make_strip<double>(a.g);
-    lds_clear(lp);
-    const int nx = a.g.nx;
-    Strip2DState<S> v;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        v.x[s] = 0.0;
-        if (row_ok<EX, S>(st, s)) v.x[s] = a.u[((j - 1) * a.m) * a.n + (int64_t)(st.gbase + s * nx)];
-    }
-    long long its = psi2d<S, EX, PER>(a, st, v, lp, red, slot);
-#pragma unroll
-    for (int s = 0; s < S; ++s)
-        if (row_ok<EX, S>(st, s)) {
-            const int64_t idx = (int64_t)(st.gbase + s * nx);
-            const double vj = a.u[(j * a.m) * a.n + idx];
-            a.tau[j * a.n + idx] = (vj - v.x[s]) + cpoint_residual(a, j, idx);
-        }
-    count_cg(a, its);
+    tau2d_body<S, EX, PER>(a, blockIdx.x + 1, lp, red);  // windows 1..N_T
 }
 
 template <int S, bool EX, bool PER>

@@ -19,102 +19,16 @@
 // of Phi(u_{i-1}) - u_i.
 #include "atm_device.hpp"
 #include "atm_kernels.hpp"
+#include "atm_bodies.hpp"
 
 namespace atm {
 
-// Zero the halo cells of an LDS vector of a Dirichlet grid: columns -1 and nx
-// (rows -1..ny) and rows -1 and ny of every column.  The mixed sweep reuses one
-// LDS block for an FP64 and an FP32 vector, so each layout's halo is cleared
-// before that layout is written.
-template <typename T>
-__device__ __forceinline__ void lds_clear_halo(const Grid2D& g, T* lp)
-{
-    constexpr int H = Lds2D<T>::H, V = Lds2D<T>::V;
-    const int rows = g.ny + 2;
-    for (int i = threadIdx.x; i < 2 * rows; i += blockDim.x) {
-        const int col = (i < rows) ? 0 : g.nx + 1;
-        const int y = (i < rows) ? i : i - rows;
-        lp[col * H + V - 1 + y] = (T)0;
-    }
-    for (int i = threadIdx.x; i < 2 * g.nx; i += blockDim.x) {
-        const int col = 1 + (i >> 1);
-        lp[col * H + ((i & 1) ? V + g.ny : V - 1)] = (T)0;
-    }
-}
-
-// Mixed sweep over interval j (one workgroup per task, modes as in the FP64
-// sweep).  The starting value of the step that produces y_{j+1} = Phi(u_{jm+m-1})
-// is, by mode: 0 the C-point u_{(j+1)m}; 1 y_{j+1} on entry (y is in/out);
-// 2 aux_{j+1} (the Phi values of the previous sweep).
 template <int S, bool EX, bool PER>
 __global__ __launch_bounds__(kBlock2D) void sweep2d_mixed_kernel(KArgs a)
 {
-    // one LDS block holds the FP64 staging of u_i^old for the defect and then
-    // the FP32 search direction of the CG (the FP32 layout is the smaller one)
     __shared__ __align__(16) double ldsd[Lds2D<double>::size];
     __shared__ double red[4 * kWaves2D];
-    static_assert(Lds2D<float>::size * sizeof(float) <= Lds2D<double>::size * sizeof(double), "LDS alias");
-    float* lpf = reinterpret_cast<float*>(ldsd);
-    int slot = 0;
-    const int64_t j = blockIdx.x;
-    const Strip sd = make_strip<double>(a.g);
-    const Strip sf = make_strip<float>(a.g);
-    const int nx = a.g.nx;
-    lds_clear(ldsd);
-    double up[S];
-    float x[S], r[S], q[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        up[s] = 0.0;
-        if (row_ok<EX, S>(sd, s)) {
-            const int64_t idx = (int64_t)(sd.gbase + s * nx);
-            up[s] = sweep_start(a, j, idx);
-            if (a.mode != 0) a.u[(j * a.m) * a.n + idx] = up[s];
-        }
-    }
-    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
-    long long its = 0;
-    for (int64_t t = 1; t <= total; ++t) {
-        const bool ystep = (t == a.m);
-        const double* xo;
-        if (!ystep)
-            xo = a.u + (j * a.m + t) * a.n;
-        else
-            xo = (a.mode == 0 ? a.u + ((j + 1) * a.m) * a.n : (a.mode == 1 ? a.y : a.aux) + (j + 1) * a.n);
-        double* dst = ystep ? a.y + (j + 1) * a.n : a.u + (j * a.m + t) * a.n;
-        // defect of the starting value in FP64, rounded to FP32 as the CG right-hand side
-        if (!PER) lds_clear_halo(a.g, ldsd);
-        {
-            const int64_t off = opaque_off(sd.gbase);
-            lds_put_fn<double, S, EX, PER, false>(a.g, sd, ldsd,
-                                                  [&](int s, double) { return xo[off + (int64_t)s * nx]; });
-        }
-        __syncthreads();
-        if (EX || sd.nr > 0)
-            strip_stencil<double, S, EX>(sd, ldsd, [&](int s, double u_, double c_, double d_, double w_, double e_) {
-                const double res = explicit_part(a.fine, up[s]) - stencil_value(a.fine, u_, c_, d_, w_, e_);
-                r[s] = (float)res;
-                return res;
-            });
-        __syncthreads();  // every read of the FP64 staging precedes its reuse as FP32
-        if (!PER) lds_clear_halo(a.g, lpf);
-#pragma unroll
-        for (int s = 0; s < S; ++s) x[s] = 0.0f;
-        its += cg2d<float, S, EX, PER, true>(a.g, a.fine, sf, x, r, q, lpf, red, slot, a.rtol2_mixed, a.maxit,
-                                             a.fail);
-        {
-            const int64_t off = opaque_off(sd.gbase);
-#pragma unroll
-            for (int s = 0; s < S; ++s)
-                if (row_ok<EX, S>(sd, s)) {
-                    const double v = xo[off + (int64_t)s * nx] + (double)x[s];
-                    up[s] = v;
-                    dst[off + (int64_t)s * nx] = v;
-                }
-        }
-        __syncthreads();  // the next step's FP64 staging overwrites the FP32 direction
-    }
-    count_cg(a, its);
+    sweep2d_mixed_body<S, EX, PER>(a, blockIdx.x, ldsd, red);
 }
 
 // FP64 implicit residual |rho|^2 = sum_i |psi(u_{i-1}) - M u_i|^2, i = 1..nt.

@@ -238,3 +238,43 @@ def cnn_epoch_orders(seed: int, n_pairs: int, epochs: int):
     """One seeded permutation of the training pairs per epoch."""
     rng = np.random.default_rng(seed)
     return [rng.permutation(n_pairs) for _ in range(epochs)]
+
+
+def batch_config(count: int = 256, seed: int = 4):
+    """The batched workload: `count` independent instances drawn from default_rng(seed).
+
+    kind uniform in {1D heat, 2D heat, 2D Allen-Cahn}; m uniform in {8, 16, 32};
+    Nt = m * floor(U{512..8192} / m); 1D: nx in U{63..511} (the 1D heat recipe, nu 1,
+    t in [0, 1], FP64); 2D heat: n x n, n in U{32..128} (the 2D heat recipe, nu 0.1,
+    t in [0, 1]); 2D Allen-Cahn: periodic n x n, eps 0.02, dt 1e-5, u0 ~ U[-0.05, 0.05],
+    coarse substeps s = ceil(m dt / eps^2 / 0.4) so that each coarse step keeps
+    dT / (s eps^2) <= 0.4.  2D instances run the FP32-fine / FP64-residual form.
+    Instance b draws its initial field with seed 1000 + b.  FCF, tol 1e-8,
+    k = max(2, ceil(0.1 (N_T + 1))).  Returns a list of (Problem, Options, u0).
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        kind = (HEAT1D, HEAT2D, AC2D)[int(rng.integers(0, 3))]
+        m = (8, 16, 32)[int(rng.integers(0, 3))]
+        nt = m * (int(rng.integers(512, 8193)) // m)
+        k = default_k(nt // m)
+        if kind == HEAT1D:
+            nx = int(rng.integers(63, 512))
+            p = Problem(HEAT1D, nx=nx, ny=1, length=1.0, nu=1.0, t0=0.0, tf=1.0, nt=nt)
+            u0, _ = heat1d_u0(nx, seed=1000 + b)
+            o = Options(m=m, k=k, relax=1, tol=1e-8)
+        elif kind == HEAT2D:
+            n = int(rng.integers(32, 129))
+            p = Problem(HEAT2D, nx=n, ny=n, length=1.0, nu=0.1, t0=0.0, tf=1.0, nt=nt, cg_rtol=1e-12)
+            u0, _ = heat2d_u0(n, n, seed=1000 + b)
+            o = Options(m=m, k=k, relax=1, tol=1e-8, precision=1)
+        else:
+            n = int(rng.integers(32, 129))
+            dt, eps = 1e-5, 0.02
+            p = Problem(AC2D, nx=n, ny=n, length=1.0, nu=1.0, eps=eps, t0=0.0, tf=nt * dt, nt=nt, cg_rtol=1e-12)
+            u0 = ac2d_u0(n, n, seed=1000 + b)
+            s = max(1, math.ceil(m * dt / eps ** 2 / 0.4))
+            o = Options(m=m, k=k, relax=1, tol=1e-8, precision=1, coarse_substeps=s)
+        out.append((p, o, u0))
+    return out
