@@ -7,9 +7,10 @@ interpolation, residual norm and stopping test) of the 2D heat workload
 FP64) from the zero initial guess, with all inputs resident in HBM.  The
 initial guess is restored by a device copy at the start of each step (inside
 the timed region).  The CG inside the coarse propagator Psi runs to relative
-tolerance 1e-6 (--coarse-rtol; Psi only approximates Phi^m, the fixed point
-does not depend on it, and the cycle count equals the strict solve's); one
-extra solve with Psi at the fine tolerance is reported as "strict_coarse".
+tolerance 1e-3 (--coarse-rtol; Psi only approximates Phi^m, the fixed point
+does not depend on it, and the cycle count equals the strict solve's: 12 at
+1e-2, 1e-3, 1e-4, 1e-6 and 1e-12); one extra solve with Psi at the fine
+tolerance is reported as "strict_coarse".
 
 Prints one JSON line (see the keys below).  --gpus > 1 is refused: this build
 runs on a single GPU.
@@ -47,11 +48,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--coarse-rtol", type=float, default=1e-6,
+    ap.add_argument("--coarse-rtol", type=float, default=1e-3,
                     help="CG tolerance inside the coarse propagator (0 = the fine cg_rtol)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-coarse-propagator comparison")
     ap.add_argument("--learned-epochs", type=int, default=15)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve leg")
+    ap.add_argument("--batch-count", type=int, default=256,
+                    help="instances of the seeded batched workload (the first N of the 256)")
+    ap.add_argument("--batch-sample", type=int, default=16,
+                    help="instances solved one at a time (every k-th) for the batched-vs-individual comparison")
     ap.add_argument("--cpu-steps", type=int, default=4096,
                     help="time steps of the oracle's sequential stepping timed for cpu_baseline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -136,9 +142,78 @@ def learned_leg(epochs):
     res["training"] = {"pairs": len(ix), "epochs": epochs, "batch": 64, "lr": 1e-3, "seconds": train_s,
                        "data_generation_seconds": gen_s, "final_train_loss": losses[-1], "validation_loss": val_loss}
     res["workload"] = ("2D Allen-Cahn 128x128 periodic, eps=0.03, dt=1e-5, Nt=4096, m=32, k=%d, FCF, precision %d, "
-                       "tol 1e-8; learned = CNN 1-32-32-32-1 (BF16, FP32 accumulate) linearised in the windows" %
+                       "tol 1e-8; learned = CNN 1-32-32-32-1 (BF16, FP32 accumulate) as Psi in the FAS windows, plain Psi as fallback" %
                        (o.k, o.precision))
     return res
+
+
+def batch_leg(count, sample):
+    """Batched solves: the first `count` instances of the seeded batch (1D heat, 2D heat and 2D Allen-Cahn of
+    uneven sizes; FP32-fine / FP64-residual for 2D), one captured cycle per graph replay.  The first run
+    includes the autotuner; the second is timed.  A sample of the instances is also solved one at a time
+    with atm_solve and the sum extrapolated to the whole batch."""
+    import numpy as np
+    import torch
+
+    import paper_2107_09596_amd as atm
+    import workloads as W
+
+    items = W.batch_config(256)[:count]
+    dev = torch.device("cuda:0")
+    guess = []
+    for p, _, u0 in items:
+        g = torch.zeros((p.nt + 1, p.n), dtype=torch.float64, device=dev)
+        g[0].copy_(torch.from_numpy(np.ascontiguousarray(u0, dtype=np.float64).reshape(-1)))
+        guess.append(g)
+    us = [g.clone() for g in guess]
+    b = atm.Batch([p for p, _, _ in items], [o for _, o, _ in items], us)
+    runs = []
+    for r in range(2):
+        for u, g in zip(us, guess):
+            u.copy_(g)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        st, status, stats, hists, ms, mt = b.run(use_graph=True, check_every=4)
+        torch.cuda.synchronize()
+        runs.append(((time.perf_counter() - ts) * 1e3, status, stats, ms, mt))
+        print(f"# batch run {r}: {ms:.1f} ms solve, {mt:.1f} ms tuning", file=sys.stderr, flush=True)
+    wall, status, stats, ms, _ = runs[-1]
+    tuning = b.tuning()
+    tune_ms = runs[0][4]
+    b.close()
+    pts = sum(p.nt * p.n for p, _, _ in items)
+    cycles = [s["iterations"] for s in stats]
+    # one at a time: every k-th instance, extrapolated by count / sample size
+    step = max(1, count // max(sample, 1))
+    idx = list(range(0, count, step))[:sample]
+    one_ms = 0.0
+    for i in idx:
+        p, o, u0 = items[i]
+        u = guess[i].clone()
+        ws = atm.workspace(atm.atm_workspace_bytes(p, o), device=dev)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        atm.atm_solve(p, o, u, ws=ws, allow=(atm.ATM_OK,))
+        torch.cuda.synchronize()
+        one_ms += (time.perf_counter() - ts) * 1e3
+        del ws, u
+    one_ms_all = one_ms * count / len(idx)
+    kinds = [p.kind for p, _, _ in items]
+    return {
+        "value": pts / (wall / 1e3), "unit": "space-time point-updates/s", "ms": wall, "ms_solve_reported": ms,
+        "instances": count, "space_time_points": pts,
+        "mix": {"heat1d": kinds.count(W.HEAT1D), "heat2d": kinds.count(W.HEAT2D), "ac2d": kinds.count(W.AC2D)},
+        "all_converged": all(s == atm.ATM_OK for s in status),
+        "cycles": {"min": min(cycles), "mean": float(np.mean(cycles)), "max": max(cycles)},
+        "max_final_residual": max(s["final_residual"] for s in stats),
+        "autotuner": {"order": ["natural", "longest_first"][tuning[1]], "tiles": ["generic32", "per_instance"][tuning[2]],
+                      "ms": tune_ms},
+        "one_at_a_time": {"sample": len(idx), "every": step, "ms_sample": one_ms, "ms_extrapolated": one_ms_all,
+                          "speedup_of_batch": one_ms_all / wall},
+        "workload": "seeded batch of %d: 1D heat nx 63..511 (FP64), 2D heat and periodic 2D Allen-Cahn n x n, "
+                    "n 32..128 (FP32 fine / FP64 residual), Nt 512..8192, m in {8,16,32}, k = max(2, ceil(0.1 (N_T+1))), "
+                    "FCF, tol 1e-8" % count,
+    }
 
 
 def main():
@@ -262,6 +337,8 @@ def main():
     }
     if not args.no_learned:
         out["learned_coarse"] = learned_leg(args.learned_epochs)
+    if not args.no_batch:
+        out["batched"] = batch_leg(args.batch_count, args.batch_sample)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, u0, min(args.cpu_steps, p.nt))
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

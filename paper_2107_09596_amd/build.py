@@ -14,6 +14,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one source expression, so that every instantiation of a
+    # body (exact or masked tiling, alone or batched) rounds the same way
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

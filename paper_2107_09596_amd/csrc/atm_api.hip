@@ -554,6 +554,7 @@ struct Inst {
 
 struct Group {
     int phase, cls, S;
+    bool small;  // every instance has at most 64 columns (S = 8 only)
     Body body;
     size_t task_off;
     int ntasks;
@@ -744,13 +745,17 @@ void build_tables(atm_batch* B, std::vector<Task>& tasks)
     B->groups.clear();
     for (int ph = 0; ph < NPH; ++ph)
         for (int cls = 0; cls < NCLS; ++cls) {
-            // distinct (body, S) of this phase and class
+            // distinct (body, tile) of this phase and class; tile = S, plus 256 for the small-grid form
+            auto tile_of = [&](const Inst& in) {
+                if (cls == CLS_1D) return 0;
+                const int S = B->tiles ? in.S : 32;
+                return S + ((S == 8 && in.p.nx <= 64) ? 256 : 0);
+            };
             std::vector<std::pair<int, int>> keys;
             for (int i = 0; i < B->n; ++i) {
                 const Inst& in = B->inst[i];
                 if (in.cls != cls || phase_tasks(in, ph) == 0) continue;
-                const int S = (cls == CLS_1D) ? 0 : (B->tiles ? in.S : 32);
-                const std::pair<int, int> key((int)phase_body(in, ph), S);
+                const std::pair<int, int> key((int)phase_body(in, ph), tile_of(in));
                 if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
             }
             for (const auto& key : keys) {
@@ -758,8 +763,7 @@ void build_tables(atm_batch* B, std::vector<Task>& tasks)
                 for (int i = 0; i < B->n; ++i) {
                     const Inst& in = B->inst[i];
                     if (in.cls != cls || (int)phase_body(in, ph) != key.first) continue;
-                    const int S = (cls == CLS_1D) ? 0 : (B->tiles ? in.S : 32);
-                    if (S != key.second) continue;
+                    if (tile_of(in) != key.second) continue;
                     const int nt = phase_tasks(in, ph);
                     const int first = (ph == PH_TAU || ((ph == PH_N0 || ph == PH_N) && !in.mixed)) ? 1 : 0;
                     for (int t = 0; t < nt; ++t) g.push_back({task_cost(in, ph, t + first), Task{i, t + first}});
@@ -772,7 +776,8 @@ void build_tables(atm_batch* B, std::vector<Task>& tasks)
                 Group gr;
                 gr.phase = ph;
                 gr.cls = cls;
-                gr.S = key.second;
+                gr.S = key.second & 255;
+                gr.small = key.second >= 256;
                 gr.body = (Body)key.first;
                 gr.task_off = tasks.size();
                 gr.ntasks = (int)g.size();
@@ -806,10 +811,8 @@ atm_status enqueue_phases(atm_batch* B, const int* phases, int nphases)
             l.ntasks = g.ntasks;
             l.ctl = B->ctl_dev;
             l.nchunk = B->nchunk_dev;
-            const Inst& any = B->inst[0];
-            (void)any;
             const bool per = g.cls == CLS_2DP;
-            atm::batch::launch_tasks(g.body, g.S, per, l, B->br[g.cls]);
+            atm::batch::launch_tasks(g.body, g.S, per, g.small, l, B->br[g.cls]);
         }
     for (int c = 0; c < NCLS; ++c) {
         ATM_HIP(hipEventRecord(B->join[c], B->br[c]));
@@ -1331,19 +1334,36 @@ atm_status atm_batch_run(atm_batch* B, int32_t use_graph, int32_t check_every, a
             }
         }
     }
-    // paper-form residual of the precision-1 instances' results
+    // paper-form residual of the precision-1 instances' results: every instance's pass is enqueued
+    // (spread over the branch streams so that they overlap), then the headers are read
     std::vector<double> final_res(B->n);
+    std::vector<int> pending;
+    ATM_HIP(hipEventRecord(B->fork, B->main));
+    for (int c = 0; c < NCLS; ++c) ATM_HIP(hipStreamWaitEvent(B->br[c], B->fork, 0));
     for (int i = 0; i < B->n; ++i) {
         final_res[i] = ctl[i].res;
         const Inst& in = B->inst[i];
         if (in.mixed && (ctl[i].status == ATM_OK || ctl[i].status == ATM_NOT_CONVERGED)) {
             atm::KArgs a;
             if ((st = make_args(&in.p, &in.o, B->ws + in.off, in.L.total, a))) return st;
-            atm::Header h;
-            if ((st = do_step_norm(a, &in.p, &in.o, in.u, B->main, &final_res[i], &h))) return st;
+            a.u = in.u;
+            atm::launch_step_residual(a, sweep_tasks(&in.p, &in.o), B->br[pending.size() % NCLS]);
+            pending.push_back(i);
         }
     }
+    if ((st = check_launch())) return st;
+    for (int c = 0; c < NCLS; ++c) {
+        ATM_HIP(hipEventRecord(B->join[c], B->br[c]));
+        ATM_HIP(hipStreamWaitEvent(B->main, B->join[c], 0));
+    }
     ATM_HIP(hipStreamSynchronize(B->main));
+    for (int i : pending) {
+        const Inst& in = B->inst[i];
+        atm::Header h;
+        ATM_HIP(hipMemcpy(&h, B->ws + in.off + in.L.header, sizeof(h), hipMemcpyDeviceToHost));
+        final_res[i] = sqrt(h.norm2);
+        if (h.fail) ctl[i].status = ATM_ERR_INNER_SOLVE;
+    }
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() - tune;
     atm_status worst = ATM_OK;
     for (int i = 0; i < B->n; ++i) {

@@ -17,6 +17,10 @@
 namespace atm {
 namespace batch {
 
+// Grids of at most 64 columns (64 threads along x) need 66 LDS columns: with
+// 8-row strips such a workgroup fits twice on a CU (LDS and registers).
+constexpr int kSmallCols = 64 + 2;
+
 #define BATCH_TASK_PRELUDE                       \
     const Task t = tasks[blockIdx.x];            \
     if (!ctl[t.inst].active) return;             \
@@ -38,47 +42,51 @@ __global__ __launch_bounds__(512) void coarse1d_batch(const KArgs* __restrict__ 
     coarse1d_body(a, t.idx, lds);
 }
 
-template <int S, bool PER>
+template <int S, bool PER, bool SMALL>
 __global__ __launch_bounds__(kBlock2D) void sweep2d_batch(const KArgs* __restrict__ args,
                                                           const Task* __restrict__ tasks,
                                                           const InstCtl* __restrict__ ctl)
 {
-    __shared__ __align__(16) double lds[Lds2D<double>::size];
+    constexpr int COLS = SMALL ? kSmallCols : kMaxSide2D + 2;
+    __shared__ __align__(16) double lds[COLS * Lds2D<double>::H];
     __shared__ double red[4 * kWaves2D];
     BATCH_TASK_PRELUDE
-    sweep2d_mixed_body<S, false, PER>(a, t.idx, lds, red);
+    sweep2d_mixed_body<S, false, PER, COLS>(a, t.idx, lds, red);
 }
 
-template <int S, bool PER>
+template <int S, bool PER, bool SMALL>
 __global__ __launch_bounds__(kBlock2D) void sweep2d64_batch(const KArgs* __restrict__ args,
                                                             const Task* __restrict__ tasks,
                                                             const InstCtl* __restrict__ ctl)
 {
-    __shared__ __align__(16) double lds[Lds2D<double>::size];
+    constexpr int COLS = SMALL ? kSmallCols : kMaxSide2D + 2;
+    __shared__ __align__(16) double lds[COLS * Lds2D<double>::H];
     __shared__ double red[4 * kWaves2D];
     BATCH_TASK_PRELUDE
-    sweep2d_body<S, false, PER>(a, t.idx, lds, red);
+    sweep2d_body<S, false, PER, COLS>(a, t.idx, lds, red);
 }
 
-template <int S, bool PER>
+template <int S, bool PER, bool SMALL>
 __global__ __launch_bounds__(kBlock2D) void coarse2d_batch(const KArgs* __restrict__ args,
                                                            const Task* __restrict__ tasks,
                                                            const InstCtl* __restrict__ ctl)
 {
-    __shared__ __align__(16) double lds[Lds2D<double>::size];
+    constexpr int COLS = SMALL ? kSmallCols : kMaxSide2D + 2;
+    __shared__ __align__(16) double lds[COLS * Lds2D<double>::H];
     __shared__ double red[4 * kWaves2D];
     BATCH_TASK_PRELUDE
-    coarse2d_body<S, false, PER>(a, t.idx, lds, red);
+    coarse2d_body<S, false, PER, COLS>(a, t.idx, lds, red);
 }
 
-template <int S, bool PER>
+template <int S, bool PER, bool SMALL>
 __global__ __launch_bounds__(kBlock2D) void tau2d_batch(const KArgs* __restrict__ args, const Task* __restrict__ tasks,
                                                         const InstCtl* __restrict__ ctl)
 {
-    __shared__ __align__(16) double lds[Lds2D<double>::size];
+    constexpr int COLS = SMALL ? kSmallCols : kMaxSide2D + 2;
+    __shared__ __align__(16) double lds[COLS * Lds2D<double>::H];
     __shared__ double red[4 * kWaves2D];
     BATCH_TASK_PRELUDE
-    tau2d_body<S, false, PER>(a, t.idx, lds, red);
+    tau2d_body<S, false, PER, COLS>(a, t.idx, lds, red);
 }
 
 constexpr int kNormThreads = 256;
@@ -200,16 +208,26 @@ __global__ void reset_headers_batch(const KArgs* __restrict__ args, InstCtl* ctl
     ctl[i].res = 0.0;
 }
 
-#define BATCH_S(kernel, PER, l, s)                                                                               \
-    do {                                                                                                         \
-        switch (S) {                                                                                             \
-            case 8: hipLaunchKernelGGL(HIP_KERNEL_NAME(kernel<8, PER>), dim3(l.ntasks), dim3(kBlock2D), 0, s,    \
-                                       l.args, l.tasks, l.ctl); break;                                           \
-            case 16: hipLaunchKernelGGL(HIP_KERNEL_NAME(kernel<16, PER>), dim3(l.ntasks), dim3(kBlock2D), 0, s,  \
-                                        l.args, l.tasks, l.ctl); break;                                          \
-            default: hipLaunchKernelGGL(HIP_KERNEL_NAME(kernel<32, PER>), dim3(l.ntasks), dim3(kBlock2D), 0, s,  \
-                                        l.args, l.tasks, l.ctl); break;                                          \
-        }                                                                                                        \
+#define BATCH_S(kernel, PER, l, s)                                                                              \
+    do {                                                                                                        \
+        switch (S) {                                                                                            \
+            case 8:                                                                                             \
+                if (small)                                                                                      \
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(kernel<8, PER, true>), dim3(l.ntasks), dim3(kBlock2D), 0, \
+                                       s, l.args, l.tasks, l.ctl);                                              \
+                else                                                                                            \
+                    hipLaunchKernelGGL(HIP_KERNEL_NAME(kernel<8, PER, false>), dim3(l.ntasks), dim3(kBlock2D), 0, \
+                                       s, l.args, l.tasks, l.ctl);                                              \
+                break;                                                                                          \
+            case 16:                                                                                            \
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(kernel<16, PER, false>), dim3(l.ntasks), dim3(kBlock2D), 0, s, \
+                                   l.args, l.tasks, l.ctl);                                                     \
+                break;                                                                                          \
+            default:                                                                                            \
+                hipLaunchKernelGGL(HIP_KERNEL_NAME(kernel<32, PER, false>), dim3(l.ntasks), dim3(kBlock2D), 0, s, \
+                                   l.args, l.tasks, l.ctl);                                                     \
+                break;                                                                                          \
+        }                                                                                                       \
     } while (0)
 
 #define BATCH_SP(kernel, l, s)                   \
@@ -220,7 +238,7 @@ __global__ void reset_headers_batch(const KArgs* __restrict__ args, InstCtl* ctl
             BATCH_S(kernel, false, l, s);        \
     } while (0)
 
-void launch_tasks(Body body, int S, bool per, const Launch& l, hipStream_t s)
+void launch_tasks(Body body, int S, bool per, bool small, const Launch& l, hipStream_t s)
 {
     if (l.ntasks <= 0) return;
     switch (body) {

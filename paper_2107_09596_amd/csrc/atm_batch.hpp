@@ -47,8 +47,9 @@ enum Body {
     kNormFinalI,
 };
 
-// launch body over the task table with strip template S (2D) and periodic flag
-void launch_tasks(Body body, int S, bool per, const Launch& l, hipStream_t s);
+// launch body over the task table with strip template S (2D), periodic flag and small flag (every
+// instance of the table has at most 64 columns; used with S = 8)
+void launch_tasks(Body body, int S, bool per, bool small, const Launch& l, hipStream_t s);
 // decision after the norm of every instance: history, status, activity
 void launch_decide(const KArgs* args, InstCtl* ctl, double* hist, int hist_cap, int n_inst, bool first, hipStream_t s);
 void launch_reset_headers(const KArgs* args, InstCtl* ctl, int n_inst, hipStream_t s);

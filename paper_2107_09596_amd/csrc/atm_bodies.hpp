@@ -90,12 +90,12 @@ __device__ __forceinline__ int step2d(const KArgs& a, const StepCoef& c, double 
     return cg2d<double, S, EX, PER, true>(a.g, c, st, v.x, v.r, v.q, lp, red, slot, rtol2, a.maxit, a.fail);
 }
 
-template <int S, bool EX, bool PER>
+template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2>
 __device__ __forceinline__ void sweep2d_body(const KArgs& a, int64_t j, double* lp, double* red)
 {
     int slot = 0;
     const Strip st = make_strip<double>(a.g);
-    lds_clear(lp);
+    lds_clear<COLS>(lp);
     Strip2DState<S> v;
     const int nx = a.g.nx;
     bool same = true;
@@ -133,13 +133,13 @@ __device__ __forceinline__ long long psi2d(const KArgs& a, const Strip& st, Stri
     return its;
 }
 
-template <int S, bool EX, bool PER>
+template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2>
 __device__ __forceinline__ void coarse2d_body(const KArgs& a, int64_t p, double* lp, double* red)
 {
     int slot = 0;
     const int64_t s0 = p - a.k + 1 > 0 ? p - a.k + 1 : 0;
     const Strip st = make_strip<double>(a.g);
-    lds_clear(lp);
+    lds_clear<COLS>(lp);
     const int nx = a.g.nx;
     Strip2DState<S> v;
 #pragma unroll
@@ -171,12 +171,12 @@ __device__ __forceinline__ void coarse2d_body(const KArgs& a, int64_t p, double*
     count_cg(a, its);
 }
 
-template <int S, bool EX, bool PER>
+template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2>
 __device__ __forceinline__ void tau2d_body(const KArgs& a, int64_t j, double* lp, double* red)
 {
     int slot = 0;
     const Strip st = make_strip<double>(a.g);
-    lds_clear(lp);
+    lds_clear<COLS>(lp);
     const int nx = a.g.nx;
     Strip2DState<S> v;
 #pragma unroll
@@ -223,18 +223,18 @@ __device__ __forceinline__ void lds_clear_halo(const Grid2D& g, T* lp)
 // sweep).  The starting value of the step that produces y_{j+1} = Phi(u_{jm+m-1})
 // is, by mode: 0 the C-point u_{(j+1)m}; 1 y_{j+1} on entry (y is in/out);
 // 2 aux_{j+1} (the Phi values of the previous sweep).
-template <int S, bool EX, bool PER>
+template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2>
 __device__ __forceinline__ void sweep2d_mixed_body(const KArgs& a, int64_t j, double* ldsd, double* red)
 {
     // one LDS block holds the FP64 staging of u_i^old for the defect and then
     // the FP32 search direction of the CG (the FP32 layout is the smaller one)
-    static_assert(Lds2D<float>::size * sizeof(float) <= Lds2D<double>::size * sizeof(double), "LDS alias");
+    static_assert(Lds2D<float>::H * sizeof(float) <= Lds2D<double>::H * sizeof(double), "LDS alias");
     float* lpf = reinterpret_cast<float*>(ldsd);
     int slot = 0;
     const Strip sd = make_strip<double>(a.g);
     const Strip sf = make_strip<float>(a.g);
     const int nx = a.g.nx;
-    lds_clear(ldsd);
+    lds_clear<COLS>(ldsd);
     double up[S];
     float x[S], r[S], q[S];
 #pragma unroll

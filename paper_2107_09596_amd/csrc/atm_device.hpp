@@ -272,10 +272,12 @@ __device__ __forceinline__ bool row_ok(const Strip& st, int s)
 
 // Zero the whole LDS vector including its halo (once per kernel; ends with a
 // barrier so no clear can land after a strip store of another thread).
-template <typename T>
+// COLS: LDS columns held by the caller (grid columns + 2 halo columns at most;
+// the full size fits every grid up to the largest side).
+template <int COLS = kMaxSide2D + 2, typename T>
 __device__ __forceinline__ void lds_clear(T* lp)
 {
-    for (int i = threadIdx.x; i < Lds2D<T>::size; i += blockDim.x) lp[i] = (T)0;
+    for (int i = threadIdx.x; i < COLS * Lds2D<T>::H; i += blockDim.x) lp[i] = (T)0;
     __syncthreads();
 }
 

@@ -225,8 +225,12 @@ def test_c2_full_size_sampled(atm, orc):
         x = u[j * o.m].copy()
         for i in range(1, o.m):
             x = orc.step(p, p.dt, x)
-            # two CG runs to rtol 1e-12 agree to about rtol per step
-            assert_close(u[j * o.m + i], x, rtol=5e-12, what=f"c2 interval {j} step {i}")
+            # each step's CG (either side, from its own starting value) stops at |b - M x| <= rtol |b|
+            # with |M^-1| <= 1, so it is within rtol |b| of the exact step, |b| <= |u_{jm}| for heat;
+            # the errors of i steps add up (Phi does not amplify them)
+            err = float(np.linalg.norm(u[j * o.m + i] - x))
+            bound = 2 * i * p.cg_rtol * float(np.linalg.norm(u[j * o.m]))
+            assert err <= bound, f"c2 interval {j} step {i}: |diff| = {err:.3e} > {bound:.3e}"
     # the converged iterate is the sequential solution up to the residual tolerance
     q = W.Problem(**{**p.__dict__, "nt": 256, "tf": p.t0 + 256 * p.dt})
     ref = orc.sequential(q, u0)
