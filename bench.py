@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-coarse-propagator comparison")
     ap.add_argument("--learned-epochs", type=int, default=15)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the c1 and c3 solves")
     ap.add_argument("--batch-count", type=int, default=256,
                     help="instances of the seeded batched workload (the first N of the 256)")
     ap.add_argument("--batch-sample", type=int, default=16,
@@ -145,6 +146,40 @@ def learned_leg(epochs):
                        "tol 1e-8; learned = CNN 1-32-32-32-1 (BF16, FP32 accumulate) as Psi in the FAS windows, plain Psi as fallback" %
                        (o.k, o.precision))
     return res
+
+
+def config_leg(name, runs):
+    """One more workload of the suite (c1: 1D heat FP64; c3: 2D Allen-Cahn 256x256, FP32 fine / FP64
+    residual, large-grid kernels): `runs` timed solves after one warm-up (c1) or a single solve."""
+    import torch
+
+    import paper_2107_09596_amd as atm
+    import workloads as W
+
+    p, o, u0 = W.config(name)
+    o.profile = 1
+    dev = torch.device("cuda:0")
+    guess = torch.from_numpy(W.initial_guess(p, u0)).to(dev)
+    u = torch.empty_like(guess)
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o), device=dev)
+    times = []
+    for r in range(runs):
+        u.copy_(guess)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        status, hist, st = atm.atm_solve(p, o, u, ws=ws, allow=(atm.ATM_OK,))
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - ts) * 1e3)
+        print(f"# {name} run {r}: {st['iterations']} cycles, {times[-1]:.1f} ms", file=sys.stderr, flush=True)
+    ms = times[-1] if runs == 1 else min(times[1:])
+    return {"value": p.n * p.nt / (ms / 1e3), "unit": "space-time point-updates/s", "ms": ms,
+            "iterations": st["iterations"], "final_residual": st["final_residual"], "stopping_norm": hist[-1],
+            "phase_ms": {k: st[k] for k in ("ms_sweep", "ms_coarse", "ms_norm")},
+            "cg_iters": {"fine": st["cg_fine"], "coarse": st["cg_coarse"]},
+            "timed": "single solve" if runs == 1 else "best of %d after a warm-up" % (runs - 1),
+            "workload": {"c1": "1D heat nx=63, Nt=1024, m=16, k=7, FCF, FP64, tol 1e-8",
+                         "c3": "2D Allen-Cahn 256x256 periodic, eps 0.02, dt 1e-5, Nt=8192, m=64, k=%d, FCF, "
+                               "4 coarse substeps, FP32 fine / FP64 residual, tol 1e-8" % o.k}[name]}
 
 
 def batch_leg(count, sample):
@@ -339,6 +374,8 @@ def main():
         out["learned_coarse"] = learned_leg(args.learned_epochs)
     if not args.no_batch:
         out["batched"] = batch_leg(args.batch_count, args.batch_sample)
+    if not args.no_configs:
+        out["other_configs"] = {"c1": config_leg("c1", 4), "c3": config_leg("c3", 1)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, u0, min(args.cpu_steps, p.nt))
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

@@ -38,7 +38,8 @@ __device__ __forceinline__ LCol make_col(const Grid2D& g)
 
 // M v at (x, y), v a full field in global memory
 template <typename T>
-__device__ __forceinline__ T stencil_g(const Grid2D& g, const StepCoef& c, const LCol& col, const T* v, int y)
+__device__ __forceinline__ T stencil_g(const Grid2D& g, const StepCoef& c, const LCol& col, const T* __restrict__ v,
+                                       int y)
 {
     const int64_t row = (int64_t)y * g.nx;
     const int yn = y > 0 ? y - 1 : (g.periodic ? g.ny - 1 : -1);
@@ -51,26 +52,77 @@ __device__ __forceinline__ T stencil_g(const Grid2D& g, const StepCoef& c, const
     return stencil_value(c, up, cen, dn, w, e);
 }
 
+// The rows of a thread (y = ty, ty + TY, ...).  A plain loop over them waits out one memory
+// latency per row, so the passes of the CG below take the rows in batches of kRowBatch: every load
+// of a batch is issued before any is used (the vectors are distinct, __restrict__), and the sums
+// keep the row order.  The loops outside the CG iterations are unrolled by the same factor.
+constexpr int kRowBatch = 4;
 #define FOR_ROWS(col, g, y) for (int y = (col).ty; (col).act && y < (g).ny; y += (col).TY)
+#define FOR_BATCH(col, g, y0) for (int y0 = (col).ty; (col).act && y0 < (g).ny; y0 += kRowBatch * (col).TY)
+
+// the five stencil inputs of row y (zero outside a Dirichlet boundary)
+template <typename T>
+struct Nb {
+    T cen, w, e, up, dn;
+};
+
+// Offsets within one slice are 32-bit (a slice holds at most 1024 x 1024 points), so that a load is
+// a uniform base plus one offset register.
+__device__ __forceinline__ uint32_t pt(const Grid2D& g, const LCol& col, int y)
+{
+    return (uint32_t)y * (uint32_t)g.nx + (uint32_t)col.x;
+}
+
+template <typename T>
+__device__ __forceinline__ Nb<T> load_nb(const Grid2D& g, const LCol& col, const T* __restrict__ v, int y)
+{
+    const uint32_t row = (uint32_t)y * (uint32_t)g.nx;
+    const int yn = y > 0 ? y - 1 : (g.periodic ? g.ny - 1 : -1);
+    const int ys = y < g.ny - 1 ? y + 1 : (g.periodic ? 0 : -1);
+    Nb<T> b;
+    b.cen = v[row + (uint32_t)col.x];
+    b.w = col.xw >= 0 ? v[row + (uint32_t)col.xw] : (T)0;
+    b.e = col.xe >= 0 ? v[row + (uint32_t)col.xe] : (T)0;
+    b.up = yn >= 0 ? v[(uint32_t)yn * (uint32_t)g.nx + (uint32_t)col.x] : (T)0;
+    b.dn = ys >= 0 ? v[(uint32_t)ys * (uint32_t)g.nx + (uint32_t)col.x] : (T)0;
+    return b;
+}
 
 // Jacobi-preconditioned CG (constant diagonal: plain CG on the scaled direction) for M x = b with
 // the vectors in global memory.  On entry x = x0, r = b.  Same stopping rule and failure flag as
 // the on-chip solver.  Returns the iteration count.
 template <typename T>
-__device__ int cg_large(const Grid2D& g, const StepCoef& c, const LCol& col, T* x, T* r, T* p, T* q, double* red,
-                        int& slot, double rtol2, int maxit, int* fail)
+__device__ int cg_large(const Grid2D& g, const StepCoef& c, const LCol& col, T* __restrict__ x, T* __restrict__ r,
+                        T* __restrict__ p, T* __restrict__ q, double* red, int& slot, double rtol2, int maxit,
+                        int* fail)
 {
+    constexpr int U = kRowBatch;
     double bb = 0.0, rr = 0.0;
-    FOR_ROWS(col, g, y)
+    // r = b - M x0, p = r (the stencil reads x at neighbours; r and p only at the thread's own points)
+    FOR_BATCH(col, g, y0)
     {
-        // the stencil reads x at neighbours; r and p are only touched at the thread's own points
-        const int64_t i = (int64_t)y * g.nx + col.x;
-        const T b = r[i];
-        bb += (double)b * (double)b;
-        const T ri = b - stencil_g(g, c, col, x, y);
-        rr += (double)ri * (double)ri;
-        r[i] = ri;
-        p[i] = ri;
+        Nb<T> nb[U];
+        T b[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int y = y0 + u * col.TY;
+            if (y < g.ny) {
+                nb[u] = load_nb(g, col, x, y);
+                b[u] = r[pt(g, col, y)];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int y = y0 + u * col.TY;
+            if (y < g.ny) {
+                const uint32_t i = pt(g, col, y);
+                bb += (double)b[u] * (double)b[u];
+                const T ri = b[u] - stencil_value(c, nb[u].up, nb[u].cen, nb[u].dn, nb[u].w, nb[u].e);
+                rr += (double)ri * (double)ri;
+                r[i] = ri;
+                p[i] = ri;
+            }
+        }
     }
     block_sum2(bb, rr, red, slot, kWavesL);
     const bool bzero = (bb == 0.0);
@@ -78,39 +130,84 @@ __device__ int cg_large(const Grid2D& g, const StepCoef& c, const LCol& col, T* 
     double gamma = rr;
     int it = 0;
     while (!bzero && rr > thresh && it < maxit) {
+        // q = M p, (p, q)
         double pq = 0.0;
-        FOR_ROWS(col, g, y)
+        FOR_BATCH(col, g, y0)
         {
-            const int64_t i = (int64_t)y * g.nx + col.x;
-            const T v = stencil_g(g, c, col, p, y);
-            q[i] = v;
-            pq += (double)p[i] * (double)v;
+            Nb<T> nb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int y = y0 + u * col.TY;
+                if (y < g.ny) nb[u] = load_nb(g, col, p, y);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int y = y0 + u * col.TY;
+                if (y < g.ny) {
+                    const T v = stencil_value(c, nb[u].up, nb[u].cen, nb[u].dn, nb[u].w, nb[u].e);
+                    q[pt(g, col, y)] = v;
+                    pq += (double)nb[u].cen * (double)v;
+                }
+            }
         }
         pq = block_sum1(pq, red, slot, kWavesL);
         const T alpha = (T)(gamma / pq);
+        // x += alpha p, r -= alpha q
         rr = 0.0;
-        FOR_ROWS(col, g, y)
+        FOR_BATCH(col, g, y0)
         {
-            const int64_t i = (int64_t)y * g.nx + col.x;
-            x[i] = x[i] + alpha * p[i];
-            const T ri = r[i] - alpha * q[i];
-            r[i] = ri;
-            rr += (double)ri * (double)ri;
+            T xv[U], pv[U], rv[U], qv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int y = y0 + u * col.TY;
+                if (y < g.ny) {
+                    const uint32_t i = pt(g, col, y);
+                    xv[u] = x[i];
+                    pv[u] = p[i];
+                    rv[u] = r[i];
+                    qv[u] = q[i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int y = y0 + u * col.TY;
+                if (y < g.ny) {
+                    const uint32_t i = pt(g, col, y);
+                    x[i] = xv[u] + alpha * pv[u];
+                    const T ri = rv[u] - alpha * qv[u];
+                    r[i] = ri;
+                    rr += (double)ri * (double)ri;
+                }
+            }
         }
         rr = block_sum1(rr, red, slot, kWavesL);
         const T beta = (T)(rr / gamma);
         gamma = rr;
-        FOR_ROWS(col, g, y)
+        // p = r + beta p
+        FOR_BATCH(col, g, y0)
         {
-            const int64_t i = (int64_t)y * g.nx + col.x;
-            p[i] = r[i] + beta * p[i];
+            T rv[U], pv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int y = y0 + u * col.TY;
+                if (y < g.ny) {
+                    const uint32_t i = pt(g, col, y);
+                    rv[u] = r[i];
+                    pv[u] = p[i];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int y = y0 + u * col.TY;
+                if (y < g.ny) p[pt(g, col, y)] = rv[u] + beta * pv[u];
+            }
         }
         __syncthreads();
         ++it;
     }
     if (!bzero && rr > thresh && threadIdx.x == 0) atomicOr(fail, 1);
     if (bzero) {
-        FOR_ROWS(col, g, y) x[(int64_t)y * g.nx + col.x] = (T)0;
+        FOR_ROWS(col, g, y) x[pt(g, col, y)] = (T)0;
         __syncthreads();
     }
     return it;
@@ -125,8 +222,9 @@ struct LScratch {
 
 // one FP64 step v <- Phi_c(v) in place (v global), using CG vectors x, r, p, q
 __device__ __forceinline__ long long step_large64(const KArgs& a, const StepCoef& c, double rtol2, const LCol& col,
-                                                  double* v, double* x, double* r, double* p, double* q, double* red,
-                                                  int& slot)
+                                                  double* __restrict__ v, double* __restrict__ x,
+                                                  double* __restrict__ r, double* __restrict__ p,
+                                                  double* __restrict__ q, double* red, int& slot)
 {
     const Grid2D& g = a.g;
     FOR_ROWS(col, g, y)
@@ -180,11 +278,12 @@ __global__ __launch_bounds__(kBlockL) void sweep_large_kernel(KArgs a, LScratch 
     for (int64_t t = 1; t <= total; ++t) {
         its += step_large64(a, a.fine, a.rtol2, col, v, sc.vec(j, 0), sc.vec(j, 1), sc.vec(j, 2), sc.vec(j, 3), red,
                             slot);
-        double* dst = (t < a.m) ? a.u + (j * a.m + t) * n : a.y + (j + 1) * n;
+        double* __restrict__ dst = (t < a.m) ? a.u + (j * a.m + t) * n : a.y + (j + 1) * n;
+        const double* __restrict__ vs = v;
         FOR_ROWS(col, g, y)
         {
             const int64_t i = (int64_t)y * g.nx + col.x;
-            dst[i] = v[i];
+            dst[i] = vs[i];
         }
     }
     count_cg(a, its);
@@ -200,11 +299,11 @@ __global__ __launch_bounds__(kBlockL) void sweep_large_mixed_kernel(KArgs a, LSc
     const Grid2D& g = a.g;
     const LCol col = make_col(g);
     const int64_t n = a.n;
-    float* x = reinterpret_cast<float*>(sc.vec(j, 0));
-    float* r = reinterpret_cast<float*>(sc.vec(j, 1));
-    float* p = reinterpret_cast<float*>(sc.vec(j, 2));
-    float* q = reinterpret_cast<float*>(sc.vec(j, 3));
-    double* prev = sc.vec(j, 4);
+    float* __restrict__ x = reinterpret_cast<float*>(sc.vec(j, 0));
+    float* __restrict__ r = reinterpret_cast<float*>(sc.vec(j, 1));
+    float* __restrict__ p = reinterpret_cast<float*>(sc.vec(j, 2));
+    float* __restrict__ q = reinterpret_cast<float*>(sc.vec(j, 3));
+    double* __restrict__ prev = sc.vec(j, 4);
     FOR_ROWS(col, g, y)
     {
         const int64_t i = (int64_t)y * g.nx + col.x;
@@ -217,12 +316,13 @@ __global__ __launch_bounds__(kBlockL) void sweep_large_mixed_kernel(KArgs a, LSc
     long long its = 0;
     for (int64_t t = 1; t <= total; ++t) {
         const bool ystep = (t == a.m);
-        const double* xo;
+        const double* xo_;
         if (!ystep)
-            xo = a.u + (j * a.m + t) * n;
+            xo_ = a.u + (j * a.m + t) * n;
         else
-            xo = (a.mode == 0 ? a.u + ((j + 1) * a.m) * n : (a.mode == 1 ? a.y : a.aux) + (j + 1) * n);
-        double* dst = ystep ? a.y + (j + 1) * n : a.u + (j * a.m + t) * n;
+            xo_ = (a.mode == 0 ? a.u + ((j + 1) * a.m) * n : (a.mode == 1 ? a.y : a.aux) + (j + 1) * n);
+        const double* __restrict__ xo = xo_;
+        double* __restrict__ dst = ystep ? a.y + (j + 1) * n : a.u + (j * a.m + t) * n;
         FOR_ROWS(col, g, y)
         {
             const int64_t i = (int64_t)y * g.nx + col.x;
@@ -264,7 +364,7 @@ __global__ __launch_bounds__(kBlockL) void coarse_large_kernel(KArgs a, LScratch
     const Grid2D& g = a.g;
     const LCol col = make_col(g);
     const int64_t n = a.n;
-    double* w = sc.vec(p, 4);
+    double* __restrict__ w = sc.vec(p, 4);
     FOR_ROWS(col, g, y)
     {
         const int64_t i = (int64_t)y * g.nx + col.x;
@@ -349,8 +449,8 @@ __global__ __launch_bounds__(kBlockL) void step_residual_large_kernel(KArgs a, L
     const Grid2D& g = a.g;
     const LCol col = make_col(g);
     const int64_t n = a.n;
-    double* x = sc.vec(j, 0);
-    double* r = sc.vec(j, 1);
+    double* __restrict__ x = sc.vec(j, 0);
+    double* __restrict__ r = sc.vec(j, 1);
     const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
     double acc = 0.0;
     long long its = 0;
