@@ -100,6 +100,11 @@ typedef struct atm_options {
                               form with the residual, coarse correction and iterate in FP64
                               (see atm_sweep and atm_solve) */
     int32_t profile;       /* 1: time every kernel launch of atm_solve with HIP events (atm_stats.ms_*) */
+    int32_t coarse_solver; /* the implicit solve inside Psi (2D kinds): 0 auto = exact solve in the
+                              eigenbasis of the constant-coefficient operator where built (grids with
+                              more than 128 points per side), CG elsewhere; 1 CG everywhere (to
+                              coarse_cg_rtol).  Both take the same step: the eigenbasis solve is exact to
+                              rounding, CG to its tolerance */
 } atm_options;
 
 typedef struct atm_stats {

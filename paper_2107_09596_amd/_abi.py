@@ -40,7 +40,7 @@ class AtmOptions(ctypes.Structure):
         ("fallback_ratio", ctypes.c_double), ("cnn_params", ctypes.c_void_p),
         ("m", ctypes.c_int32), ("k", ctypes.c_int32), ("relax", ctypes.c_int32),
         ("max_iter", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32), ("coarse_form", ctypes.c_int32),
-        ("precision", ctypes.c_int32), ("profile", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("profile", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
     ]
 
 
@@ -144,4 +144,5 @@ def options(o) -> AtmOptions:
                       fallback_ratio=float(getattr(o, "fallback_ratio", 0.0)), cnn_params=cnn,
                       m=o.m, k=o.k, relax=o.relax,
                       max_iter=o.max_iter, coarse_substeps=o.coarse_substeps, coarse_form=o.coarse_form,
-                      precision=getattr(o, "precision", 0), profile=int(getattr(o, "profile", 0)))
+                      precision=getattr(o, "precision", 0), profile=int(getattr(o, "profile", 0)),
+                      coarse_solver=int(getattr(o, "coarse_solver", 0)))

@@ -49,7 +49,7 @@ constexpr double kLearnedGrowthLimit = 1e6;  // learned coarse solve: give up be
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t header, partials, ya, yb, e, tau, pk, d1, d2, large, total;
+    size_t header, partials, ya, yb, e, tau, pk, d1, d2, large, spec, total;
 };
 
 int64_t n_intervals(const atm_problem* p, const atm_options* o) { return p->nt / o->m; }
@@ -70,6 +70,9 @@ bool use_fas(const atm_problem* p, const atm_options* o)
 }
 
 bool learned(const atm_options* o) { return o->coarse_form == 3; }
+
+// Psi's implicit solve by the eigenbasis (large grids, coarse_solver 0)
+bool spectral(const atm_problem* p, const atm_options* o) { return large_grid(p) && o->coarse_solver == 0; }
 
 Layout layout(const atm_problem* p, const atm_options* o)
 {
@@ -99,6 +102,8 @@ Layout layout(const atm_problem* p, const atm_options* o)
     off += align_up((NT + 1) * act);
     L.large = off;
     off += large_grid(p) ? align_up((NT + 1) * 5 * (size_t)n_space(p) * sizeof(double)) : 0;
+    L.spec = off;
+    off += spectral(p, o) ? align_up(atm::spectral_table_doubles(p->nx, p->ny) * sizeof(double)) : 0;
     L.total = off;
     return L;
 }
@@ -122,6 +127,8 @@ atm_status validate(const atm_problem* p, const atm_options* o)
     if (o->relax != 0 && o->relax != 1) return fail(ATM_ERR_INVALID_ARG, "relax must be 0 (F) or 1 (FCF)");
     if (o->coarse_substeps < 1) return fail(ATM_ERR_INVALID_ARG, "coarse_substeps must be >= 1");
     if (o->coarse_form < 0 || o->coarse_form > 3) return fail(ATM_ERR_INVALID_ARG, "coarse_form must be 0, 1, 2 or 3");
+    if (o->coarse_solver != 0 && o->coarse_solver != 1)
+        return fail(ATM_ERR_INVALID_ARG, "coarse_solver must be 0 (auto) or 1 (CG)");
     if (o->coarse_form == 3) {
         if (p->kind != ATM_AC2D)
             return fail(ATM_ERR_UNSUPPORTED, "the learned coarse propagator is built for the periodic ATM_AC2D grid");
@@ -202,6 +209,8 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
     if (large_grid(p)) {
         a.large = 1;
         a.large_scratch = (double*)(base + L.large);
+        a.spectral = spectral(p, o) ? 1 : 0;
+        a.spec = a.spectral ? (double*)(base + L.spec) : nullptr;
         a.g.nx = p->nx;
         a.g.ny = p->ny;
         a.g.periodic = (p->kind == ATM_AC2D);

@@ -49,6 +49,11 @@ struct KArgs {
     // (five n-vectors of doubles per interval or window)
     int large;
     double* large_scratch;
+    // Psi's implicit solve in the eigenbasis of the constant-coefficient operator (large grids):
+    // tables Qx [nx][nx], Qx^T, Qy [ny][ny], Qy^T and the mode factors ex [nx], ey [ny] of the coarse
+    // step, built on the device before the windows
+    int spectral;
+    double* spec;
 };
 
 // ---------------------------------------------------------------------------
@@ -134,6 +139,8 @@ void launch_step_residual(const KArgs& a, int64_t n_tasks, hipStream_t s);
 constexpr int kMaxSideLarge = 1024;
 void launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t s);
 void launch_coarse_large(const KArgs& a, hipStream_t s);
+// doubles of the eigenbasis tables of an nx x ny grid (KArgs::spec)
+size_t spectral_table_doubles(int nx, int ny);
 void launch_sequential_large(const KArgs& a, hipStream_t s);
 void launch_step_residual_large(const KArgs& a, int64_t n_tasks, hipStream_t s);
 

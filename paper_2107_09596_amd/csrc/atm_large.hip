@@ -344,13 +344,181 @@ __global__ __launch_bounds__(kBlockL) void sweep_large_mixed_kernel(KArgs a, LSc
     count_cg(a, its);
 }
 
+// ---------------------------------------------------------------------------
+// Psi's implicit solve in the eigenbasis of M = I - dT nu L (constant coefficients).
+//
+// The 1D second differences are diagonalised by orthonormal bases: Dirichlet (n interior points)
+// Q[x][k] = sqrt(2/(n+1)) sin(pi (x+1)(k+1)/(n+1)), angle theta_k = pi (k+1)/(n+1); periodic (n
+// points) the real Fourier basis, column 0 constant, columns 2m-1 / 2m cos / sin of 2 pi m x / n,
+// (and for even n the last column (-1)^x), angle 2 pi m / n.  The 5-point operator
+// M v = (1 + 2cx + 2cy) v - cx (w + e) - cy (n + s) has the eigenvalue
+// 1 + ex[kx] + ey[ky], e = 2c (1 - cos theta), on Qy[:, ky] (x) Qx[:, kx], so with the field b as
+// an ny x nx matrix, M^-1 b = Qy ((Qy^T b Qx) ./ (1 + ex + ey)) Qx^T: four dense products.
+// ---------------------------------------------------------------------------
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct SpecTables {
+    const double *qx, *qxt, *qy, *qyt, *ex, *ey;
+};
+
+__device__ __forceinline__ SpecTables spec_tables(const KArgs& a)
+{
+    const int64_t nx = a.g.nx, ny = a.g.ny;
+    SpecTables t;
+    t.qx = a.spec;
+    t.qxt = t.qx + nx * nx;
+    t.qy = t.qxt + nx * nx;
+    t.qyt = t.qy + ny * ny;
+    t.ex = t.qyt + ny * ny;
+    t.ey = t.ex + nx;
+    return t;
+}
+
+size_t spectral_table_doubles(int nx, int ny) { return 2 * (size_t)nx * nx + 2 * (size_t)ny * ny + nx + ny; }
+
+// basis entry Q[x][k] and mode angle of column k
+__device__ __forceinline__ double basis(int n, bool periodic, int x, int k, double* theta)
+{
+    if (!periodic) {
+        // angles reduced with integer arithmetic: pi t / (n + 1), t = (x+1)(k+1) mod 2(n+1)
+        const int64_t t = ((int64_t)(x + 1) * (k + 1)) % (2 * (int64_t)(n + 1));
+        *theta = kPi * (double)(k + 1) / (double)(n + 1);
+        return sqrt(2.0 / (double)(n + 1)) * sin(kPi * (double)t / (double)(n + 1));
+    }
+    const int m = (k + 1) / 2;
+    *theta = 2.0 * kPi * (double)m / (double)n;
+    if (k == 0) return sqrt(1.0 / (double)n);
+    const int64_t t = ((int64_t)m * x) % n;
+    const double ang = 2.0 * kPi * (double)t / (double)n;
+    if (2 * m == n) return sqrt(1.0 / (double)n) * ((x & 1) ? -1.0 : 1.0);
+    return sqrt(2.0 / (double)n) * ((k & 1) ? cos(ang) : sin(ang));
+}
+
+__global__ __launch_bounds__(256) void spectral_tables_kernel(KArgs a)
+{
+    const int nx = a.g.nx, ny = a.g.ny;
+    const bool per = a.g.periodic != 0;
+    double* qx = a.spec;
+    double* qxt = qx + (int64_t)nx * nx;
+    double* qy = qxt + (int64_t)nx * nx;
+    double* qyt = qy + (int64_t)ny * ny;
+    double* ex = qyt + (int64_t)ny * ny;
+    double* ey = ex + nx;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double th;
+    for (int64_t i = first; i < (int64_t)nx * nx; i += stride) {
+        const int x = (int)(i / nx), k = (int)(i % nx);
+        const double v = basis(nx, per, x, k, &th);
+        qx[(int64_t)x * nx + k] = v;
+        qxt[(int64_t)k * nx + x] = v;
+    }
+    for (int64_t i = first; i < (int64_t)ny * ny; i += stride) {
+        const int y = (int)(i / ny), k = (int)(i % ny);
+        const double v = basis(ny, per, y, k, &th);
+        qy[(int64_t)y * ny + k] = v;
+        qyt[(int64_t)k * ny + y] = v;
+    }
+    for (int64_t k = first; k < nx; k += stride) {
+        (void)basis(nx, per, 0, (int)k, &th);
+        ex[k] = 2.0 * a.coarse.cx * (1.0 - cos(th));
+    }
+    for (int64_t k = first; k < ny; k += stride) {
+        (void)basis(ny, per, 0, (int)k, &th);
+        ey[k] = 2.0 * a.coarse.cy * (1.0 - cos(th));
+    }
+}
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+// C[M x N] = A[M x K] B[K x N] (row-major, leading dimensions lda, ldb, ldc) by the whole workgroup
+// on v_mfma_f64_16x16x4f64 (lane l holds A[l%16][l/16] and B[l/16][l%16]; result item t of lane l is
+// C[4t + l/16][l%16]).  Each wave takes 32 x 32 blocks of C (2 x 2 tiles) in turn; the k loop reads
+// four k-steps of fragments before their products.  Entries beyond M, N, K read as zero and are not
+// written; C[i][j] is stored as epi(i, j, value).
+template <typename F>
+__device__ __forceinline__ void gemm_f64(const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                         int ldb, double* __restrict__ C, int ldc, int M, int N, int K, F&& epi)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int bm = (M + 31) / 32, bn = (N + 31) / 32;
+    for (int blk = wave; blk < bm * bn; blk += kWavesL) {
+        const int i0 = (blk / bn) * 32, j0 = (blk % bn) * 32;
+        f64x4 acc[2][2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int s = 0; s < 2; ++s) acc[r][s] = f64x4{0.0, 0.0, 0.0, 0.0};
+        const int ia = i0 + li, ib = i0 + 16 + li, ja = j0 + li, jb = j0 + 16 + li;
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            double fa[4][2], fb[4][2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = k0 + 4 * q + lk;
+                const bool kin = k < K;
+                fa[q][0] = (kin && ia < M) ? A[(int64_t)ia * lda + k] : 0.0;
+                fa[q][1] = (kin && ib < M) ? A[(int64_t)ib * lda + k] : 0.0;
+                fb[q][0] = (kin && ja < N) ? B[(int64_t)k * ldb + ja] : 0.0;
+                fb[q][1] = (kin && jb < N) ? B[(int64_t)k * ldb + jb] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 2; ++r)
+#pragma unroll
+                    for (int s = 0; s < 2; ++s)
+                        acc[r][s] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[q][r], fb[q][s], acc[r][s], 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int i = i0 + 16 * r + 4 * t + lk, j = j0 + 16 * s + li;
+                    if (i < M && j < N) C[(int64_t)i * ldc + j] = epi(i, j, acc[r][s][t]);
+                }
+    }
+}
+
+// one Psi substep w <- M^-1 psi(w) (coarse coefficients) by the eigenbasis solve; t0, t1 scratch
+__device__ __forceinline__ void spectral_step(const KArgs& a, const LCol& col, double* __restrict__ w,
+                                              double* __restrict__ t0, double* __restrict__ t1)
+{
+    const Grid2D& g = a.g;
+    const SpecTables T = spec_tables(a);
+    const int nx = g.nx, ny = g.ny;
+    auto same = [](int, int, double v) { return v; };
+    FOR_ROWS(col, g, y)
+    {
+        const int64_t i = (int64_t)y * nx + col.x;
+        t0[i] = explicit_part(a.coarse, w[i]);
+    }
+    __syncthreads();
+    gemm_f64(T.qyt, ny, t0, nx, t1, nx, ny, nx, ny, same);  // Qy^T b
+    __syncthreads();
+    gemm_f64(t1, nx, T.qx, nx, t0, nx, ny, nx, nx,           // (.. Qx) ./ (1 + ex + ey)
+             [&](int i, int j, double v) { return v / (1.0 + (T.ex[j] + T.ey[i])); });
+    __syncthreads();
+    gemm_f64(T.qy, ny, t0, nx, t1, nx, ny, nx, ny, same);    // Qy ..
+    __syncthreads();
+    gemm_f64(t1, nx, T.qxt, nx, w, nx, ny, nx, nx, same);    // .. Qx^T
+    __syncthreads();
+}
+
 __device__ __forceinline__ long long psi_large(const KArgs& a, const LCol& col, double* w, const LScratch& sc,
                                                int64_t task, double* red, int& slot)
 {
     long long its = 0;
-    for (int q = 0; q < a.substeps; ++q)
-        its += step_large64(a, a.coarse, a.rtol2_coarse, col, w, sc.vec(task, 0), sc.vec(task, 1), sc.vec(task, 2),
-                            sc.vec(task, 3), red, slot);
+    for (int q = 0; q < a.substeps; ++q) {
+        if (a.spectral)
+            spectral_step(a, col, w, sc.vec(task, 0), sc.vec(task, 1));
+        else
+            its += step_large64(a, a.coarse, a.rtol2_coarse, col, w, sc.vec(task, 0), sc.vec(task, 1),
+                                sc.vec(task, 2), sc.vec(task, 3), red, slot);
+    }
     return its;
 }
 
@@ -499,6 +667,7 @@ void launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t
 
 void launch_coarse_large(const KArgs& a, hipStream_t s)
 {
+    if (a.spectral) hipLaunchKernelGGL(spectral_tables_kernel, dim3(64), dim3(256), 0, s, a);
     if (a.fas && a.NT >= 1) hipLaunchKernelGGL(tau_large_kernel, dim3(a.NT), dim3(kBlockL), 0, s, a, scratch_of(a));
     hipLaunchKernelGGL(coarse_large_kernel, dim3(a.NT + 1), dim3(kBlockL), 0, s, a, scratch_of(a));
 }

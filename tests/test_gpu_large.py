@@ -55,12 +55,15 @@ def test_large_sweeps_match_oracle(atm, orc, case):
     assert_close(host(y3)[1:], y_of(orc, p, o, u_c)[1:], what="correction y")
 
 
+@pytest.mark.parametrize("solver", [0, 1], ids=["eigenbasis", "cg"])
 @pytest.mark.parametrize("form", [1, 2])
 @pytest.mark.parametrize("case", LARGE, ids=ids)
-def test_large_coarse_solves_match_oracle(atm, orc, case, form):
+def test_large_coarse_solves_match_oracle(atm, orc, case, form, solver):
+    """Psi's implicit solve by the eigenbasis of the constant-coefficient operator (exact to rounding) or by
+    CG (to rtol 1e-14, as the oracle's): both give the oracle's local solves."""
     kind, nx, ny, nt, m, k = case
     p, u0 = small(kind, nx, ny, nt)
-    o = W.Options(m=m, k=k, coarse_form=form, coarse_substeps=2 if kind == W.AC2D else 1)
+    o = W.Options(m=m, k=k, coarse_form=form, coarse_substeps=2 if kind == W.AC2D else 1, coarse_solver=solver)
     NT = p.nt // m
     g = W.initial_guess(p, u0, "random", seed=4) * 0.5
     g[0] = u0

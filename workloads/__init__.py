@@ -68,6 +68,7 @@ class Options:
     coarse_form: int = 0    # 0 auto (linear for heat, FAS for Allen-Cahn), 1 linear, 2 FAS, 3 learned
     precision: int = 0      # 0 FP64 throughout, 1 FP32 fine sweeps + FP64 residual/correction
     profile: int = 0        # 1: the GPU solve times every kernel launch with HIP events
+    coarse_solver: int = 0  # Psi's implicit solve: 0 auto (eigenbasis solve on large grids), 1 CG
     coarse_cg_rtol: float = 0.0  # CG tolerance inside Psi; 0 = the problem's cg_rtol
     mixed_cg_rtol: float = 0.0   # precision 1: FP32 CG tolerance of the fine correction solves; 0 = 1e-6
     fallback_ratio: float = 0.0  # coarse_form 3: stagnation ratio that switches to the plain Psi; 0 = 0.95
