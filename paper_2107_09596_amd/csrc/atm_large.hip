@@ -352,8 +352,9 @@ __global__ __launch_bounds__(kBlockL) void sweep_large_mixed_kernel(KArgs a, LSc
 // points) the real Fourier basis, column 0 constant, columns 2m-1 / 2m cos / sin of 2 pi m x / n,
 // (and for even n the last column (-1)^x), angle 2 pi m / n.  The 5-point operator
 // M v = (1 + 2cx + 2cy) v - cx (w + e) - cy (n + s) has the eigenvalue
-// 1 + ex[kx] + ey[ky], e = 2c (1 - cos theta), on Qy[:, ky] (x) Qx[:, kx], so with the field b as
-// an ny x nx matrix, M^-1 b = Qy ((Qy^T b Qx) ./ (1 + ex + ey)) Qx^T: four dense products.
+// 1 + 2cx ex[kx] + 2cy ey[ky], e = 1 - cos theta, on Qy[:, ky] (x) Qx[:, kx], so with the field b as
+// an ny x nx matrix, M^-1 b = Qy ((Qy^T b Qx) ./ mu) Qx^T: four dense products; and as the bases
+// are orthonormal, |M^-1 b| = |(Qy^T b Qx) ./ mu|: two.
 // ---------------------------------------------------------------------------
 
 constexpr double kPi = 3.14159265358979323846;
@@ -422,11 +423,11 @@ __global__ __launch_bounds__(256) void spectral_tables_kernel(KArgs a)
     }
     for (int64_t k = first; k < nx; k += stride) {
         (void)basis(nx, per, 0, (int)k, &th);
-        ex[k] = 2.0 * a.coarse.cx * (1.0 - cos(th));
+        ex[k] = 1.0 - cos(th);
     }
     for (int64_t k = first; k < ny; k += stride) {
         (void)basis(ny, per, 0, (int)k, &th);
-        ey[k] = 2.0 * a.coarse.cy * (1.0 - cos(th));
+        ey[k] = 1.0 - cos(th);
     }
 }
 
@@ -499,8 +500,9 @@ __device__ __forceinline__ void spectral_step(const KArgs& a, const LCol& col, d
     __syncthreads();
     gemm_f64(T.qyt, ny, t0, nx, t1, nx, ny, nx, ny, same);  // Qy^T b
     __syncthreads();
-    gemm_f64(t1, nx, T.qx, nx, t0, nx, ny, nx, nx,           // (.. Qx) ./ (1 + ex + ey)
-             [&](int i, int j, double v) { return v / (1.0 + (T.ex[j] + T.ey[i])); });
+    const double cx2 = 2.0 * a.coarse.cx, cy2 = 2.0 * a.coarse.cy;
+    gemm_f64(t1, nx, T.qx, nx, t0, nx, ny, nx, nx,           // (.. Qx) ./ mu
+             [&](int i, int j, double v) { return v / (1.0 + (cx2 * T.ex[j] + cy2 * T.ey[i])); });
     __syncthreads();
     gemm_f64(T.qy, ny, t0, nx, t1, nx, ny, nx, ny, same);    // Qy ..
     __syncthreads();
@@ -622,7 +624,30 @@ __global__ __launch_bounds__(kBlockL) void step_residual_large_kernel(KArgs a, L
     const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
     double acc = 0.0;
     long long its = 0;
-    for (int64_t t = 1; t <= total; ++t) {
+    if (a.spectral) {
+        // |M^-1 rho|^2 = |(Qy^T rho Qx) ./ mu|^2 (fine coefficients), the sum taken over each
+        // thread's entries in a fixed order
+        const SpecTables T = spec_tables(a);
+        const double cx2 = 2.0 * a.fine.cx, cy2 = 2.0 * a.fine.cy;
+        for (int64_t t = 1; t <= total; ++t) {
+            const int64_t i0 = j * a.m + t;
+            FOR_ROWS(col, g, y)
+            {
+                const int64_t i = (int64_t)y * g.nx + col.x;
+                r[i] = explicit_part(a.fine, a.u[(i0 - 1) * n + i]) - stencil_g(g, a.fine, col, a.u + i0 * n, y);
+            }
+            __syncthreads();
+            gemm_f64(T.qyt, g.ny, r, g.nx, x, g.nx, g.ny, g.nx, g.ny, [](int, int, double v) { return v; });
+            __syncthreads();
+            gemm_f64(x, g.nx, T.qx, g.nx, r, g.nx, g.ny, g.nx, g.nx, [&](int i, int jj, double v) {
+                const double c = v / (1.0 + (cx2 * T.ex[jj] + cy2 * T.ey[i]));
+                acc += c * c;
+                return c;
+            });
+            __syncthreads();
+        }
+    }
+    for (int64_t t = 1; t <= (a.spectral ? 0 : total); ++t) {
         const int64_t i0 = j * a.m + t;
         FOR_ROWS(col, g, y)
         {
@@ -679,6 +704,7 @@ void launch_sequential_large(const KArgs& a, hipStream_t s)
 
 void launch_step_residual_large(const KArgs& a, int64_t n_tasks, hipStream_t s)
 {
+    if (a.spectral) hipLaunchKernelGGL(spectral_tables_kernel, dim3(64), dim3(256), 0, s, a);
     hipLaunchKernelGGL(step_residual_large_kernel, dim3(n_tasks), dim3(kBlockL), 0, s, a, scratch_of(a));
     hipLaunchKernelGGL(sum_partials_large_kernel, dim3(1), dim3(256), 0, s, a, n_tasks);
 }
