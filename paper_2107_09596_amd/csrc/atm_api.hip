@@ -71,8 +71,8 @@ bool use_fas(const atm_problem* p, const atm_options* o)
 
 bool learned(const atm_options* o) { return o->coarse_form == 3; }
 
-// Psi's implicit solve by the eigenbasis (large grids, coarse_solver 0)
-bool spectral(const atm_problem* p, const atm_options* o) { return large_grid(p) && o->coarse_solver == 0; }
+// Psi's implicit solve by the eigenbasis of the constant-coefficient operator (2D kinds, coarse_solver 0)
+bool spectral(const atm_problem* p, const atm_options* o) { return p->kind != ATM_HEAT1D && o->coarse_solver == 0; }
 
 Layout layout(const atm_problem* p, const atm_options* o)
 {
@@ -206,11 +206,12 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
     const double mrtol = o->mixed_cg_rtol > 0.0 ? o->mixed_cg_rtol : kMixedRtolDefault;
     a.rtol2_mixed = mrtol * mrtol;
     a.maxit = p->cg_max_iter;
+    a.spectral = spectral(p, o) ? 1 : 0;
+    a.spec = a.spectral ? (double*)(base + L.spec) : nullptr;
     if (large_grid(p)) {
         a.large = 1;
         a.large_scratch = (double*)(base + L.large);
-        a.spectral = spectral(p, o) ? 1 : 0;
-        a.spec = a.spectral ? (double*)(base + L.spec) : nullptr;
+
         a.g.nx = p->nx;
         a.g.ny = p->ny;
         a.g.periodic = (p->kind == ATM_AC2D);
@@ -293,6 +294,7 @@ atm_status do_coarse(atm::KArgs a, double* u, double* y, double* e, hipStream_t 
         atm::launch_coarse_large(a, s);
         return check_launch();
     }
+    if (a.spectral) atm::launch_spectral_tables(a, s);
     if (a.fas) {
         atm::launch_tau(a, s);
         atm_status st = check_launch();
@@ -598,8 +600,8 @@ Body phase_body(const Inst& in, int ph)
         case PH_S0:
         case PH_S2:
         case PH_S1: return in.cls == CLS_1D ? kSweep1D : (in.mixed ? kSweep2D : kSweep2D64);
-        case PH_TAU: return kTau2D;
-        case PH_C: return in.cls == CLS_1D ? kCoarse1D : kCoarse2D;
+        case PH_TAU: return spectral(&in.p, &in.o) ? kTau2DSpec : kTau2D;
+        case PH_C: return in.cls == CLS_1D ? kCoarse1D : (spectral(&in.p, &in.o) ? kCoarse2DSpec : kCoarse2D);
         case PH_N0:
         case PH_N: return in.mixed ? kNormI : kNormC;
         default: return in.mixed ? kNormFinalI : kNormFinalC;
@@ -1282,6 +1284,10 @@ atm_status atm_batch_create(atm_batch** out, int32_t n, const atm_problem* probs
     if (he == hipSuccess) he = hipMemcpy(B->ctl_dev, ctl.data(), n * sizeof(InstCtl), hipMemcpyHostToDevice);
     if (he == hipSuccess) he = hipMemcpy(B->nchunk_dev, nchunk.data(), n * sizeof(int), hipMemcpyHostToDevice);
     if (he != hipSuccess) return cleanup(fail(ATM_ERR_DEVICE, "batch arguments: %s", hipGetErrorString(he)));
+    // eigenbasis tables of the instances whose Psi uses them (they depend on the grid only)
+    for (int i = 0; i < n; ++i)
+        if (args[(size_t)PH_C * n + i].spectral) atm::launch_spectral_tables(args[(size_t)PH_C * n + i], B->main);
+    if ((st = check_launch())) return cleanup(st);
     if ((st = upload_tables(B))) return cleanup(st);
     *out = B;
     return ATM_OK;

@@ -45,6 +45,8 @@ enum Body {
     kNormI,      // implicit residual pieces (precision 1)
     kNormFinalC,
     kNormFinalI,
+    kCoarse2DSpec,  // windows with Psi in the eigenbasis
+    kTau2DSpec,
 };
 
 // launch body over the task table with strip template S (2D), periodic flag and small flag (every

@@ -5,6 +5,7 @@
 
 #include "atm_device.hpp"
 #include "atm_kernels.hpp"
+#include "atm_spectral.hpp"
 
 namespace atm {
 
@@ -140,16 +141,144 @@ __device__ __forceinline__ void sweep2d_body(const KArgs& a, int64_t j, double* 
     count_cg(a, its);
 }
 
-template <int S, bool EX, bool PER>
+// ---------------------------------------------------------------------------
+// On-chip eigenbasis step (grids up to 128 per side): the field is a dense row-major matrix in the
+// workgroup's LDS, row pitch P (odd, so that the 16 rows of a column fragment fall on distinct
+// banks); the products alternate a table operand (global, L2-resident) with the LDS matrix on
+// v_mfma_f64_16x16x4f64.  Output tile t = w + 8q (q < 8) of wave w: at most 64 tiles of 16 x 16.
+// ---------------------------------------------------------------------------
+
+constexpr int kSpecTiles = 8;  // output tiles per wave (8 waves: 128 x 128 at most)
+constexpr int kSpecPass = 4;   // tiles accumulated at a time
+
+// acc[q] (q < kSpecTiles) = the wave's tiles of X Y with X [M x K], Y [K x N].  XL: X is the LDS matrix D
+// (pitch P) and Y a table in global memory (leading dimension ldq); otherwise Y is D and X a table, passed
+// as its transpose Xt [K x M] so that a fragment reads 16 consecutive entries of a row.  Tile
+// t = wave + 8 q covers rows 16 (t / nt) and columns 16 (t % nt), nt = ceil(N / 16); when nt divides 8
+// every tile of a wave has the same columns and their Y fragment is read once.  Offsets are 32-bit from
+// uniform bases; four tiles are accumulated at a time.
+template <int P, bool XL>
+__device__ __forceinline__ void spec_mm(const double* __restrict__ X, const double* __restrict__ Y, int ldq, int M,
+                                        int N, int K, f64x4 (&acc)[kSpecTiles])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nt = (N + 15) >> 4, ntiles = ((M + 15) >> 4) * nt;
+    const int ldy = XL ? ldq : P;
+    const bool shared_y = (8 % nt) == 0;
+#pragma unroll
+    for (int q = 0; q < kSpecTiles; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int g = 0; g < kSpecTiles; g += kSpecPass) {
+        if (wave + 8 * g >= ntiles) break;  // uniform over the wave
+        // row offsets into X and columns of Y of this pass's tiles (-1: outside)
+        int xo[kSpecPass], yj[kSpecPass];
+#pragma unroll
+        for (int q = 0; q < kSpecPass; ++q) {
+            const int t = wave + 8 * (g + q);
+            const int i = (t / nt) * 16 + li, j = (t % nt) * 16 + li;
+            xo[q] = (t < ntiles && i < M) ? (XL ? i * P : i) : -1;
+            yj[q] = (t < ntiles && j < N) ? j : -1;
+        }
+        auto load = [&](int k0, double (&fa)[kSpecPass], double (&fb)[kSpecPass]) {
+            const int k = k0 + lk;
+            const bool kin = k < K;
+            const uint32_t yrow = (uint32_t)k * (uint32_t)ldy;
+            const uint32_t xrow = XL ? 0u : (uint32_t)k * (uint32_t)ldq;
+#pragma unroll
+            for (int q = 0; q < kSpecPass; ++q)
+                fa[q] = (kin && xo[q] >= 0) ? (XL ? X[(uint32_t)(xo[q] + k)] : X[xrow + (uint32_t)xo[q]]) : 0.0;
+            if (shared_y) {
+                const double b = (kin && yj[0] >= 0) ? Y[yrow + (uint32_t)yj[0]] : 0.0;
+#pragma unroll
+                for (int q = 0; q < kSpecPass; ++q) fb[q] = b;
+            } else {
+#pragma unroll
+                for (int q = 0; q < kSpecPass; ++q) fb[q] = (kin && yj[q] >= 0) ? Y[yrow + (uint32_t)yj[q]] : 0.0;
+            }
+        };
+#pragma unroll 1
+        for (int k0 = 0; k0 < K; k0 += 4) {
+            double fa[kSpecPass], fb[kSpecPass];
+            load(k0, fa, fb);
+#pragma unroll
+            for (int q = 0; q < kSpecPass; ++q)
+                acc[g + q] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[q], fb[q], acc[g + q], 0, 0, 0);
+        }
+    }
+}
+
+// D[i][j] = epi(i, j, acc) for the wave's tiles (result item r of lane l: row 4r + l/16, column l%16)
+template <int P, typename F>
+__device__ __forceinline__ void spec_store(double* D, int M, int N, const f64x4 (&acc)[kSpecTiles], F&& epi)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nt = (N + 15) >> 4, ntiles = ((M + 15) >> 4) * nt;
+#pragma unroll
+    for (int q = 0; q < kSpecTiles; ++q) {
+        const int t = wave + 8 * q;
+        if (t >= ntiles) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = (t / nt) * 16 + 4 * r + lk, j = (t % nt) * 16 + li;
+            if (i < M && j < N) D[i * P + j] = epi(i, j, acc[q][r]);
+        }
+    }
+}
+
+// one Psi substep x <- M^-1 psi(x) (coarse coefficients) on the strip state, exactly in the eigenbasis
+template <int S, bool EX, int P>
+__device__ __forceinline__ void spectral_step2d(const KArgs& a, const Strip& st, double (&x)[S], double* D)
+{
+    const SpecTables T = spec_tables(a);
+    const int nx = a.g.nx, ny = a.g.ny;
+    const double cx2 = 2.0 * a.coarse.cx, cy2 = 2.0 * a.coarse.cy;
+    auto same = [](int, int, double v) { return v; };
+    f64x4 acc[kSpecTiles];
+    __syncthreads();  // earlier readers of the LDS block are done
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+        if (row_ok<EX, S>(st, s)) D[(st.y0 + s) * P + st.tx] = explicit_part(a.coarse, x[s]);
+    __syncthreads();
+    spec_mm<P, false>(T.qy, D, ny, ny, nx, ny, acc);   // Qy^T b (Qy^T read through its transpose Qy)
+    __syncthreads();
+    spec_store<P>(D, ny, nx, acc, same);
+    __syncthreads();
+    spec_mm<P, true>(D, T.qx, nx, ny, nx, nx, acc);    // (.. Qx) ./ mu
+    __syncthreads();
+    spec_store<P>(D, ny, nx, acc, [&](int i, int j, double v) { return v / (1.0 + (cx2 * T.ex[j] + cy2 * T.ey[i])); });
+    __syncthreads();
+    spec_mm<P, false>(T.qyt, D, ny, ny, nx, ny, acc);  // Qy .. (read through Qy^T)
+    __syncthreads();
+    spec_store<P>(D, ny, nx, acc, same);
+    __syncthreads();
+    spec_mm<P, true>(D, T.qxt, nx, ny, nx, nx, acc);   // .. Qx^T
+    __syncthreads();
+    spec_store<P>(D, ny, nx, acc, same);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S; ++s) x[s] = row_ok<EX, S>(st, s) ? D[(st.y0 + s) * P + st.tx] : 0.0;
+    __syncthreads();  // the LDS block is free again (the CG's staging may follow)
+}
+
+// Psi: s substeps, by CG or (SP) in the eigenbasis; the two are separate instantiations so that each
+// kernel's registers serve one solver
+template <int S, bool EX, bool PER, int COLS, bool SP>
 __device__ __forceinline__ long long psi2d(const KArgs& a, const Strip& st, Strip2DState<S>& v, double* lp,
                                            double* red, int& slot)
 {
     long long its = 0;
-    for (int q = 0; q < a.substeps; ++q) its += step2d<S, EX, PER>(a, a.coarse, a.rtol2_coarse, st, v, lp, red, slot);
+    for (int q = 0; q < a.substeps; ++q) {
+        if constexpr (SP)
+            spectral_step2d<S, EX, COLS - 1>(a, st, v.x, lp);
+        else
+            its += step2d<S, EX, PER>(a, a.coarse, a.rtol2_coarse, st, v, lp, red, slot);
+    }
     return its;
 }
 
-template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2>
+template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2, bool SP = false>
 __device__ __forceinline__ void coarse2d_body(const KArgs& a, int64_t p, double* lp, double* red)
 {
     int slot = 0;
@@ -169,7 +298,7 @@ __device__ __forceinline__ void coarse2d_body(const KArgs& a, int64_t p, double*
     }
     long long its = 0;
     for (int64_t jj = s0 + 1; jj <= p; ++jj) {
-        its += psi2d<S, EX, PER>(a, st, v, lp, red, slot);
+        its += psi2d<S, EX, PER, COLS, SP>(a, st, v, lp, red, slot);
         const int64_t off = opaque_off(st.gbase);
 #pragma unroll
         for (int s = 0; s < S; ++s)
@@ -187,7 +316,7 @@ __device__ __forceinline__ void coarse2d_body(const KArgs& a, int64_t p, double*
     count_cg(a, its);
 }
 
-template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2>
+template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2, bool SP = false>
 __device__ __forceinline__ void tau2d_body(const KArgs& a, int64_t j, double* lp, double* red)
 {
     int slot = 0;
@@ -200,7 +329,7 @@ __device__ __forceinline__ void tau2d_body(const KArgs& a, int64_t j, double* lp
         v.x[s] = 0.0;
         if (row_ok<EX, S>(st, s)) v.x[s] = a.u[((j - 1) * a.m) * a.n + (int64_t)(st.gbase + s * nx)];
     }
-    long long its = psi2d<S, EX, PER>(a, st, v, lp, red, slot);
+    long long its = psi2d<S, EX, PER, COLS, SP>(a, st, v, lp, red, slot);
 #pragma unroll
     for (int s = 0; s < S; ++s)
         if (row_ok<EX, S>(st, s)) {

@@ -7,6 +7,7 @@
 // fine point written once per sweep and never re-read by the sweep.
 #include "atm_device.hpp"
 #include "atm_kernels.hpp"
+#include "atm_spectral.hpp"
 #include "atm_bodies.hpp"
 
 namespace atm {
@@ -85,6 +86,23 @@ __global__ __launch_bounds__(kBlock2D) void tau2d_kernel(KArgs a)
     __shared__ __align__(16) double lp[Lds2D<double>::size];
     __shared__ double red[4 * kWaves2D];
     tau2d_body<S, EX, PER>(a, blockIdx.x + 1, lp, red);  // windows 1..N_T
+}
+
+// the same with Psi in the eigenbasis
+template <int S, bool EX, bool PER>
+__global__ __launch_bounds__(kBlock2D) void coarse2d_spec_kernel(KArgs a)
+{
+    __shared__ __align__(16) double lp[Lds2D<double>::size];
+    __shared__ double red[4 * kWaves2D];
+    coarse2d_body<S, EX, PER, kMaxSide2D + 2, true>(a, blockIdx.x, lp, red);
+}
+
+template <int S, bool EX, bool PER>
+__global__ __launch_bounds__(kBlock2D) void tau2d_spec_kernel(KArgs a)
+{
+    __shared__ __align__(16) double lp[Lds2D<double>::size];
+    __shared__ double red[4 * kWaves2D];
+    tau2d_body<S, EX, PER, kMaxSide2D + 2, true>(a, blockIdx.x + 1, lp, red);
 }
 
 template <int S, bool EX, bool PER>
@@ -197,6 +215,8 @@ void launch_tau(const KArgs& a, hipStream_t s)
     if (a.NT < 1) return;
     if (a.is1d)
         hipLaunchKernelGGL(tau1d_kernel, dim3(a.NT), dim3(block1d(a)), 0, s, a);
+    else if (a.spectral)
+        ATM_LAUNCH_2D(tau2d_spec_kernel, a.NT, s, a);
     else
         ATM_LAUNCH_2D(tau2d_kernel, a.NT, s, a);
 }
@@ -205,6 +225,8 @@ void launch_coarse(const KArgs& a, hipStream_t s)
 {
     if (a.is1d)
         hipLaunchKernelGGL(coarse1d_kernel, dim3(a.NT + 1), dim3(block1d(a)), 0, s, a);
+    else if (a.spectral)
+        ATM_LAUNCH_2D(coarse2d_spec_kernel, a.NT + 1, s, a);
     else
         ATM_LAUNCH_2D(coarse2d_kernel, a.NT + 1, s, a);
 }
@@ -221,6 +243,53 @@ void launch_sequential(const KArgs& a, hipStream_t s)
         hipLaunchKernelGGL(seq1d_kernel, dim3(1), dim3(block1d(a)), 0, s, a);
     else
         ATM_LAUNCH_2D(seq2d_kernel, 1, s, a);
+}
+
+// ---------------------------------------------------------------------------
+// eigenbasis tables of the 2D operator (see atm_spectral.hpp): they depend on the grid only
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void spectral_tables_kernel(KArgs a)
+{
+    const int nx = a.g.nx, ny = a.g.ny;
+    const bool per = a.g.periodic != 0;
+    double* qx = a.spec;
+    double* qxt = qx + (int64_t)nx * nx;
+    double* qy = qxt + (int64_t)nx * nx;
+    double* qyt = qy + (int64_t)ny * ny;
+    double* ex = qyt + (int64_t)ny * ny;
+    double* ey = ex + nx;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double th;
+    for (int64_t i = first; i < (int64_t)nx * nx; i += stride) {
+        const int x = (int)(i / nx), k = (int)(i % nx);
+        const double v = basis(nx, per, x, k, &th);
+        qx[(int64_t)x * nx + k] = v;
+        qxt[(int64_t)k * nx + x] = v;
+    }
+    for (int64_t i = first; i < (int64_t)ny * ny; i += stride) {
+        const int y = (int)(i / ny), k = (int)(i % ny);
+        const double v = basis(ny, per, y, k, &th);
+        qy[(int64_t)y * ny + k] = v;
+        qyt[(int64_t)k * ny + y] = v;
+    }
+    for (int64_t k = first; k < nx; k += stride) {
+        (void)basis(nx, per, 0, (int)k, &th);
+        ex[k] = 1.0 - cos(th);
+    }
+    for (int64_t k = first; k < ny; k += stride) {
+        (void)basis(ny, per, 0, (int)k, &th);
+        ey[k] = 1.0 - cos(th);
+    }
+}
+
+
+size_t spectral_table_doubles(int nx, int ny) { return 2 * (size_t)nx * nx + 2 * (size_t)ny * ny + nx + ny; }
+
+void launch_spectral_tables(const KArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(spectral_tables_kernel, dim3(64), dim3(256), 0, s, a);
 }
 
 }  // namespace atm

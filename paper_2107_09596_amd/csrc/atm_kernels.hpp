@@ -139,8 +139,9 @@ void launch_step_residual(const KArgs& a, int64_t n_tasks, hipStream_t s);
 constexpr int kMaxSideLarge = 1024;
 void launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t s);
 void launch_coarse_large(const KArgs& a, hipStream_t s);
-// doubles of the eigenbasis tables of an nx x ny grid (KArgs::spec)
+// doubles of the eigenbasis tables of an nx x ny grid (KArgs::spec), and their construction
 size_t spectral_table_doubles(int nx, int ny);
+void launch_spectral_tables(const KArgs& a, hipStream_t s);
 void launch_sequential_large(const KArgs& a, hipStream_t s);
 void launch_step_residual_large(const KArgs& a, int64_t n_tasks, hipStream_t s);
 

@@ -11,6 +11,7 @@
 // steps with FP64 update (precision 1), FP64 coarse steps.
 #include "atm_device.hpp"
 #include "atm_kernels.hpp"
+#include "atm_spectral.hpp"
 
 namespace atm {
 
@@ -344,101 +345,13 @@ __global__ __launch_bounds__(kBlockL) void sweep_large_mixed_kernel(KArgs a, LSc
     count_cg(a, its);
 }
 
-// ---------------------------------------------------------------------------
-// Psi's implicit solve in the eigenbasis of M = I - dT nu L (constant coefficients).
-//
-// The 1D second differences are diagonalised by orthonormal bases: Dirichlet (n interior points)
-// Q[x][k] = sqrt(2/(n+1)) sin(pi (x+1)(k+1)/(n+1)), angle theta_k = pi (k+1)/(n+1); periodic (n
-// points) the real Fourier basis, column 0 constant, columns 2m-1 / 2m cos / sin of 2 pi m x / n,
-// (and for even n the last column (-1)^x), angle 2 pi m / n.  The 5-point operator
-// M v = (1 + 2cx + 2cy) v - cx (w + e) - cy (n + s) has the eigenvalue
-// 1 + 2cx ex[kx] + 2cy ey[ky], e = 1 - cos theta, on Qy[:, ky] (x) Qx[:, kx], so with the field b as
-// an ny x nx matrix, M^-1 b = Qy ((Qy^T b Qx) ./ mu) Qx^T: four dense products; and as the bases
-// are orthonormal, |M^-1 b| = |(Qy^T b Qx) ./ mu|: two.
-// ---------------------------------------------------------------------------
-
-constexpr double kPi = 3.14159265358979323846;
-
-struct SpecTables {
-    const double *qx, *qxt, *qy, *qyt, *ex, *ey;
-};
-
-__device__ __forceinline__ SpecTables spec_tables(const KArgs& a)
-{
-    const int64_t nx = a.g.nx, ny = a.g.ny;
-    SpecTables t;
-    t.qx = a.spec;
-    t.qxt = t.qx + nx * nx;
-    t.qy = t.qxt + nx * nx;
-    t.qyt = t.qy + ny * ny;
-    t.ex = t.qyt + ny * ny;
-    t.ey = t.ex + nx;
-    return t;
-}
-
-size_t spectral_table_doubles(int nx, int ny) { return 2 * (size_t)nx * nx + 2 * (size_t)ny * ny + nx + ny; }
-
-// basis entry Q[x][k] and mode angle of column k
-__device__ __forceinline__ double basis(int n, bool periodic, int x, int k, double* theta)
-{
-    if (!periodic) {
-        // angles reduced with integer arithmetic: pi t / (n + 1), t = (x+1)(k+1) mod 2(n+1)
-        const int64_t t = ((int64_t)(x + 1) * (k + 1)) % (2 * (int64_t)(n + 1));
-        *theta = kPi * (double)(k + 1) / (double)(n + 1);
-        return sqrt(2.0 / (double)(n + 1)) * sin(kPi * (double)t / (double)(n + 1));
-    }
-    const int m = (k + 1) / 2;
-    *theta = 2.0 * kPi * (double)m / (double)n;
-    if (k == 0) return sqrt(1.0 / (double)n);
-    const int64_t t = ((int64_t)m * x) % n;
-    const double ang = 2.0 * kPi * (double)t / (double)n;
-    if (2 * m == n) return sqrt(1.0 / (double)n) * ((x & 1) ? -1.0 : 1.0);
-    return sqrt(2.0 / (double)n) * ((k & 1) ? cos(ang) : sin(ang));
-}
-
-__global__ __launch_bounds__(256) void spectral_tables_kernel(KArgs a)
-{
-    const int nx = a.g.nx, ny = a.g.ny;
-    const bool per = a.g.periodic != 0;
-    double* qx = a.spec;
-    double* qxt = qx + (int64_t)nx * nx;
-    double* qy = qxt + (int64_t)nx * nx;
-    double* qyt = qy + (int64_t)ny * ny;
-    double* ex = qyt + (int64_t)ny * ny;
-    double* ey = ex + nx;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double th;
-    for (int64_t i = first; i < (int64_t)nx * nx; i += stride) {
-        const int x = (int)(i / nx), k = (int)(i % nx);
-        const double v = basis(nx, per, x, k, &th);
-        qx[(int64_t)x * nx + k] = v;
-        qxt[(int64_t)k * nx + x] = v;
-    }
-    for (int64_t i = first; i < (int64_t)ny * ny; i += stride) {
-        const int y = (int)(i / ny), k = (int)(i % ny);
-        const double v = basis(ny, per, y, k, &th);
-        qy[(int64_t)y * ny + k] = v;
-        qyt[(int64_t)k * ny + y] = v;
-    }
-    for (int64_t k = first; k < nx; k += stride) {
-        (void)basis(nx, per, 0, (int)k, &th);
-        ex[k] = 1.0 - cos(th);
-    }
-    for (int64_t k = first; k < ny; k += stride) {
-        (void)basis(ny, per, 0, (int)k, &th);
-        ey[k] = 1.0 - cos(th);
-    }
-}
-
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
 // C[M x N] = A[M x K] B[K x N] (row-major, leading dimensions lda, ldb, ldc) by the whole workgroup
 // on v_mfma_f64_16x16x4f64 (lane l holds A[l%16][l/16] and B[l/16][l%16]; result item t of lane l is
 // C[4t + l/16][l%16]).  Each wave takes 32 x 32 blocks of C (2 x 2 tiles) in turn; the k loop reads
 // four k-steps of fragments before their products.  Entries beyond M, N, K read as zero and are not
-// written; C[i][j] is stored as epi(i, j, value).
-template <typename F>
+// written; C[i][j] is stored as epi(i, j, value).  AT: A is passed as its transpose [K x M] (leading
+// dimension lda), so that a fragment reads 16 consecutive entries of a row.
+template <bool AT = false, typename F>
 __device__ __forceinline__ void gemm_f64(const double* __restrict__ A, int lda, const double* __restrict__ B,
                                          int ldb, double* __restrict__ C, int ldc, int M, int N, int K, F&& epi)
 {
@@ -459,8 +372,8 @@ __device__ __forceinline__ void gemm_f64(const double* __restrict__ A, int lda, 
             for (int q = 0; q < 4; ++q) {
                 const int k = k0 + 4 * q + lk;
                 const bool kin = k < K;
-                fa[q][0] = (kin && ia < M) ? A[(int64_t)ia * lda + k] : 0.0;
-                fa[q][1] = (kin && ib < M) ? A[(int64_t)ib * lda + k] : 0.0;
+                fa[q][0] = (kin && ia < M) ? (AT ? A[(int64_t)k * lda + ia] : A[(int64_t)ia * lda + k]) : 0.0;
+                fa[q][1] = (kin && ib < M) ? (AT ? A[(int64_t)k * lda + ib] : A[(int64_t)ib * lda + k]) : 0.0;
                 fb[q][0] = (kin && ja < N) ? B[(int64_t)k * ldb + ja] : 0.0;
                 fb[q][1] = (kin && jb < N) ? B[(int64_t)k * ldb + jb] : 0.0;
             }
@@ -498,13 +411,13 @@ __device__ __forceinline__ void spectral_step(const KArgs& a, const LCol& col, d
         t0[i] = explicit_part(a.coarse, w[i]);
     }
     __syncthreads();
-    gemm_f64(T.qyt, ny, t0, nx, t1, nx, ny, nx, ny, same);  // Qy^T b
+    gemm_f64<true>(T.qy, ny, t0, nx, t1, nx, ny, nx, ny, same);  // Qy^T b (read through Qy)
     __syncthreads();
     const double cx2 = 2.0 * a.coarse.cx, cy2 = 2.0 * a.coarse.cy;
     gemm_f64(t1, nx, T.qx, nx, t0, nx, ny, nx, nx,           // (.. Qx) ./ mu
              [&](int i, int j, double v) { return v / (1.0 + (cx2 * T.ex[j] + cy2 * T.ey[i])); });
     __syncthreads();
-    gemm_f64(T.qy, ny, t0, nx, t1, nx, ny, nx, ny, same);    // Qy ..
+    gemm_f64<true>(T.qyt, ny, t0, nx, t1, nx, ny, nx, ny, same); // Qy .. (read through Qy^T)
     __syncthreads();
     gemm_f64(t1, nx, T.qxt, nx, w, nx, ny, nx, nx, same);    // .. Qx^T
     __syncthreads();
@@ -637,7 +550,7 @@ __global__ __launch_bounds__(kBlockL) void step_residual_large_kernel(KArgs a, L
                 r[i] = explicit_part(a.fine, a.u[(i0 - 1) * n + i]) - stencil_g(g, a.fine, col, a.u + i0 * n, y);
             }
             __syncthreads();
-            gemm_f64(T.qyt, g.ny, r, g.nx, x, g.nx, g.ny, g.nx, g.ny, [](int, int, double v) { return v; });
+            gemm_f64<true>(T.qy, g.ny, r, g.nx, x, g.nx, g.ny, g.nx, g.ny, [](int, int, double v) { return v; });
             __syncthreads();
             gemm_f64(x, g.nx, T.qx, g.nx, r, g.nx, g.ny, g.nx, g.nx, [&](int i, int jj, double v) {
                 const double c = v / (1.0 + (cx2 * T.ex[jj] + cy2 * T.ey[i]));
@@ -692,7 +605,7 @@ void launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t
 
 void launch_coarse_large(const KArgs& a, hipStream_t s)
 {
-    if (a.spectral) hipLaunchKernelGGL(spectral_tables_kernel, dim3(64), dim3(256), 0, s, a);
+    if (a.spectral) launch_spectral_tables(a, s);
     if (a.fas && a.NT >= 1) hipLaunchKernelGGL(tau_large_kernel, dim3(a.NT), dim3(kBlockL), 0, s, a, scratch_of(a));
     hipLaunchKernelGGL(coarse_large_kernel, dim3(a.NT + 1), dim3(kBlockL), 0, s, a, scratch_of(a));
 }
@@ -704,7 +617,7 @@ void launch_sequential_large(const KArgs& a, hipStream_t s)
 
 void launch_step_residual_large(const KArgs& a, int64_t n_tasks, hipStream_t s)
 {
-    if (a.spectral) hipLaunchKernelGGL(spectral_tables_kernel, dim3(64), dim3(256), 0, s, a);
+    if (a.spectral) launch_spectral_tables(a, s);
     hipLaunchKernelGGL(step_residual_large_kernel, dim3(n_tasks), dim3(kBlockL), 0, s, a, scratch_of(a));
     hipLaunchKernelGGL(sum_partials_large_kernel, dim3(1), dim3(256), 0, s, a, n_tasks);
 }

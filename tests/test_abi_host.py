@@ -48,7 +48,12 @@ def test_num_intervals_and_workspace(abi):
     assert abi.lib().atm_num_intervals(ctypes.byref(P), ctypes.byref(O)) == 128
     ws = abi.lib().atm_workspace_bytes(ctypes.byref(P), ctypes.byref(O))
     slab = 129 * 128 * 128 * 8
-    assert 3 * slab <= ws <= 3 * slab + 64 * 1024
+    tables = (2 * 128 * 128 * 2 + 2 * 128) * 8  # eigenbasis tables of Psi's solve: Qx, Qx^T, Qy, Qy^T, ex, ey
+    assert 3 * slab + tables <= ws <= 3 * slab + tables + 64 * 1024
+    o.coarse_solver = 1  # Psi by CG: no tables
+    ws_cg = abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(o)))
+    assert 3 * slab <= ws_cg <= 3 * slab + 64 * 1024 and ws - ws_cg >= tables
+    o.coarse_solver = 0
     o.coarse_form = 2
     ws_fas = abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(o)))
     assert ws_fas >= ws + slab
@@ -56,7 +61,7 @@ def test_num_intervals_and_workspace(abi):
 
 @pytest.mark.parametrize("field,value,status", [
     ("m", 1, -1), ("k", 0, -1), ("relax", 2, -1), ("coarse_substeps", 0, -1), ("max_iter", -1, -1),
-    ("precision", 3, -1), ("mixed_cg_rtol", -1.0, -1), ("mixed_cg_rtol", 1.0, -1),
+    ("precision", 3, -1), ("mixed_cg_rtol", -1.0, -1), ("mixed_cg_rtol", 1.0, -1), ("coarse_solver", 2, -1),
     ("precision", 1, -2),  # the FP32 fine form is built for the 2D kinds only
 ])
 def test_invalid_options_rejected_before_launch(abi, field, value, status):

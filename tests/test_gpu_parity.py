@@ -107,14 +107,16 @@ def test_sweeps_match_oracle(atm, orc, case):
     assert_close(host(y3)[1:], y_of(orc, p, o, u_c)[1:], what="correction y")
 
 
-@pytest.mark.parametrize("crtol", [0.0, 1e-13])
+@pytest.mark.parametrize("solver", [(0, 0.0), (1, 0.0), (1, 1e-13)], ids=["eigenbasis", "cg", "cg-1e-13"])
 @pytest.mark.parametrize("form", [1, 2])
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"k{c[0]}-{c[1]}x{c[2]}-nt{c[3]}-m{c[4]}-k{c[5]}")
-def test_coarse_solves_match_oracle(atm, orc, case, form, crtol):
+def test_coarse_solves_match_oracle(atm, orc, case, form, solver):
+    """Psi's implicit solve in the eigenbasis (exact to rounding) or by CG (to the problem's rtol 1e-14, or 1e-13):
+    the windows match the oracle's local solves (its Psi by CG to rtol 1e-14)."""
     kind, nx, ny, nt, m, k = case
     p, u0 = small(kind, nx, ny, nt)
     o = W.Options(m=m, k=k, relax=1, coarse_form=form, coarse_substeps=2 if kind == W.AC2D else 1,
-                  coarse_cg_rtol=crtol)
+                  coarse_solver=solver[0], coarse_cg_rtol=solver[1])
     NT = p.nt // m
     g = W.initial_guess(p, u0, "random", seed=4) * 0.5
     g[0] = u0
@@ -273,9 +275,10 @@ def test_error_paths(atm):
 
 
 def test_c2_loose_coarse_tolerance_same_fixed_point(atm, orc):
-    """coarse_cg_rtol = 1e-6 (the benchmarked setting): same cycle count as the strict solve on the 2D heat
-    workload, and the result still has a residual below tol by the oracle's own integrator."""
+    """Psi by CG to coarse_cg_rtol = 1e-6: same cycle count as the strict solve on the 2D heat workload, and
+    the result still has a residual below tol by the oracle's own integrator."""
     p, o, u0 = W.config("c2")
+    o.coarse_solver = 1
     strict = dev(W.initial_guess(p, u0))
     _, hs, ss = atm.atm_solve(p, o, strict)
     o.coarse_cg_rtol = 1e-6
