@@ -40,7 +40,7 @@ FLOPS_PER_CG_ITER_POINT = 20
 FLOPS_PER_SOLVE_POINT = 14
 # HBM bytes per launch of the FP64 sweep kernel on this workload (read, written), from rocprofv3
 # FETCH_SIZE and WRITE_SIZE counters scaled by the same counters of a plain 1 GiB copy (x2.0, x1.0)
-SWEEP_TRAFFIC_BYTES = (37.4e6, 318.4e6)
+SWEEP_TRAFFIC_BYTES = (40.8e6, 321.8e6)
 
 
 def parse():

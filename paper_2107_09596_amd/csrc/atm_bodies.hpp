@@ -116,26 +116,10 @@ __device__ __forceinline__ void sweep2d_body(const KArgs& a, int64_t j, double* 
         skip_interval(a, j, total, st.gbase, nx, EX ? S : st.nr);
         return;
     }
-    // Each step's CG starts from the linear extrapolation 2 x_{t-1} - x_{t-2} of the two previous
-    // slices (x_{t-2} was stored by this workgroup one step earlier and is read back from L2; q is
-    // free between solves); the first step starts from the C-point.  For a solution smooth in time
-    // the start is off by O(dt^2) instead of O(dt).
-    double* const base = a.u + (j * a.m) * a.n;
     long long its = 0;
     for (int64_t t = 1; t <= total; ++t) {
-#pragma unroll
-        for (int s = 0; s < S; ++s) v.r[s] = explicit_part(a.fine, v.x[s]);
-        if (t >= 2) {
-            const double* older = base + (t - 2) * a.n;
-            const int64_t off = opaque_off(st.gbase);
-#pragma unroll
-            for (int s = 0; s < S; ++s) v.q[s] = row_ok<EX, S>(st, s) ? older[off + (int64_t)s * nx] : 0.0;
-#pragma unroll
-            for (int s = 0; s < S; ++s) v.x[s] = v.x[s] + (v.x[s] - v.q[s]);
-        }
-        its += cg2d<double, S, EX, PER, true>(a.g, a.fine, st, v.x, v.r, v.q, lp, red, slot, a.rtol2, a.maxit,
-                                              a.fail);
-        double* dst = (t < a.m) ? base + t * a.n : a.y + (j + 1) * a.n;
+        its += step2d<S, EX, PER>(a, a.fine, a.rtol2, st, v, lp, red, slot);
+        double* dst = (t < a.m) ? a.u + (j * a.m + t) * a.n : a.y + (j + 1) * a.n;
         strip_store<S, EX>(dst, st, nx, v.x);
     }
     count_cg(a, its);

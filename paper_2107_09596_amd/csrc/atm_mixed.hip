@@ -38,6 +38,7 @@ __global__ __launch_bounds__(kBlock2D) void sweep2d_mixed_kernel(KArgs a)
 // Work units are numbered so that the tiles of one chunk run on one XCD (the
 // dispatcher deals workgroups to the 8 XCDs in turn) and share its L2.
 constexpr int kResidTile = 256;
+constexpr int kResidSteps = 4;
 
 __global__ __launch_bounds__(kResidTile) void implicit_residual_kernel(KArgs a, int64_t ntile, int64_t chunk,
                                                                        int64_t units)
@@ -64,17 +65,35 @@ __global__ __launch_bounds__(kResidTile) void implicit_residual_kernel(KArgs a, 
     const StepCoef c = a.fine;
     double acc = 0.0;
     if (act) {
-        double prev = a.u[(i0 - 1) * a.n + idx];
-        for (int64_t i = i0; i <= i1; ++i) {
-            const double* ui = a.u + i * a.n;
-            const double cen = ui[idx];
-            const double wv = ow >= 0 ? ui[ow] : 0.0;
-            const double ev = oe >= 0 ? ui[oe] : 0.0;
-            const double nv = on >= 0 ? ui[on] : 0.0;
-            const double sv = os >= 0 ? ui[os] : 0.0;
-            const double rho = explicit_part(c, prev) - stencil_value(c, nv, cen, sv, wv, ev);
-            acc += rho * rho;
-            prev = cen;
+        // steps in batches of kResidSteps: every load of a batch is issued before the first is used
+        // (the sum keeps the step order)
+        constexpr int B = kResidSteps;
+        const double* __restrict__ u = a.u;
+        double prev = u[(i0 - 1) * a.n + idx];
+        for (int64_t ib = i0; ib <= i1; ib += B) {
+            double cen[B], wv[B], ev[B], nv[B], sv[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const int64_t i = ib + q;
+                cen[q] = wv[q] = ev[q] = nv[q] = sv[q] = 0.0;
+                if (i <= i1) {
+                    // a uniform slice base plus 32-bit offsets (a slice holds at most 1024 x 1024 points)
+                    const double* ui = u + i * a.n;
+                    cen[q] = ui[(uint32_t)idx];
+                    if (ow >= 0) wv[q] = ui[(uint32_t)ow];
+                    if (oe >= 0) ev[q] = ui[(uint32_t)oe];
+                    if (on >= 0) nv[q] = ui[(uint32_t)on];
+                    if (os >= 0) sv[q] = ui[(uint32_t)os];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                if (ib + q <= i1) {
+                    const double rho = explicit_part(c, prev) - stencil_value(c, nv[q], cen[q], sv[q], wv[q], ev[q]);
+                    acc += rho * rho;
+                    prev = cen[q];
+                }
+            }
         }
     }
     double unused = 0.0;
