@@ -32,72 +32,107 @@ __global__ __launch_bounds__(kBlock2D) void sweep2d_mixed_kernel(KArgs a)
 }
 
 // FP64 implicit residual |rho|^2 = sum_i |psi(u_{i-1}) - M u_i|^2, i = 1..nt.
-// HBM-bound: each workgroup owns 256 consecutive points of a slice over a
-// chunk of consecutive time indices, keeps u_{i-1} in registers and reads the
-// stencil neighbours of u_i through the caches (each slice leaves HBM once).
-// Work units are numbered so that the tiles of one chunk run on one XCD (the
-// dispatcher deals workgroups to the 8 XCDs in turn) and share its L2.
-constexpr int kResidTile = 256;
-constexpr int kResidSteps = 4;
+// HBM-bound: each slice leaves HBM once.  A workgroup (4 waves) owns a tile of 64 columns x 4 kResRows
+// rows of the slice over a chunk of consecutive time indices; lane l of wave w holds column x0 + l, rows
+// y0 + w kResRows .. + kResRows - 1, and keeps the previous slice's values there in registers.  Per step
+// a lane loads its own points (coalesced over the wave) and the two halo rows; the north / south
+// neighbours come from its registers, the west / east ones from lanes l -+ 1 by DPP wave shifts (the
+// wave's edge lanes and the grid's edge columns load theirs).  Work units are numbered so that the
+// tiles of one chunk run on one XCD (the dispatcher deals workgroups to the 8 XCDs in turn) and share
+// its L2 for the halo rows.
+constexpr int kResidThreads = 256;
+constexpr int kResRows = 8;
+constexpr int kResTileRows = 4 * kResRows;
 
-__global__ __launch_bounds__(kResidTile) void implicit_residual_kernel(KArgs a, int64_t ntile, int64_t chunk,
-                                                                       int64_t units)
+// the value of v held by lane l - 1 (dir = 0) or l + 1 (dir = 1) of the wave (0 where there is none)
+__device__ __forceinline__ double wave_shift(double v, int dir)
 {
-    __shared__ double red[2 * 2 * (kResidTile / 64)];
+    const long long b = __double_as_longlong(v);
+    int lo = (int)(b & 0xffffffffll), hi = (int)(b >> 32);
+    if (dir == 0) {
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, true);  // wave_shr:1
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, true);
+    } else {
+        lo = __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, true);  // wave_shl:1
+        hi = __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, true);
+    }
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+__global__ __launch_bounds__(kResidThreads) void implicit_residual_kernel(KArgs a, int64_t ntile, int64_t chunk,
+                                                                          int64_t units)
+{
+    __shared__ double red[2 * 2 * (kResidThreads / 64)];
     int slot = 0;
     const int64_t per_xcd = gridDim.x / 8;
     const int64_t w = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     if (w >= units) return;  // whole workgroup, before any barrier
+    const int nx = a.nx;
+    const int ny = (int)(a.n / nx);
+    const int tiles_x = (nx + 63) / 64;
     const int64_t tile = w % ntile;
     const int64_t i0 = 1 + (w / ntile) * chunk;
     const int64_t i1 = (i0 + chunk - 1 < a.nt) ? i0 + chunk - 1 : a.nt;
-    const int64_t idx = tile * kResidTile + threadIdx.x;
-    const bool act = idx < a.n;
-    const int nx = a.nx;
-    const int ny = (int)(a.n / nx);
-    const int x = (int)(idx % nx), y = (int)(idx / nx);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x = (int)(tile % tiles_x) * 64 + lane;
+    const int y0 = (int)(tile / tiles_x) * kResTileRows + wv * kResRows;
     const bool per = a.g.periodic != 0;
-    // neighbour offsets (Dirichlet: -1 marks the zero boundary)
-    const int64_t ow = x > 0 ? idx - 1 : (per ? idx + nx - 1 : -1);
-    const int64_t oe = x < nx - 1 ? idx + 1 : (per ? idx - (nx - 1) : -1);
-    const int64_t on = y > 0 ? idx - nx : (per ? idx + (int64_t)(ny - 1) * nx : -1);
-    const int64_t os = y < ny - 1 ? idx + nx : (per ? idx - (int64_t)(ny - 1) * nx : -1);
+    const bool colok = x < nx;
+    // columns whose west / east neighbour is loaded: the wave's edge lanes and the grid's edge columns
+    const int xw = x == 0 ? (per ? nx - 1 : -1) : x - 1;
+    const int xe = x == nx - 1 ? (per ? 0 : -1) : x + 1;
+    const bool load_w = colok && (lane == 0 || x == 0);
+    const bool load_e = colok && (lane == 63 || x == nx - 1);
+    // halo rows: above the first row, below the last (zero outside a Dirichlet boundary)
+    const int yu = y0 == 0 ? (per ? ny - 1 : -1) : y0 - 1;
+    const int ylast = (y0 + kResRows < ny ? y0 + kResRows : ny) - 1;  // last row of the strip in the grid
+    const int yd = ylast == ny - 1 ? (per ? 0 : -1) : ylast + 1;
     const StepCoef c = a.fine;
+    const double* __restrict__ u = a.u;
+    double prev[kResRows], cen[kResRows];
     double acc = 0.0;
-    if (act) {
-        // steps in batches of kResidSteps: every load of a batch is issued before the first is used
-        // (the sum keeps the step order)
-        constexpr int B = kResidSteps;
-        const double* __restrict__ u = a.u;
-        double prev = u[(i0 - 1) * a.n + idx];
-        for (int64_t ib = i0; ib <= i1; ib += B) {
-            double cen[B], wv[B], ev[B], nv[B], sv[B];
+    // the previous slice of the chunk's first step
+    {
+        const double* up0 = u + (i0 - 1) * a.n;
 #pragma unroll
-            for (int q = 0; q < B; ++q) {
-                const int64_t i = ib + q;
-                cen[q] = wv[q] = ev[q] = nv[q] = sv[q] = 0.0;
-                if (i <= i1) {
-                    // a uniform slice base plus 32-bit offsets (a slice holds at most 1024 x 1024 points)
-                    const double* ui = u + i * a.n;
-                    cen[q] = ui[(uint32_t)idx];
-                    if (ow >= 0) wv[q] = ui[(uint32_t)ow];
-                    if (oe >= 0) ev[q] = ui[(uint32_t)oe];
-                    if (on >= 0) nv[q] = ui[(uint32_t)on];
-                    if (os >= 0) sv[q] = ui[(uint32_t)os];
-                }
-            }
+        for (int r = 0; r < kResRows; ++r) {
+            const int y = y0 + r;
+            prev[r] = (colok && y < ny) ? up0[(uint32_t)(y * nx + x)] : 0.0;
+        }
+    }
+    for (int64_t i = i0; i <= i1; ++i) {
+        const double* ui = u + i * a.n;
+        double hu = 0.0, hd = 0.0, ew[kResRows], ee[kResRows];
 #pragma unroll
-            for (int q = 0; q < B; ++q) {
-                if (ib + q <= i1) {
-                    const double rho = explicit_part(c, prev) - stencil_value(c, nv[q], cen[q], sv[q], wv[q], ev[q]);
-                    acc += rho * rho;
-                    prev = cen[q];
-                }
+        for (int r = 0; r < kResRows; ++r) {
+            const int y = y0 + r;
+            const bool ok = colok && y < ny;
+            cen[r] = ok ? ui[(uint32_t)(y * nx + x)] : 0.0;
+            ew[r] = (ok && load_w && xw >= 0) ? ui[(uint32_t)(y * nx + xw)] : 0.0;
+            ee[r] = (ok && load_e && xe >= 0) ? ui[(uint32_t)(y * nx + xe)] : 0.0;
+        }
+        if (colok && y0 < ny) {
+            if (yu >= 0) hu = ui[(uint32_t)(yu * nx + x)];
+            if (yd >= 0) hd = ui[(uint32_t)(yd * nx + x)];
+        }
+#pragma unroll
+        for (int r = 0; r < kResRows; ++r) {
+            // every lane takes part in the shifts (their sources are all lanes of the wave)
+            const double sw = wave_shift(cen[r], 0), se = wave_shift(cen[r], 1);
+            const int y = y0 + r;
+            if (colok && y < ny) {
+                const double wv_ = load_w ? ew[r] : sw;
+                const double ev_ = load_e ? ee[r] : se;
+                const double nv = r == 0 ? hu : cen[r - 1];
+                const double sv = y == ylast ? hd : cen[r + 1 < kResRows ? r + 1 : r];
+                const double rho = explicit_part(c, prev[r]) - stencil_value(c, nv, cen[r], sv, wv_, ev_);
+                acc += rho * rho;
             }
+            prev[r] = cen[r];
         }
     }
     double unused = 0.0;
-    block_sum2(acc, unused, red, slot, kResidTile / 64);
+    block_sum2(acc, unused, red, slot, kResidThreads / 64);
     if (threadIdx.x == 0) a.partials[w] = acc;
 }
 
@@ -230,7 +265,8 @@ struct ResidGrid {
 ResidGrid resid_grid(const KArgs& a)
 {
     ResidGrid r;
-    r.ntile = (a.n + kResidTile - 1) / kResidTile;
+    const int64_t ny = a.n / a.nx;
+    r.ntile = ((a.nx + 63) / 64) * ((ny + kResTileRows - 1) / kResTileRows);
     int64_t nchunk = kResidBlocks / r.ntile;
     if (nchunk < 1) nchunk = 1;
     if (nchunk > a.nt) nchunk = a.nt;
@@ -247,7 +283,7 @@ int64_t implicit_residual_blocks(const KArgs& a) { return resid_grid(a).units; }
 void launch_implicit_residual(const KArgs& a, hipStream_t s)
 {
     const ResidGrid r = resid_grid(a);
-    hipLaunchKernelGGL(implicit_residual_kernel, dim3(r.blocks), dim3(kResidTile), 0, s, a, r.ntile, r.chunk,
+    hipLaunchKernelGGL(implicit_residual_kernel, dim3(r.blocks), dim3(kResidThreads), 0, s, a, r.ntile, r.chunk,
                        r.units);
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, a, r.units);
 }
