@@ -115,3 +115,45 @@ def test_ac256_full_size(atm, orc):
     ref = orc.sequential(q, u0)
     err = float(np.max(np.abs(u[:65] - ref)))
     assert err <= 1e-8, f"max error against the FP64 oracle on the first 64 steps: {err:.2e}"
+
+
+@pytest.mark.parametrize("solver", [0, 1], ids=["eigenbasis", "cg"])
+def test_max_row_length(atm, orc, solver):
+    """The longest supported row (1024 points) with a short side of 40 and a ragged tail: F-relaxation and
+    the windows (both Psi solvers) against the oracle."""
+    # nu dt / h^2 of order 1 on h = 1/1025 (the default nu would need thousands of CG iterations per step)
+    p, u0 = W.small_problem(W.HEAT2D, seed=5, nt=7, nx=1024, ny=40, nu=1e-5, tf=0.7, cg_rtol=1e-14)
+    o = W.Options(m=2, k=2, relax=1, coarse_solver=solver)
+    NT = p.nt // o.m
+    u = W.initial_guess(p, u0, "random", seed=3)
+    u[0] = u0
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o))
+    ud, yd = dev(u), dev(np.zeros((NT + 1, p.n)))
+    atm.atm_sweep(p, o, 0, ud, None, yd, ws)
+    u_f = orc.f_relax(p, o, u)
+    assert_close(host(ud), u_f, what="F-relaxation u")
+    y = y_of(orc, p, o, u_f)
+    assert_close(host(yd)[1:], y[1:], what="F-relaxation y")
+    vc = np.stack([u_f[j * o.m] for j in range(NT + 1)])
+    rc = y - vc
+    rc[0] = 0.0
+    e = dev(np.zeros((NT + 1, p.n)))
+    atm.atm_coarse_solve(p, o, dev(u_f), dev(y), e, ws)
+    assert_close(host(e), orc.local_solves(p, o, rc, vc), what="windows")
+
+
+def test_max_1d_grid(atm, orc):
+    """1D heat at the largest supported nx (1024 points, one workgroup of 1024 threads): sweep and solve."""
+    p, u0 = small(W.HEAT1D, 1024, 1, 40)
+    o = W.Options(m=4, k=3, relax=1, tol=1e-12)
+    NT = p.nt // o.m
+    u = W.initial_guess(p, u0, "random", seed=5)
+    u[0] = u0
+    ud, yd = dev(u), dev(np.zeros((NT + 1, p.n)))
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o))
+    atm.atm_sweep(p, o, 0, ud, None, yd, ws)
+    assert_close(host(ud), orc.f_relax(p, o, u), what="1D F-relaxation")
+    ud = dev(W.initial_guess(p, u0))
+    status, hist, st = atm.atm_solve(p, o, ud)
+    assert status == atm.ATM_OK and hist[-1] <= o.tol
+    assert_close(host(ud), orc.sequential(p, u0), rtol=1e-10, what="1D solve vs sequential stepping")
