@@ -219,3 +219,23 @@ def test_c2_mixed_full_size(atm, orc):
     ref = orc.sequential(q, u0)
     err = float(np.max(np.abs(u[:257] - ref)))
     assert err <= 1e-9, f"max error against the FP64 oracle on the first 256 steps: {err:.2e}"
+
+
+def test_c5_full_size(atm, orc):
+    """2D Allen-Cahn 128x128 periodic, eps 0.03, dt 1e-5, Nt 4096, m 32, k 13, FCF, FP32 fine solves, Psi in the
+    eigenbasis (the benchmarked plain solve of the learned-propagator comparison): converge to 1e-8; the stopping
+    norm is the oracle's implicit residual of the result, the paper-form residual is bracketed by it, and the
+    first 64 steps match the oracle's sequential stepping."""
+    p, o, u0 = W.config("c5")
+    ud = dev(W.initial_guess(p, u0))
+    status, hist, st = atm.atm_solve(p, o, ud)
+    print(f"cycles {st['iterations']}, residual {hist[-1]:.3e}, final {st['final_residual']:.3e}")
+    assert status == atm.ATM_OK and hist[-1] <= o.tol
+    u = host(ud)
+    floor = rounding_floor(p, u)
+    rho = float(np.linalg.norm(orc.implicit_residual(p, u)))
+    assert abs(hist[-1] - rho) <= 1e-12 * rho + floor
+    assert st["final_residual"] <= hist[-1] * (1 + 1e-9) + floor
+    q = W.Problem(**{**p.__dict__, "nt": 64, "tf": p.t0 + 64 * p.dt, "cg_rtol": 1e-14})
+    err = float(np.max(np.abs(u[:65] - orc.sequential(q, u0))))
+    assert err <= 1e-8, f"max error against the FP64 oracle on the first 64 steps: {err:.2e}"

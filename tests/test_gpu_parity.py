@@ -209,9 +209,10 @@ def test_c1_k_extremes(atm, orc, k):
 
 
 def test_c2_full_size_sampled(atm, orc):
-    """2D heat 128^2 x 4096, m = 32, FCF, CG rtol 1e-12 (the benchmarked launch): converge on the GPU,
-    then check sampled intervals and every C-point residual with the oracle's integrator."""
+    """2D heat 128^2 x 4096, m = 32, FCF, CG rtol 1e-12, Psi's CG to 1e-3 (the benchmarked launch): converge on
+    the GPU, then check sampled intervals and every C-point residual with the oracle's integrator."""
     p, o, u0 = W.config("c2")
+    o.coarse_solver, o.coarse_cg_rtol = 1, 1e-3
     ud = dev(W.initial_guess(p, u0))
     status, hist, st = atm.atm_solve(p, o, ud)
     assert status == atm.ATM_OK and hist[-1] <= o.tol
