@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--learned-epochs", type=int, default=15)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the c1 and c3 solves")
+    ap.add_argument("--no-k-study", action="store_true", help="skip the 1D heat k-study leg")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline solves only (no context solves, no other legs): for profiling runs")
     ap.add_argument("--batch-count", type=int, default=256,
@@ -211,6 +212,52 @@ def config_leg(name, runs):
     if graph is not None:
         out["graph_captured_cycle"] = graph
     return out
+
+
+K_STUDY = {128: (2, 4, 6, 8, 10, 12, 16, 128), 64: (4, 8, 12, 16, 20, 24, 32, 256),
+           32: (8, 16, 24, 32, 40, 48, 64, 512)}
+
+
+def k_study_leg(runs=2):
+    """The k-study of section 4.3 on the GPU: the manufactured 1D heat problem with 1025 grid points
+    (1023 unknowns) and 16384 time points, random initial guess, two-level AT-MGRIT with
+    F-relaxation and tol 1e-7, for three coarsening factors and a range of k.  Each entry: cycles,
+    best wall time of `runs` solves, and the largest error against the exact solution."""
+    import torch
+    import paper_2107_09596_amd as atm
+    import workloads as W
+    dev = torch.device("cuda:0")
+    p, u0, src, ug = W.heat1d_forced()
+    exact = torch.from_numpy(W.heat1d_forced_exact(p)).to(dev)
+    srcd = torch.from_numpy(src).to(dev)
+    guess = torch.from_numpy(ug).to(dev)
+    u = torch.empty_like(guess)
+    table = {}
+    for m, ks in K_STUDY.items():
+        rows = []
+        for k in ks:
+            o = W.k_study_options(m, k)
+            ws = atm.workspace(atm.atm_workspace_bytes(p, o), device=dev)
+            best = None
+            for _ in range(runs):
+                u.copy_(guess)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                status, hist, st = atm.atm_solve(p, o, u, ws=ws, source=srcd, allow=(atm.ATM_OK,))
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3
+                best = ms if best is None else min(best, ms)
+            err = float((u - exact).abs().max())
+            rows.append({"k": k, "k_over_C": k / (p.nt // m + 1), "cycles": st["iterations"], "ms": best,
+                         "value": p.n * p.nt / (best / 1e3), "final_residual": hist[-1], "err_exact": err})
+            print(f"# k-study m={m} k={k}: {st['iterations']} cycles, {best:.1f} ms", file=sys.stderr, flush=True)
+        par = rows[-1]["cycles"]
+        sat = min(r["k"] for r in rows if r["cycles"] <= par)
+        table[str(m)] = {"C_points": p.nt // m + 1, "runs": rows, "parareal_cycles": par,
+                         "smallest_k_at_parareal_cycles": sat, "saturation_ratio": sat / (p.nt // m + 1)}
+    return {"workload": "1D heat u_t - u_xx = b on [0,3] x [0,pi], u = sin(pi x) cos t, 1023 unknowns, "
+                        "nt 16383, random guess U[-1,1], F-relaxation, tol 1e-7, FP64",
+            "unit": "space-time point-updates/s", "by_m": table}
 
 
 def batch_leg(count, sample):
@@ -412,6 +459,8 @@ def main():
         out["batched"] = batch_leg(args.batch_count, args.batch_sample)
     if not args.no_configs:
         out["other_configs"] = {"c1": config_leg("c1", 4), "c3": config_leg("c3", 1)}
+    if not args.no_k_study:
+        out["k_study"] = k_study_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, u0, min(args.cpu_steps, p.nt))
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]

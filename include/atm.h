@@ -29,7 +29,9 @@
  *   workspace must be ordered on one stream.
  *
  * Problem statement (section 2, eq. (2)): u_0 = g_0, u_i = Phi(u_{i-1}) + g_i,
- * with g_i = 0 for i >= 1.  Time grid t_i = t0 + i dt, dt = (tf - t0)/nt.
+ * with g_i = 0 for i >= 1 unless the problem carries a PDE source (then each
+ * backward Euler step takes it at its new time level, see atm_problem.source).
+ * Time grid t_i = t0 + i dt, dt = (tf - t0)/nt.
  */
 #ifndef ATM_H
 #define ATM_H
@@ -69,6 +71,14 @@ typedef struct atm_problem {
     int32_t kind;   /* ATM_HEAT1D, ATM_HEAT2D or ATM_AC2D */
     int32_t nx, ny; /* spatial points; ny = 1 for ATM_HEAT1D */
     int32_t cg_max_iter;
+    const double* source; /* (device) NULL, or the PDE source b(x, t_i) at every time point, [nt+1][n]
+                             FP64 (row 0 unused), for the forced heat equation u_t - nu u_xx = b of
+                             the k-study in section 4.3.  Each fine step then solves
+                             (I - dt nu L) u_i = u_{i-1} + dt b(t_i), i.e. g_i = (I - dt nu L)^{-1} dt b(t_i)
+                             in eq. (2); Psi is unchanged (it acts on corrections, or on C-point values
+                             with the FAS right-hand side).  ATM_HEAT1D only (other kinds and the batch
+                             API: ATM_ERR_UNSUPPORTED).  Read by the kernels of the call; it must stay
+                             valid until the stream has run them */
 } atm_problem;
 
 typedef struct atm_options {

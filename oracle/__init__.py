@@ -29,6 +29,7 @@ class OrProblem(ctypes.Structure):
         ("nt", ctypes.c_int64),
         ("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("cg_max_iter", ctypes.c_int32),
+        ("src", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -97,9 +98,18 @@ def lib():
     return _lib
 
 
-def _prob(p) -> OrProblem:
+def _prob(p, source=None) -> OrProblem:
+    """The C problem; source is the PDE forcing b(x, t_i), float64 [nt+1, n] (the caller keeps it alive)."""
+    src = None
+    if source is not None:
+        assert source.shape == (p.nt + 1, p.n)
+        src = _ptr(source)
     return OrProblem(length=p.length, nu=p.nu, eps=p.eps, t0=p.t0, tf=p.tf, cg_rtol=p.cg_rtol, nt=p.nt,
-                     kind=p.kind, nx=p.nx, ny=p.ny, cg_max_iter=p.cg_max_iter)
+                     kind=p.kind, nx=p.nx, ny=p.ny, cg_max_iter=p.cg_max_iter, src=src)
+
+
+def _src(source):
+    return None if source is None else np.ascontiguousarray(source, dtype=np.float64)
 
 
 def _opts(o) -> OrOptions:
@@ -147,53 +157,59 @@ def coarse_step(p, o, x):
     return out
 
 
-def sequential(p, u0):
-    """Sequential time stepping u_i = Phi(u_{i-1}); returns [nt+1, n]."""
+def sequential(p, u0, source=None):
+    """Sequential time stepping u_i = Phi(u_{i-1}) + g_i; returns [nt+1, n]."""
+    src = _src(source)
     u = np.zeros((p.nt + 1, p.n), dtype=np.float64)
     u[0] = u0
     cg = ctypes.c_int64(0)
-    _check(lib().or_sequential(ctypes.byref(_prob(p)), _ptr(u), ctypes.byref(cg)), "sequential")
+    _check(lib().or_sequential(ctypes.byref(_prob(p, src)), _ptr(u), ctypes.byref(cg)), "sequential")
     return u
 
 
-def f_relax(p, o, u):
+def f_relax(p, o, u, source=None):
+    src = _src(source)
     u = np.array(u, dtype=np.float64, order="C")
-    _check(lib().or_f_relax(ctypes.byref(_prob(p)), ctypes.byref(_opts(o)), _ptr(u), None), "f_relax")
+    _check(lib().or_f_relax(ctypes.byref(_prob(p, src)), ctypes.byref(_opts(o)), _ptr(u), None), "f_relax")
     return u
 
 
-def c_relax(p, o, u):
+def c_relax(p, o, u, source=None):
+    src = _src(source)
     u = np.array(u, dtype=np.float64, order="C")
-    _check(lib().or_c_relax(ctypes.byref(_prob(p)), ctypes.byref(_opts(o)), _ptr(u), None), "c_relax")
+    _check(lib().or_c_relax(ctypes.byref(_prob(p, src)), ctypes.byref(_opts(o)), _ptr(u), None), "c_relax")
     return u
 
 
-def residual(p, u, g0):
+def residual(p, u, g0, source=None):
     """Full space-time residual g - A(u), [nt+1, n]."""
+    src = _src(source)
     u = np.ascontiguousarray(u, dtype=np.float64)
     g0 = np.ascontiguousarray(g0, dtype=np.float64)
     r = np.empty_like(u)
-    _check(lib().or_residual(ctypes.byref(_prob(p)), _ptr(u), _ptr(g0), _ptr(r), None), "residual")
+    _check(lib().or_residual(ctypes.byref(_prob(p, src)), _ptr(u), _ptr(g0), _ptr(r), None), "residual")
     return r
 
 
-def residual_norm(p, u, g0):
-    return float(np.sqrt(np.sum(residual(p, u, g0) ** 2)))
+def residual_norm(p, u, g0, source=None):
+    return float(np.sqrt(np.sum(residual(p, u, g0, source) ** 2)))
 
 
-def implicit_residual(p, u):
-    """rho_i = psi(u_{i-1}) - M u_i, [nt+1, n] (row 0 is zero)."""
+def implicit_residual(p, u, source=None):
+    """rho_i = psi(u_{i-1}) + dt b(t_i) - M u_i, [nt+1, n] (row 0 is zero; b only with a source)."""
+    src = _src(source)
     u = np.ascontiguousarray(u, dtype=np.float64)
     rho = np.empty_like(u)
-    _check(lib().or_implicit_residual(ctypes.byref(_prob(p)), _ptr(u), _ptr(rho)), "implicit_residual")
+    _check(lib().or_implicit_residual(ctypes.byref(_prob(p, src)), _ptr(u), _ptr(rho)), "implicit_residual")
     return rho
 
 
-def step_residual(p, u):
+def step_residual(p, u, source=None):
     """r_i = M^{-1} rho_i (the residual with the step solved from zero), [nt+1, n]."""
+    src = _src(source)
     u = np.ascontiguousarray(u, dtype=np.float64)
     r = np.empty_like(u)
-    _check(lib().or_step_residual(ctypes.byref(_prob(p)), _ptr(u), _ptr(r), None), "step_residual")
+    _check(lib().or_step_residual(ctypes.byref(_prob(p, src)), _ptr(u), _ptr(r), None), "step_residual")
     return r
 
 
@@ -215,30 +231,33 @@ def local_solves(p, o, rc, vc):
     return e
 
 
-def correct(p, o, u, e):
+def correct(p, o, u, e, source=None):
+    src = _src(source)
     u = np.array(u, dtype=np.float64, order="C")
     e = np.ascontiguousarray(e, dtype=np.float64)
-    _check(lib().or_correct(ctypes.byref(_prob(p)), ctypes.byref(_opts(o)), _ptr(u), _ptr(e), None), "correct")
+    _check(lib().or_correct(ctypes.byref(_prob(p, src)), ctypes.byref(_opts(o)), _ptr(u), _ptr(e), None), "correct")
     return u
 
 
-def cycle(p, o, u, g0=None, parareal=False):
+def cycle(p, o, u, g0=None, parareal=False, source=None):
     """One AT-MGRIT (or Parareal) cycle of Alg. 1 applied to a copy of u."""
+    src = _src(source)
     u = np.array(u, dtype=np.float64, order="C")
     g0 = np.ascontiguousarray(u[0] if g0 is None else g0, dtype=np.float64)
     st = OrStats()
     f = lib().or_parareal_cycle if parareal else lib().or_cycle
-    _check(f(ctypes.byref(_prob(p)), ctypes.byref(_opts(o)), _ptr(u), _ptr(g0), ctypes.byref(st)), "cycle")
+    _check(f(ctypes.byref(_prob(p, src)), ctypes.byref(_opts(o)), _ptr(u), _ptr(g0), ctypes.byref(st)), "cycle")
     return u
 
 
-def solve(p, o, u, parareal=False, hist_cap=1000, allow_status=(OK,)):
+def solve(p, o, u, parareal=False, hist_cap=1000, allow_status=(OK,), source=None):
     """AT-MGRIT (or Parareal) until tol; returns (u, hist, stats dict)."""
+    src = _src(source)
     u = np.array(u, dtype=np.float64, order="C")
     hist = np.zeros(hist_cap, dtype=np.float64)
     st = OrStats()
     f = lib().or_parareal_solve if parareal else lib().or_atmgrit_solve
-    status = f(ctypes.byref(_prob(p)), ctypes.byref(_opts(o)), _ptr(u), _ptr(hist), hist_cap, ctypes.byref(st))
+    status = f(ctypes.byref(_prob(p, src)), ctypes.byref(_opts(o)), _ptr(u), _ptr(hist), hist_cap, ctypes.byref(st))
     if status not in allow_status:
         raise OracleError(status, "solve")
     stats = {name: getattr(st, name) for name, _ in OrStats._fields_}

@@ -24,7 +24,12 @@
  *     (section 4.3).
  *
  * Readings taken where the paper is silent (all repeated in the design doc):
- *   - g_i = 0 for i >= 1 (no forcing); g_0 = u_0.
+ *   - g_0 = u_0.  Without a forcing term g_i = 0 for i >= 1.  With a PDE source
+ *     b(x, t) (the manufactured 1D heat problem of section 4.3) the backward
+ *     Euler step takes it at the new time level, M u_i = psi(u_{i-1}) + dt b(t_i),
+ *     so Phi(u_{i-1}) + g_i is that solve and g_i = M^{-1} dt b(t_i); the coarse
+ *     propagator Psi acts on corrections (linear form) or on C-point values with
+ *     the FAS right-hand side, and takes no source.
  *   - Selective ideal interpolation is applied as "add e_p to C-point p, then
  *     F-relax interval p from it".  For a linear Phi this equals adding
  *     Phi^i e_p to the F-points of an F-relaxed iterate; for a nonlinear Phi
@@ -56,6 +61,7 @@ typedef struct {
     double length, nu, eps, t0, tf, cg_rtol;
     int64_t nt;
     int32_t kind, nx, ny, cg_max_iter;
+    const double* src; /* nullable [nt+1][n]: PDE source b(x, t_i) at every time point (row 0 unused) */
 } or_problem;
 
 typedef struct {
@@ -222,41 +228,46 @@ static void apply_M_fine(const or_problem* P, const double* x, double* y)
     apply_M2d(P, cx, P->nu * dt / (hy * hy), x, y);
 }
 
-/* One step of the integrator with step size dt: out = Phi_dt(in), with the
-   linear systems of the 2D kinds solved to relative tolerance rtol.
-   work must hold 6n doubles.  out may not alias in. */
-static int step_dt_tol(const or_problem* P, double dt, double rtol, const double* in, double* out,
-                       double* work, int64_t* cg_its);
+/* One step of the integrator with step size dt: out solves
+   M out = psi(in) + dt f, with f the source at the step's new time level
+   (NULL: no source), the linear systems of the 2D kinds solved to relative
+   tolerance rtol.  work must hold 6n doubles.  out may not alias in. */
+static int step_dt_tol(const or_problem* P, double dt, double rtol, const double* in, const double* f,
+                       double* out, double* work, int64_t* cg_its);
 
-static int step_dt(const or_problem* P, double dt, const double* in, double* out, double* work,
-                   int64_t* cg_its)
+static int step_dt(const or_problem* P, double dt, const double* in, const double* f, double* out,
+                   double* work, int64_t* cg_its)
 {
-    return step_dt_tol(P, dt, P->cg_rtol, in, out, work, cg_its);
+    return step_dt_tol(P, dt, P->cg_rtol, in, f, out, work, cg_its);
 }
 
-static int step_dt_tol(const or_problem* P, double dt, double rtol, const double* in, double* out,
-                       double* work, int64_t* cg_its)
+static int step_dt_tol(const or_problem* P, double dt, double rtol, const double* in, const double* f,
+                       double* out, double* work, int64_t* cg_its)
 {
     const int64_t n = nspace(P);
+    double* b = work + 4 * n;
+    explicit_part(P, dt, in, b);
+    if (f)
+        for (int64_t i = 0; i < n; ++i) b[i] += dt * f[i];
     if (P->kind == OR_HEAT1D) {
         const double h = spacing(P, P->nx);
-        thomas(P->nx, P->nu * dt / (h * h), in, out, work);
+        thomas(P->nx, P->nu * dt / (h * h), b, out, work);
         return OR_OK;
     }
     const double hx = spacing(P, P->nx), hy = spacing(P, P->ny);
     const double cx = P->nu * dt / (hx * hx), cy = P->nu * dt / (hy * hy);
-    double* b = work + 4 * n;
-    explicit_part(P, dt, in, b);
     for (int64_t i = 0; i < n; ++i) out[i] = in[i];
     return pcg2d(P, cx, cy, rtol, b, out, work, cg_its);
 }
 
 static int64_t work_len(const or_problem* P) { return 6 * nspace(P); }
 
-/* Phi: one fine step of size dt (eq. (2)). */
-static int fine_step(const or_problem* P, const double* in, double* out, double* work, int64_t* cg)
+/* Phi(in) + g_i: the fine step of size dt that produces time point i (eq. (2)),
+   with the source at t_i when the problem has one. */
+static int fine_step(const or_problem* P, int64_t i, const double* in, double* out, double* work,
+                     int64_t* cg)
 {
-    return step_dt(P, step_size(P), in, out, work, cg);
+    return step_dt(P, step_size(P), in, P->src ? P->src + i * nspace(P) : NULL, out, work, cg);
 }
 
 /* Psi: the coarse propagator, a re-discretisation with dT = m dt taken in s substeps. */
@@ -271,7 +282,7 @@ static int coarse_step(const or_problem* P, const or_options* O, const double* i
     const double* src = in;
     for (int i = 0; i < s; ++i) {
         double* dst = (i == s - 1) ? out : tmp + (i & 1) * n;
-        int st = step_dt_tol(P, dts, rtol, src, dst, work, cg);
+        int st = step_dt_tol(P, dts, rtol, src, NULL, dst, work, cg);
         if (st) return st;
         src = dst;
     }
@@ -284,10 +295,11 @@ static int64_t coarse_work_len(const or_problem* P) { return work_len(P) + 2 * n
 /* exported single steps                                                     */
 /* ------------------------------------------------------------------------ */
 
+/* one step of size dt without source */
 int or_step(const or_problem* P, double dt, const double* in, double* out, int64_t* cg_its)
 {
     double* work = malloc(sizeof(double) * work_len(P));
-    int st = step_dt(P, dt, in, out, work, cg_its);
+    int st = step_dt(P, dt, in, NULL, out, work, cg_its);
     free(work);
     return st;
 }
@@ -307,7 +319,7 @@ int or_sequential(const or_problem* P, double* u, int64_t* cg_its)
     double* work = malloc(sizeof(double) * work_len(P));
     int st = OR_OK;
     for (int64_t i = 1; i <= P->nt && st == OR_OK; ++i)
-        st = fine_step(P, u + (i - 1) * n, u + i * n, work, cg_its);
+        st = fine_step(P, i, u + (i - 1) * n, u + i * n, work, cg_its);
     free(work);
     return st;
 }
@@ -340,7 +352,7 @@ static int f_relax_interval(const or_problem* P, const or_options* O, double* u,
     const int64_t n = nspace(P);
     int st = OR_OK;
     for (int64_t i = j * O->m + 1; i <= interval_end(P, O, j) && st == OR_OK; ++i)
-        st = fine_step(P, u + (i - 1) * n, u + i * n, work, cg);
+        st = fine_step(P, i, u + (i - 1) * n, u + i * n, work, cg);
     return st;
 }
 
@@ -388,7 +400,7 @@ int or_c_relax(const or_problem* P, const or_options* O, double* u, int64_t* cg)
 #pragma omp for schedule(dynamic, 1)
         for (int64_t j = 1; j <= NT; ++j) {
             int64_t c = 0;
-            int st = fine_step(P, u + (j * O->m - 1) * n, u + j * O->m * n, work, &c);
+            int st = fine_step(P, j * O->m, u + (j * O->m - 1) * n, u + j * O->m * n, work, &c);
             cg_total += c;
             if (st) {
 #pragma omp critical
@@ -406,7 +418,7 @@ int or_c_relax(const or_problem* P, const or_options* O, double* u, int64_t* cg)
 /* ------------------------------------------------------------------------ */
 
 /* Full space-time residual at all nt+1 time points: r_0 = g_0 - u_0,
-   r_i = g_i + Phi(u_{i-1}) - u_i with g_i = 0 for i >= 1. */
+   r_i = g_i + Phi(u_{i-1}) - u_i (g_i = 0 for i >= 1 without a source). */
 int or_residual(const or_problem* P, const double* u, const double* g0, double* r, int64_t* cg)
 {
     const int64_t n = nspace(P);
@@ -420,7 +432,7 @@ int or_residual(const or_problem* P, const double* u, const double* g0, double* 
 #pragma omp for schedule(dynamic, 4)
         for (int64_t i = 1; i <= P->nt; ++i) {
             int64_t c = 0;
-            int st = fine_step(P, u + (i - 1) * n, phi, work, &c);
+            int st = fine_step(P, i, u + (i - 1) * n, phi, work, &c);
             cg_total += c;
             if (st) {
 #pragma omp critical
@@ -439,8 +451,9 @@ double or_norm2(int64_t len, const double* v) { return sqrt(dot(len, v, v)); }
 
 /* The implicit form of the residual.  Every fine step solves M u_i = psi(u_{i-1})
    (eq. (2) for the integrators above), so the paper's residual at a point,
-   r_i = Phi(u_{i-1}) - u_i, equals M^{-1} rho_i with
-       rho_i = psi(u_{i-1}) - M u_i           (i = 1..nt; rho_0 = 0 as g_0 - u_0 = 0).
+   r_i = Phi(u_{i-1}) + g_i - u_i, equals M^{-1} rho_i with
+       rho_i = psi(u_{i-1}) + dt b(t_i) - M u_i   (i = 1..nt; rho_0 = 0 as g_0 - u_0 = 0),
+   the source term present only when the problem has one.
    rho needs no solve.  M = I - dt nu L_h has eigenvalues >= 1, so |r_i| <= |rho_i|. */
 int or_implicit_residual(const or_problem* P, const double* u, double* rho)
 {
@@ -454,6 +467,8 @@ int or_implicit_residual(const or_problem* P, const double* u, double* rho)
 #pragma omp for schedule(static)
         for (int64_t i = 1; i <= P->nt; ++i) {
             explicit_part(P, dt, u + (i - 1) * n, ps);
+            if (P->src)
+                for (int64_t x = 0; x < n; ++x) ps[x] += dt * P->src[i * n + x];
             apply_M_fine(P, u + i * n, mu);
             for (int64_t x = 0; x < n; ++x) rho[i * n + x] = ps[x] - mu[x];
         }

@@ -77,8 +77,8 @@ def _f64():
     return _torch().float64
 
 
-def atm_sweep(prob, opts, mode: int, u, aux, y, ws, stream=None) -> None:
-    st = _abi.lib().atm_sweep(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts)), int(mode),
+def atm_sweep(prob, opts, mode: int, u, aux, y, ws, stream=None, source=None) -> None:
+    st = _abi.lib().atm_sweep(ctypes.byref(_abi.problem(prob, source)), ctypes.byref(_abi.options(opts)), int(mode),
                               _ptr(u, _f64(), "u"), _ptr(aux, _f64(), "aux"), _ptr(y, _f64(), "y"),
                               _ptr(ws, None, "ws"), ws.numel() * ws.element_size(), _stream(stream))
     _abi.check(st, "atm_sweep")
@@ -100,38 +100,40 @@ def atm_residual_norm(prob, opts, u, y, ws, stream=None) -> float:
     return out.value
 
 
-def _norm_of_u(fname, prob, opts, u, ws, stream):
+def _norm_of_u(fname, prob, opts, u, ws, stream, source=None):
     out = ctypes.c_double(0.0)
-    st = getattr(_abi.lib(), fname)(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts)),
+    st = getattr(_abi.lib(), fname)(ctypes.byref(_abi.problem(prob, source)), ctypes.byref(_abi.options(opts)),
                                     _ptr(u, _f64(), "u"), ctypes.byref(out), _ptr(ws, None, "ws"),
                                     ws.numel() * ws.element_size(), _stream(stream))
     _abi.check(st, fname)
     return out.value
 
 
-def atm_implicit_residual_norm(prob, opts, u, ws, stream=None) -> float:
-    return _norm_of_u("atm_implicit_residual_norm", prob, opts, u, ws, stream)
+def atm_implicit_residual_norm(prob, opts, u, ws, stream=None, source=None) -> float:
+    return _norm_of_u("atm_implicit_residual_norm", prob, opts, u, ws, stream, source)
 
 
-def atm_step_residual_norm(prob, opts, u, ws, stream=None) -> float:
-    return _norm_of_u("atm_step_residual_norm", prob, opts, u, ws, stream)
+def atm_step_residual_norm(prob, opts, u, ws, stream=None, source=None) -> float:
+    return _norm_of_u("atm_step_residual_norm", prob, opts, u, ws, stream, source)
 
 
-def atm_sequential(prob, u, ws=None, stream=None) -> None:
+def atm_sequential(prob, u, ws=None, stream=None, source=None) -> None:
     if ws is None:
         ws = workspace(atm_sequential_workspace_bytes(prob), device=u.device)
-    st = _abi.lib().atm_sequential(ctypes.byref(_abi.problem(prob)), _ptr(u, _f64(), "u"), _ptr(ws, None, "ws"),
+    st = _abi.lib().atm_sequential(ctypes.byref(_abi.problem(prob, source)), _ptr(u, _f64(), "u"), _ptr(ws, None, "ws"),
                                    ws.numel() * ws.element_size(), _stream(stream))
     _abi.check(st, "atm_sequential")
 
 
-def atm_solve(prob, opts, u, ws=None, hist_cap: int = 256, stream=None, allow=(ATM_OK, ATM_NOT_CONVERGED)):
-    """Run AT-MGRIT in place on u; returns (status, residual history list, stats dict)."""
+def atm_solve(prob, opts, u, ws=None, hist_cap: int = 256, stream=None, allow=(ATM_OK, ATM_NOT_CONVERGED),
+              source=None):
+    """Run AT-MGRIT in place on u; returns (status, residual history list, stats dict).
+    source: optional PDE source b(x, t_i), device float64 [nt+1, n] (1D heat)."""
     if ws is None:
         ws = workspace(atm_workspace_bytes(prob, opts), device=u.device)
     hist = (ctypes.c_double * max(hist_cap, 1))()
     stats = _abi.AtmStats()
-    st = _abi.lib().atm_solve(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts)),
+    st = _abi.lib().atm_solve(ctypes.byref(_abi.problem(prob, source)), ctypes.byref(_abi.options(opts)),
                               _ptr(u, _f64(), "u"), _ptr(ws, None, "ws"), ws.numel() * ws.element_size(),
                               hist, int(hist_cap), ctypes.byref(stats), _stream(stream))
     _abi.check(st, "atm_solve", allow=allow)

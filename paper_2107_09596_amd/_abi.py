@@ -31,6 +31,7 @@ class AtmProblem(ctypes.Structure):
         ("nt", ctypes.c_int64),
         ("kind", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
         ("cg_max_iter", ctypes.c_int32),
+        ("source", ctypes.c_void_p),
     ]
 
 
@@ -128,10 +129,19 @@ def check(status: int, where: str, allow=(ATM_OK,)) -> int:
     return status
 
 
-def problem(p) -> AtmProblem:
-    """AtmProblem from any object with the fields of workloads.Problem."""
+def problem(p, source=None) -> AtmProblem:
+    """AtmProblem from any object with the fields of workloads.Problem; source is an optional device
+    tensor holding the PDE source [nt+1, n] FP64 (the caller keeps it alive until the call's work ran)."""
+    src = None
+    if source is not None:
+        import torch
+        if not source.is_cuda or source.dtype != torch.float64 or not source.is_contiguous():
+            raise ValueError("source must be a contiguous float64 device tensor")
+        if tuple(source.shape) != (p.nt + 1, p.nx * p.ny):
+            raise ValueError(f"source must have shape {(p.nt + 1, p.nx * p.ny)}, got {tuple(source.shape)}")
+        src = source.data_ptr()
     return AtmProblem(length=p.length, nu=p.nu, eps=p.eps, t0=p.t0, tf=p.tf, cg_rtol=p.cg_rtol, nt=p.nt,
-                      kind=p.kind, nx=p.nx, ny=p.ny, cg_max_iter=p.cg_max_iter)
+                      kind=p.kind, nx=p.nx, ny=p.ny, cg_max_iter=p.cg_max_iter, source=src)
 
 
 def options(o) -> AtmOptions:

@@ -119,6 +119,8 @@ atm_status validate(const atm_problem* p, const atm_options* o)
     if (p->kind == ATM_AC2D && !(p->eps > 0.0)) return fail(ATM_ERR_INVALID_ARG, "eps must be > 0");
     if (!(p->tf > p->t0)) return fail(ATM_ERR_INVALID_ARG, "tf must exceed t0");
     if (p->nt < 1) return fail(ATM_ERR_INVALID_ARG, "nt must be >= 1");
+    if (p->source && p->kind != ATM_HEAT1D)
+        return fail(ATM_ERR_UNSUPPORTED, "a PDE source is supported for ATM_HEAT1D only");
     if (p->kind != ATM_HEAT1D && (!(p->cg_rtol >= 0.0) || p->cg_max_iter < 1))
         return fail(ATM_ERR_INVALID_ARG, "cg_rtol must be >= 0 and cg_max_iter >= 1");
     if (o->m < 2) return fail(ATM_ERR_INVALID_ARG, "coarsening factor m must be >= 2");
@@ -198,6 +200,8 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
     a.nx = p->nx;
     a.is1d = (p->kind == ATM_HEAT1D);
     const double dt = (p->tf - p->t0) / (double)p->nt;
+    a.src = p->source;
+    a.dt = dt;
     a.fine = step_coef(p, dt);
     a.coarse = step_coef(p, dt * o->m / o->coarse_substeps);
     a.rtol2 = p->cg_rtol * p->cg_rtol;
@@ -684,6 +688,7 @@ atm_status describe(int32_t n, const atm_problem* probs, const atm_options* opts
         if (st) return fail(st, "instance %d: %s", i, g_last_error.c_str());
         if (learned(&in.o)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches use the plain coarse propagator", i);
         if (large_grid(&in.p)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take grids up to 128 x 128", i);
+        if (in.p.source) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take no PDE source", i);
         in.cls = in.p.kind == ATM_HEAT1D ? CLS_1D : (in.p.kind == ATM_AC2D ? CLS_2DP : CLS_2D);
         if (in.cls == CLS_1D && in.p.nx > 512)
             return fail(ATM_ERR_UNSUPPORTED, "instance %d: 1D batch instances take nx <= 512", i);

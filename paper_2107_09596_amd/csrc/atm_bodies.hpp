@@ -32,6 +32,7 @@ __device__ __forceinline__ void sweep1d_body(const KArgs& a, int64_t j, double* 
         return;
     }
     for (int64_t t = 1; t <= total; ++t) {
+        if (a.src && act) x = x + a.dt * a.src[(j * a.m + t) * a.n + i];
         x = pcr_solve(f, a.nx, x, lds);
         if (act) {
             if (t < a.m)

@@ -54,6 +54,7 @@ __global__ __launch_bounds__(1024) void seq1d_kernel(KArgs a)
     pcr_setup(f, a.nx, a.fine.cx, lds);
     double x = act ? a.u[i] : 0.0;
     for (int64_t t = 1; t <= a.nt; ++t) {
+        if (a.src && act) x = x + a.dt * a.src[t * a.n + i];
         x = pcr_solve(f, a.nx, x, lds);
         if (act) a.u[t * a.n + i] = x;
     }

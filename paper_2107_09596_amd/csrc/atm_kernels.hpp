@@ -34,6 +34,10 @@ struct KArgs {
     int64_t nt, n, NT;
     int m, k, mode, fas, substeps, nx;
     int is1d, s_tmpl, exact;
+    // PDE source b(x, t_i), [nt+1][n] (1D heat), or null: every fine step adds dt b(t_i) to its
+    // right-hand side
+    const double* src;
+    double dt;
     Grid2D g;
     StepCoef fine, coarse;
     double rtol2;         // squared CG tolerance of Phi

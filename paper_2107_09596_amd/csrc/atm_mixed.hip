@@ -125,7 +125,8 @@ __global__ __launch_bounds__(kResidThreads) void implicit_residual_kernel(KArgs 
                 const double ev_ = load_e ? ee[r] : se;
                 const double nv = r == 0 ? hu : cen[r - 1];
                 const double sv = y == ylast ? hd : cen[r + 1 < kResRows ? r + 1 : r];
-                const double rho = explicit_part(c, prev[r]) - stencil_value(c, nv, cen[r], sv, wv_, ev_);
+                double rho = explicit_part(c, prev[r]) - stencil_value(c, nv, cen[r], sv, wv_, ev_);
+                if (a.src) rho += a.dt * a.src[i * a.n + (uint32_t)(y * nx + x)];
                 acc += rho * rho;
             }
             prev[r] = cen[r];
@@ -210,6 +211,7 @@ __global__ __launch_bounds__(1024) void step_residual1d_kernel(KArgs a)
             const double w = i > 0 ? ui[i - 1] : 0.0;
             const double e = i < nx - 1 ? ui[i + 1] : 0.0;
             rho = a.u[(ti - 1) * a.n + i] - (a.fine.d * ui[i] - c * (w + e));
+            if (a.src) rho += a.dt * a.src[ti * a.n + i];
         }
         const double z = pcr_solve(f, nx, rho, lds);
         if (act) acc += z * z;

@@ -129,3 +129,20 @@ def test_strip_layout_rule_accepts_all_grids_up_to_128(abi):
                 p = W.Problem(W.HEAT2D, nx=nx, ny=ny, nt=8)
                 o = W.Options(m=2, k=2, precision=precision)
                 assert abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(o))) > 0
+
+
+def test_source_accepted_for_1d_only(abi):
+    """The PDE source is validated on the host: the 1D heat kind takes it (same workspace), the 2D
+    kinds and the batch API reject it before anything is launched (the pointer is never read)."""
+    p1, o1 = W.Problem(W.HEAT1D, nx=63, nt=64), W.Options(m=4, k=2)
+    P, O = abi.problem(p1), abi.options(o1)
+    plain = abi.lib().atm_workspace_bytes(ctypes.byref(P), ctypes.byref(O))
+    P.source = 256
+    assert abi.lib().atm_workspace_bytes(ctypes.byref(P), ctypes.byref(O)) == plain > 0
+    assert abi.lib().atm_batch_workspace_bytes(1, ctypes.byref(P), ctypes.byref(O)) == 0
+    assert "source" in abi.lib().atm_last_error().decode()
+    P2 = abi.problem(W.Problem(W.HEAT2D, nx=16, ny=16, nt=64))
+    P2.source = 256
+    assert abi.lib().atm_workspace_bytes(ctypes.byref(P2), ctypes.byref(O)) == 0
+    st = abi.lib().atm_solve(ctypes.byref(P2), ctypes.byref(O), None, None, 0, None, 0, None, None)
+    assert st == abi.ATM_ERR_UNSUPPORTED

@@ -7,7 +7,9 @@ slice (``n = nx * ny``, index ``y * nx + x``) or ``[nt + 1, n]`` for a
 space-time iterate.
 
 Problem kinds (the integrator of the one-step form u_i = Phi(u_{i-1}) + g_i of
-section 2, eq. (2); g_i = 0 for i >= 1 and g_0 = u0):
+section 2, eq. (2); g_0 = u0, and g_i = 0 for i >= 1 except in the manufactured
+1D heat problem, whose PDE source enters each backward Euler step at its new
+time level):
 
 * ``HEAT1D`` -- u_t = nu u_xx on [0, L], zero Dirichlet, nx interior points,
   h = L / (nx + 1), backward Euler.
@@ -171,6 +173,38 @@ def config(name: str):
     else:
         raise KeyError(name)
     return p, o, u0
+
+
+def heat1d_forced(nx: int = 1023, nt: int = 16383, guess_seed: int = 8):
+    """The manufactured 1D heat problem of the k-study (section 4.3).
+
+    u_t - u_xx = b on x in [0, 3], t in [0, pi], zero Dirichlet ends,
+    u(x, 0) = sin(pi x), b(x, t) = -sin(pi x) (sin t - pi^2 cos t), so that
+    u = sin(pi x) cos t solves the PDE.  Defaults: 1025 grid points including
+    both ends (nx = 1023 unknowns, h = 3/1024) and 16384 time points
+    (nt = 16383 steps).  The guess at t > 0 is i.i.d. U[-1, 1] from
+    default_rng(guess_seed).  Returns (Problem, u0, source [nt+1, n], u_guess [nt+1, n]).
+    The source is the forcing evaluated at every grid point and time point.
+    """
+    p = Problem(HEAT1D, nx=nx, ny=1, length=3.0, nu=1.0, t0=0.0, tf=math.pi, nt=nt)
+    x = (p.length / (nx + 1)) * np.arange(1, nx + 1)
+    t = p.t0 + p.dt * np.arange(nt + 1)
+    sx = np.sin(np.pi * x)
+    source = np.ascontiguousarray(-np.outer(np.sin(t) - np.pi ** 2 * np.cos(t), sx), dtype=np.float64)
+    u0 = np.ascontiguousarray(sx, dtype=np.float64)
+    return p, u0, source, initial_guess(p, u0, "random", seed=guess_seed)
+
+
+def heat1d_forced_exact(p: Problem):
+    """The PDE solution sin(pi x) cos t of the manufactured problem at every grid and time point, [nt+1, n]."""
+    x = (p.length / (p.nx + 1)) * np.arange(1, p.nx + 1)
+    t = p.t0 + p.dt * np.arange(p.nt + 1)
+    return np.outer(np.cos(t), np.sin(np.pi * x))
+
+
+def k_study_options(m: int, k: int, tol: float = 1e-7, max_iter: int = 200):
+    """Two-level AT-MGRIT options of the k-study: F-relaxation, linear coarse problem, tol 1e-7."""
+    return Options(m=m, k=k, relax=0, tol=tol, max_iter=max_iter, coarse_form=1)
 
 
 def small_problem(kind: int, seed: int = 0, nt: int = 48, nx: int = 7, ny: int = None, **kw):
