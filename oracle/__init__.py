@@ -41,6 +41,18 @@ class OrOptions(ctypes.Structure):
     ]
 
 
+OR_MAX_LEVELS = 4
+
+
+class OrMlOptions(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double), ("coarse_cg_rtol", ctypes.c_double),
+        ("levels", ctypes.c_int32), ("m", ctypes.c_int32 * (OR_MAX_LEVELS - 1)),
+        ("k", ctypes.c_int32), ("relax", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+        ("coarse_substeps", ctypes.c_int32),
+    ]
+
+
 class OrStats(ctypes.Structure):
     _fields_ = [
         ("final_residual", ctypes.c_double),
@@ -88,6 +100,8 @@ def lib():
             "or_parareal_solve": (ctypes.c_int, [P, O, dp, dp, ctypes.c_int32, S]),
             "or_num_intervals": (ctypes.c_int64, [P, O]),
             "or_window_start": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32]),
+            "or_ml_cycle": (ctypes.c_int, [P, ctypes.POINTER(OrMlOptions), dp, dp, i64p]),
+            "or_ml_solve": (ctypes.c_int, [P, ctypes.POINTER(OrMlOptions), dp, dp, ctypes.c_int32, S]),
             "or_set_threads": (None, [ctypes.c_int]),
             "or_get_max_threads": (ctypes.c_int, []),
         }
@@ -116,6 +130,14 @@ def _opts(o) -> OrOptions:
     return OrOptions(tol=o.tol, coarse_cg_rtol=getattr(o, "coarse_cg_rtol", 0.0), m=o.m, k=o.k, relax=o.relax,
                      max_iter=o.max_iter,
                      coarse_substeps=o.coarse_substeps, coarse_form=o.coarse_form)
+
+
+def _ml_opts(o) -> OrMlOptions:
+    """Multilevel options: o.levels levels with factors o.m (level 0 -> 1) and o.m_coarse (between
+    the coarser levels), k, relax, tol, max_iter, coarse_substeps and coarse_cg_rtol as for two levels."""
+    ms = (ctypes.c_int32 * (OR_MAX_LEVELS - 1))(*([o.m] + [o.m_coarse] * (OR_MAX_LEVELS - 2)))
+    return OrMlOptions(tol=o.tol, coarse_cg_rtol=getattr(o, "coarse_cg_rtol", 0.0), levels=o.levels, m=ms, k=o.k,
+                       relax=o.relax, max_iter=o.max_iter, coarse_substeps=o.coarse_substeps)
 
 
 def _ptr(a: np.ndarray):
@@ -270,3 +292,27 @@ def num_intervals(p, o) -> int:
 
 def window_start(pidx: int, k: int) -> int:
     return int(lib().or_window_start(int(pidx), int(k)))
+
+
+def ml_cycle(p, o, u, g0=None, source=None):
+    """One multilevel FAS V-cycle of Alg. 2 applied to a copy of u."""
+    src = _src(source)
+    u = np.array(u, dtype=np.float64, order="C")
+    g0 = np.ascontiguousarray(u[0] if g0 is None else g0, dtype=np.float64)
+    _check(lib().or_ml_cycle(ctypes.byref(_prob(p, src)), ctypes.byref(_ml_opts(o)), _ptr(u), _ptr(g0), None),
+           "ml_cycle")
+    return u
+
+
+def ml_solve(p, o, u, hist_cap=1000, allow_status=(OK,), source=None):
+    """Multilevel FAS AT-MGRIT (Alg. 2) until tol; returns (u, hist, stats dict)."""
+    src = _src(source)
+    u = np.array(u, dtype=np.float64, order="C")
+    hist = np.zeros(hist_cap, dtype=np.float64)
+    st = OrStats()
+    status = lib().or_ml_solve(ctypes.byref(_prob(p, src)), ctypes.byref(_ml_opts(o)), _ptr(u), _ptr(hist), hist_cap,
+                               ctypes.byref(st))
+    if status not in allow_status:
+        raise OracleError(status, "ml_solve")
+    stats = {name: getattr(st, name) for name, _ in OrStats._fields_}
+    return u, hist[: st.iterations + 1].copy(), stats

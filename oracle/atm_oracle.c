@@ -21,7 +21,10 @@
  *   - the FAS form of the local problems for a nonlinear Psi (Alg. 2, the
  *     coarsest-level branch);
  *   - stopping on the discrete 2-norm of the absolute space-time residual
- *     (section 4.3).
+ *     (section 4.3);
+ *   - the multilevel FAS V-cycle of Alg. 2 (section 2.2): F(CF)^nu relaxation,
+ *     injection of the approximation and its residual, the next level's FAS
+ *     system, local grids on the coarsest level, ideal interpolation back.
  *
  * Readings taken where the paper is silent (all repeated in the design doc):
  *   - g_0 = u_0.  Without a forcing term g_i = 0 for i >= 1.  With a PDE source
@@ -826,5 +829,310 @@ int or_parareal_cycle(const or_problem* P, const or_options* O, double* u, const
     if (alloc_buffers(P, O, &B)) return OR_INVALID;
     int st = cycle(P, O, u, g0, &B, S, 1);
     free_buffers(&B);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* multilevel FAS AT-MGRIT V-cycle (section 2.2, Alg. 2)                     */
+/* ------------------------------------------------------------------------ */
+
+#define OR_MAX_LEVELS 4
+
+/* Levels l = 0..L-1: level 0 is the fine grid; level l+1 takes every m[l]-th point of level l
+   (restriction by injection); the coarsest level L-1 is replaced by the local grids of size k.
+   Level l >= 1 steps with a re-discretisation of step dt m[0]..m[l-1], taken in coarse_substeps
+   substeps whose linear systems are solved to coarse_cg_rtol (0: the problem's cg_rtol). */
+typedef struct {
+    double tol;
+    double coarse_cg_rtol;
+    int32_t levels;
+    int32_t m[OR_MAX_LEVELS - 1];
+    int32_t k, relax, max_iter, coarse_substeps;
+} or_ml_options;
+
+typedef struct {
+    int64_t nt; /* steps of this level: time points 0..nt */
+    double dt;
+    int32_t m;  /* coarsening factor to the next level (unused on the coarsest) */
+    int32_t substeps;
+    double rtol;
+    int32_t fine; /* level 0: the fine integrator (with the problem's source, if any) */
+} ml_level;
+
+static int ml_levels(const or_problem* P, const or_ml_options* O, ml_level* lv)
+{
+    if (O->levels < 2 || O->levels > OR_MAX_LEVELS || O->k < 1) return OR_INVALID;
+    int64_t nt = P->nt;
+    double dt = step_size(P);
+    for (int l = 0; l < O->levels; ++l) {
+        lv[l].nt = nt;
+        lv[l].dt = dt;
+        lv[l].fine = (l == 0);
+        lv[l].substeps = (l == 0) ? 1 : (O->coarse_substeps < 1 ? 1 : O->coarse_substeps);
+        lv[l].rtol = (l == 0 || O->coarse_cg_rtol <= 0.0) ? P->cg_rtol : O->coarse_cg_rtol;
+        lv[l].m = (l < O->levels - 1) ? O->m[l] : 0;
+        if (l < O->levels - 1) {
+            if (lv[l].m < 2 || nt < lv[l].m) return OR_INVALID;
+            nt /= lv[l].m;
+            dt *= lv[l].m;
+        }
+    }
+    return OR_OK;
+}
+
+/* the integrator of level l producing point i from in (work: coarse_work_len doubles) */
+static int ml_step(const or_problem* P, const ml_level* L, int64_t i, const double* in, double* out, double* work,
+                   int64_t* cg)
+{
+    if (L->fine) return fine_step(P, i, in, out, work, cg);
+    const int64_t n = nspace(P);
+    double* tmp = work + work_len(P);
+    const double* src = in;
+    for (int q = 0; q < L->substeps; ++q) {
+        double* dst = (q == L->substeps - 1) ? out : tmp + (q & 1) * n;
+        int st = step_dt_tol(P, L->dt / L->substeps, L->rtol, src, NULL, dst, work, cg);
+        if (st) return st;
+        src = dst;
+    }
+    return OR_OK;
+}
+
+/* right-hand side of point i >= 1 of the level's system u_i - Phi_l(u_{i-1}) = G_i (0 without G) */
+static double ml_rhs(const double* G, int64_t n, int64_t i, int64_t x) { return G ? G[i * n + x] : 0.0; }
+
+/* u_i = Phi_l(u_{i-1}) + G_i for the F-points of every interval (F-relaxation of level l) */
+static int ml_f_relax(const or_problem* P, const ml_level* L, double* u, const double* G, int64_t* cg)
+{
+    const int64_t n = nspace(P);
+    const int64_t NC = L->nt / L->m;
+    const int64_t NI = (NC * L->m < L->nt) ? NC + 1 : NC;
+    int status = OR_OK;
+    int64_t cg_total = 0;
+#pragma omp parallel num_threads(g_threads) reduction(+ : cg_total)
+    {
+        double* work = malloc(sizeof(double) * coarse_work_len(P));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t j = 0; j < NI; ++j) {
+            int64_t end = (j + 1) * L->m - 1;
+            if (end > L->nt) end = L->nt;
+            int st = OR_OK;
+            int64_t c = 0;
+            for (int64_t i = j * L->m + 1; i <= end && st == OR_OK; ++i) {
+                st = ml_step(P, L, i, u + (i - 1) * n, u + i * n, work, &c);
+                for (int64_t x = 0; x < n; ++x) u[i * n + x] += ml_rhs(G, n, i, x);
+            }
+            cg_total += c;
+            if (st) {
+#pragma omp critical
+                status = st;
+            }
+        }
+        free(work);
+    }
+    if (cg) *cg += cg_total;
+    return status;
+}
+
+/* u_{jm} = Phi_l(u_{jm-1}) + G_{jm} for every C-point j >= 1 (C-relaxation of level l) */
+static int ml_c_relax(const or_problem* P, const ml_level* L, double* u, const double* G, int64_t* cg)
+{
+    const int64_t n = nspace(P);
+    const int64_t NC = L->nt / L->m;
+    int status = OR_OK;
+    int64_t cg_total = 0;
+#pragma omp parallel num_threads(g_threads) reduction(+ : cg_total)
+    {
+        double* work = malloc(sizeof(double) * coarse_work_len(P));
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t j = 1; j <= NC; ++j) {
+            const int64_t i = j * L->m;
+            int64_t c = 0;
+            int st = ml_step(P, L, i, u + (i - 1) * n, u + i * n, work, &c);
+            for (int64_t x = 0; x < n; ++x) u[i * n + x] += ml_rhs(G, n, i, x);
+            cg_total += c;
+            if (st) {
+#pragma omp critical
+                status = st;
+            }
+        }
+        free(work);
+    }
+    if (cg) *cg += cg_total;
+    return status;
+}
+
+/* residual of level l's system injected to its C-points: rc_j = G_{jm} + Phi_l(u_{jm-1}) - u_{jm}
+   (j >= 1), rc_0 = G_0 - u_0 with G_0 = g0 on level 0 */
+static int ml_c_residual(const or_problem* P, const ml_level* L, const double* u, const double* G,
+                         const double* g0, double* rc, int64_t* cg)
+{
+    const int64_t n = nspace(P);
+    const int64_t NC = L->nt / L->m;
+    for (int64_t x = 0; x < n; ++x) rc[x] = (G ? G[x] : g0[x]) - u[x];
+    int status = OR_OK;
+    int64_t cg_total = 0;
+#pragma omp parallel num_threads(g_threads) reduction(+ : cg_total)
+    {
+        double* work = malloc(sizeof(double) * coarse_work_len(P));
+        double* phi = malloc(sizeof(double) * n);
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t j = 1; j <= NC; ++j) {
+            const int64_t i = j * L->m;
+            int64_t c = 0;
+            int st = ml_step(P, L, i, u + (i - 1) * n, phi, work, &c);
+            for (int64_t x = 0; x < n; ++x) rc[j * n + x] = (ml_rhs(G, n, i, x) + phi[x]) - u[i * n + x];
+            cg_total += c;
+            if (st) {
+#pragma omp critical
+                status = st;
+            }
+        }
+        free(phi);
+        free(work);
+    }
+    if (cg) *cg += cg_total;
+    return status;
+}
+
+/* The coarsest level: for every point p its local grid T^(l,p) = {max(0, p-k+1)..p} gets
+   v^(l,p) = R_I^(l,p) v and g^(l,p) = R_I^(l,p) g; the local problem
+   A^(l,p)(w) = A^(l,p)(v^(l,p)) + g^(l,p), with the identity on the grid's first point and
+   -Phi_l below the diagonal, is solved forward, and u_p = w_p (injection P_I^(l,p)). */
+static int ml_local_solves(const or_problem* P, const ml_level* L, int32_t k, const double* v, const double* g,
+                           double* u, int64_t* cg)
+{
+    const int64_t n = nspace(P);
+    const int64_t N = L->nt;
+    int status = OR_OK;
+    int64_t cg_total = 0;
+#pragma omp parallel num_threads(g_threads) reduction(+ : cg_total)
+    {
+        double* work = malloc(sizeof(double) * (coarse_work_len(P) + 3 * n));
+        double* w = work + coarse_work_len(P);
+        double* pw = w + n;
+        double* pv = pw + n;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t p = 0; p <= N; ++p) {
+            const int64_t s = or_window_start(p, k);
+            int st = OR_OK;
+            int64_t c = 0;
+            for (int64_t x = 0; x < n; ++x) w[x] = v[s * n + x] + g[s * n + x];
+            for (int64_t j = s + 1; j <= p && st == OR_OK; ++j) {
+                st = ml_step(P, L, j, v + (j - 1) * n, pv, work, &c);
+                if (st == OR_OK) st = ml_step(P, L, j, w, pw, work, &c);
+                for (int64_t x = 0; x < n; ++x) w[x] = pw[x] + ((v[j * n + x] - pv[x]) + g[j * n + x]);
+            }
+            for (int64_t x = 0; x < n; ++x) u[p * n + x] = w[x];
+            cg_total += c;
+            if (st) {
+#pragma omp critical
+                status = st;
+            }
+        }
+        free(work);
+    }
+    if (cg) *cg += cg_total;
+    return status;
+}
+
+/* One FAS V-cycle on level l (l < L-1) for A_l(u) = G (G = NULL on level 0: g_0 = g0, g_i = 0):
+   F(CF)^nu relaxation, injection of the approximation and of its residual, the next level
+   (recursively; local grids on the coarsest), e = u^(l+1) - v^(l+1), and the correction by ideal
+   interpolation (add e at the C-points, then F-relax). */
+static int ml_vcycle(const or_problem* P, const or_ml_options* O, const ml_level* lv, int l, double* u,
+                     const double* G, const double* g0, int64_t* cg)
+{
+    const ml_level* L = &lv[l];
+    const ml_level* Lc = &lv[l + 1];
+    const int64_t n = nspace(P);
+    const int64_t NC = Lc->nt; /* C-points 0..NC */
+    int st = ml_f_relax(P, L, u, G, cg);
+    if (!st && O->relax == 1) st = ml_c_relax(P, L, u, G, cg);
+    if (!st && O->relax == 1) st = ml_f_relax(P, L, u, G, cg);
+    if (st) return st;
+    double* v = malloc(sizeof(double) * (NC + 1) * n);
+    double* g = malloc(sizeof(double) * (NC + 1) * n);
+    double* uc = malloc(sizeof(double) * (NC + 1) * n);
+    st = ml_c_residual(P, L, u, G, g0, g, cg);
+    for (int64_t j = 0; j <= NC; ++j)
+        memcpy(v + j * n, u + j * L->m * n, sizeof(double) * n);
+    memcpy(uc, v, sizeof(double) * (NC + 1) * n);
+    if (!st) {
+        if (l + 1 == O->levels - 1) {
+            st = ml_local_solves(P, Lc, O->k, v, g, uc, cg);
+        } else {
+            /* the next level's FAS right-hand side G^(l+1) = A_{l+1}(v) + g */
+            double* Gc = malloc(sizeof(double) * (NC + 1) * n);
+            double* work = malloc(sizeof(double) * coarse_work_len(P));
+            for (int64_t x = 0; x < n; ++x) Gc[x] = v[x] + g[x];
+            for (int64_t j = 1; j <= NC && !st; ++j) {
+                st = ml_step(P, Lc, j, v + (j - 1) * n, Gc + j * n, work, cg);
+                for (int64_t x = 0; x < n; ++x) Gc[j * n + x] = (v[j * n + x] - Gc[j * n + x]) + g[j * n + x];
+            }
+            free(work);
+            if (!st) st = ml_vcycle(P, O, lv, l + 1, uc, Gc, NULL, cg);
+            free(Gc);
+        }
+    }
+    if (!st) {
+        for (int64_t j = 0; j <= NC; ++j)
+            for (int64_t x = 0; x < n; ++x) u[j * L->m * n + x] += uc[j * n + x] - v[j * n + x];
+        st = ml_f_relax(P, L, u, G, cg);
+    }
+    free(uc);
+    free(g);
+    free(v);
+    return st;
+}
+
+int or_ml_cycle(const or_problem* P, const or_ml_options* O, double* u, const double* g0, int64_t* cg)
+{
+    ml_level lv[OR_MAX_LEVELS];
+    int st = ml_levels(P, O, lv);
+    if (st) return st;
+    return ml_vcycle(P, O, lv, 0, u, NULL, g0, cg);
+}
+
+/* Multilevel FAS AT-MGRIT (Alg. 2) until ||g - A(u)||_2 <= tol, as or_atmgrit_solve: the guess is
+   F-relaxed first, hist[0] is its residual norm, hist[i] the norm after V-cycle i. */
+int or_ml_solve(const or_problem* P, const or_ml_options* O, double* u, double* hist, int32_t hist_cap,
+                or_stats* S)
+{
+    const int64_t n = nspace(P);
+    memset(S, 0, sizeof(*S));
+    ml_level lv[OR_MAX_LEVELS];
+    int st = ml_levels(P, O, lv);
+    if (st) return S->status = st;
+    double* g0 = malloc(sizeof(double) * n);
+    double* r = malloc(sizeof(double) * (P->nt + 1) * n);
+    memcpy(g0, u, sizeof(double) * n);
+    st = ml_f_relax(P, &lv[0], u, NULL, &S->cg_iters);
+    double res = 0.0;
+    if (!st) st = or_residual(P, u, g0, r, &S->cg_iters);
+    if (!st) res = or_norm2((P->nt + 1) * n, r);
+    if (!st && hist && hist_cap > 0) hist[0] = res;
+    int it = 0;
+    while (!st && !(res <= O->tol)) {
+        if (!isfinite(res)) {
+            st = OR_DIVERGED;
+            break;
+        }
+        if (it >= O->max_iter) {
+            st = OR_NOT_CONVERGED;
+            break;
+        }
+        st = ml_vcycle(P, O, lv, 0, u, NULL, g0, &S->cg_iters);
+        if (st) break;
+        ++it;
+        st = or_residual(P, u, g0, r, &S->cg_iters);
+        if (!st) res = or_norm2((P->nt + 1) * n, r);
+        if (!st && hist && it < hist_cap) hist[it] = res;
+    }
+    if (!st && !isfinite(res)) st = OR_DIVERGED;
+    S->iterations = it;
+    S->final_residual = res;
+    S->status = st;
+    free(r);
+    free(g0);
     return st;
 }
