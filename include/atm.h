@@ -115,6 +115,18 @@ typedef struct atm_options {
                               more than 128 points per side), CG elsewhere; 1 CG everywhere (to
                               coarse_cg_rtol).  Both take the same step: the eigenbasis solve is exact to
                               rounding, CG to its tolerance */
+    int32_t levels;        /* 0 or 2: two-level AT-MGRIT (Alg. 1).  3: the multilevel FAS V-cycle of
+                              Alg. 2 (section 2.2) over three levels: level 1 takes every m-th point of
+                              the fine grid and steps with dt m in coarse_substeps substeps (CG to
+                              coarse_cg_rtol); level 2, every m_coarse-th point of level 1 with step
+                              dt m m_coarse, is the coarsest and is replaced by the local grids of k
+                              points.  F(CF)^nu relaxation on levels 0 and 1, injection of the iterate
+                              and its residual, the FAS right-hand side A_1(v) + g on level 1, ideal
+                              interpolation back.  Precision 0, grids up to 128 per side, not with the
+                              learned propagator or the batch API; coarse_form and coarse_solver do
+                              not apply (the cycle is the FAS form, Psi by CG) */
+    int32_t m_coarse;      /* levels 3: coarsening factor from level 1 to level 2, >= 2, with
+                              floor(nt / m) >= m_coarse */
 } atm_options;
 
 typedef struct atm_stats {

@@ -49,7 +49,7 @@ constexpr double kLearnedGrowthLimit = 1e6;  // learned coarse solve: give up be
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t header, partials, ya, yb, e, tau, pk, d1, d2, large, spec, total;
+    size_t header, partials, ya, yb, e, tau, pk, d1, d2, large, spec, u1, y1a, y1b, tau2, e2, total;
 };
 
 int64_t n_intervals(const atm_problem* p, const atm_options* o) { return p->nt / o->m; }
@@ -60,6 +60,11 @@ bool large_grid(const atm_problem* p)
 {
     return p->kind != ATM_HEAT1D && (p->nx > atm::kMaxSide2D || p->ny > atm::kMaxSide2D);
 }
+
+// the multilevel FAS V-cycle over three levels (Alg. 2)
+bool three_level(const atm_options* o) { return o->levels == 3; }
+// level-2 points of the three-level cycle: 0..floor(floor(nt/m)/m_coarse)
+int64_t n_level2(const atm_problem* p, const atm_options* o) { return (p->nt / o->m) / o->m_coarse; }
 
 // the plain coarse propagator's form (coarse_form 3 falls back to the automatic choice)
 bool use_fas(const atm_problem* p, const atm_options* o)
@@ -72,7 +77,10 @@ bool use_fas(const atm_problem* p, const atm_options* o)
 bool learned(const atm_options* o) { return o->coarse_form == 3; }
 
 // Psi's implicit solve by the eigenbasis of the constant-coefficient operator (2D kinds, coarse_solver 0)
-bool spectral(const atm_problem* p, const atm_options* o) { return p->kind != ATM_HEAT1D && o->coarse_solver == 0; }
+bool spectral(const atm_problem* p, const atm_options* o)
+{
+    return p->kind != ATM_HEAT1D && o->coarse_solver == 0 && !three_level(o);
+}
 
 Layout layout(const atm_problem* p, const atm_options* o)
 {
@@ -90,8 +98,8 @@ Layout layout(const atm_problem* p, const atm_options* o)
     off += align_up(slab);
     L.e = off;
     off += align_up(slab);
-    L.tau = off;
-    off += use_fas(p, o) ? align_up(slab) : 0;
+    L.tau = off;  // the FAS right-hand side of the windows; with three levels, that of level 1
+    off += (use_fas(p, o) || three_level(o)) ? align_up(slab) : 0;
     // learned coarse solve: BF16 weights and two BF16 activation buffers for N_T + 1 fields
     const size_t act = learned(o) ? (size_t)n_space(p) * atm::cnn::C * 2 : 0;
     L.pk = off;
@@ -104,6 +112,19 @@ Layout layout(const atm_problem* p, const atm_options* o)
     off += large_grid(p) ? align_up((NT + 1) * 5 * (size_t)n_space(p) * sizeof(double)) : 0;
     L.spec = off;
     off += spectral(p, o) ? align_up(atm::spectral_table_doubles(p->nx, p->ny) * sizeof(double)) : 0;
+    // three levels: the level-1 iterate [N_T+1][n]; the level-1 sweeps' y (two), the level-2 FAS
+    // right-hand side and corrections, [N_2+1][n] each
+    const size_t slab2 = three_level(o) ? (size_t)(n_level2(p, o) + 1) * (size_t)n_space(p) * sizeof(double) : 0;
+    L.u1 = off;
+    off += three_level(o) ? align_up(slab) : 0;
+    L.y1a = off;
+    off += align_up(slab2);
+    L.y1b = off;
+    off += align_up(slab2);
+    L.tau2 = off;
+    off += align_up(slab2);
+    L.e2 = off;
+    off += align_up(slab2);
     L.total = off;
     return L;
 }
@@ -140,6 +161,17 @@ atm_status validate(const atm_problem* p, const atm_options* o)
         if (!(o->fallback_ratio >= 0.0)) return fail(ATM_ERR_INVALID_ARG, "fallback_ratio must be >= 0");
     }
     if (o->max_iter < 0) return fail(ATM_ERR_INVALID_ARG, "max_iter must be >= 0");
+    if (o->levels != 0 && o->levels != 2 && o->levels != 3)
+        return fail(ATM_ERR_UNSUPPORTED, "levels must be 2 (or 0) or 3");
+    if (o->levels == 3) {
+        if (o->m_coarse < 2) return fail(ATM_ERR_INVALID_ARG, "levels 3 needs m_coarse >= 2");
+        if (p->nt / o->m < o->m_coarse)
+            return fail(ATM_ERR_INVALID_ARG, "levels 3 needs floor(nt/m) (%lld) >= m_coarse (%d)",
+                        (long long)(p->nt / o->m), o->m_coarse);
+        if (o->precision != 0) return fail(ATM_ERR_UNSUPPORTED, "levels 3 runs in precision 0");
+        if (o->coarse_form == 3) return fail(ATM_ERR_UNSUPPORTED, "levels 3 uses the plain coarse propagator");
+        if (large_grid(p)) return fail(ATM_ERR_UNSUPPORTED, "levels 3 takes grids up to 128 x 128");
+    }
     if (!(o->tol >= 0.0)) return fail(ATM_ERR_INVALID_ARG, "tol must be >= 0");
     if (o->precision != 0 && o->precision != 1) return fail(ATM_ERR_INVALID_ARG, "precision must be 0 or 1");
     if (o->precision == 1 && p->kind == ATM_HEAT1D)
@@ -189,7 +221,7 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
     a.fail = &a.hdr->fail;
     a.cg_count = &a.hdr->cg_fine;
     a.partials = (double*)(base + L.partials);
-    a.tau = use_fas(p, o) ? (double*)(base + L.tau) : nullptr;
+    a.tau = (use_fas(p, o) || three_level(o)) ? (double*)(base + L.tau) : nullptr;
     a.nt = p->nt;
     a.n = n_space(p);
     a.NT = n_intervals(p, o);
@@ -202,6 +234,8 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
     const double dt = (p->tf - p->t0) / (double)p->nt;
     a.src = p->source;
     a.dt = dt;
+    a.gadd = nullptr;
+    a.fine_substeps = 1;
     a.fine = step_coef(p, dt);
     a.coarse = step_coef(p, dt * o->m / o->coarse_substeps);
     a.rtol2 = p->cg_rtol * p->cg_rtol;
@@ -539,6 +573,90 @@ int64_t window_psi_count(int64_t NT, int64_t k)
     return tot;
 }
 
+// ---------------------------------------------------------------------------
+// the multilevel FAS V-cycle over three levels (Alg. 2, section 2.2)
+// ---------------------------------------------------------------------------
+
+// Level 1 of the three-level cycle: every m-th fine point, step dt m in coarse_substeps substeps
+// (CG to coarse_cg_rtol), coarsening m_coarse to level 2 (step dt m m_coarse), the coarsest, whose
+// local grids are solved by the window kernels in FAS form.  gadd holds level 1's FAS right-hand
+// side, tau the windows'.
+atm::KArgs level1_args(const atm::KArgs& a0, const atm_problem* p, const atm_options* o, const Layout& L, char* base)
+{
+    atm::KArgs a1 = a0;
+    const double dt1 = (p->tf - p->t0) / (double)p->nt * o->m;
+    const int s = o->coarse_substeps;
+    a1.nt = p->nt / o->m;
+    a1.m = o->m_coarse;
+    a1.NT = a1.nt / o->m_coarse;
+    a1.fas = 1;
+    a1.fine_substeps = s;
+    a1.fine = step_coef(p, dt1 / s);
+    a1.substeps = s;
+    a1.coarse = step_coef(p, dt1 * o->m_coarse / s);
+    a1.rtol2 = a0.rtol2_coarse;
+    a1.src = nullptr;
+    a1.gadd = (double*)(base + L.tau);
+    a1.tau = (double*)(base + L.tau2);
+    a1.cg_count = &a0.hdr->cg_coarse;
+    a1.skip_unchanged = 0;
+    a1.skip_y_src = nullptr;
+    a1.spectral = 0;
+    return a1;
+}
+
+// a sweep of level 1 (no interval skipping: its right-hand side changes every cycle)
+atm_status do_level_sweep(atm::KArgs a, int mode, double* u, const double* aux, double* y, hipStream_t s)
+{
+    a.mode = mode;
+    a.u = u;
+    a.aux = aux;
+    a.y = y;
+    atm::launch_sweep(a, a.NT + 1, s);
+    return check_launch();
+}
+
+// Everything of one V-cycle below the fine level, given the relaxed fine iterate u and y0_j =
+// Phi(u_{jm-1}) (so the fine residual at C-point j is y0_j - u_{jm}): inject the iterate (u1 = v),
+// level 1's FAS right-hand side tau1_j = (v_j - Phi_1(v_{j-1})) + r_j, F(CF)^nu relaxation of level 1,
+// its C-point residuals and the local FAS problems of the coarsest level (windows), and level 1's
+// correction by ideal interpolation.  On return u1 holds level 1's corrected iterate; the fine
+// correction (e = u1 - v at the fine C-points, then F-interpolation) is the caller's sweep.
+atm_status do_lower_levels(const atm::KArgs& a0, const atm::KArgs& a1, const atm_options* o, double* u, double* y0,
+                           double* u1, double* tau1, double* y1a, double* y1b, double* e2, hipStream_t s,
+                           int64_t* psi_steps)
+{
+    atm::launch_gather(u, u1, a0.n, a0.m, a1.nt + 1, s);
+    atm_status st = check_launch();
+    if (st) return st;
+    atm::KArgs t0 = a0;
+    t0.u = u;
+    t0.y = y0;
+    t0.tau = tau1;  // a1.gadd
+    t0.cg_count = &a0.hdr->cg_coarse;
+    atm::launch_tau(t0, s);
+    if ((st = check_launch())) return st;
+    if ((st = do_level_sweep(a1, 0, u1, nullptr, y1a, s))) return st;
+    double* y1 = y1a;
+    int sweeps = 2;
+    if (o->relax == 1) {
+        if ((st = do_level_sweep(a1, 2, u1, y1a, y1b, s))) return st;
+        y1 = y1b;
+        sweeps = 3;
+    }
+    atm::KArgs c1 = a1;
+    c1.u = u1;
+    c1.y = y1;
+    c1.e = e2;
+    atm::launch_tau(c1, s);
+    if ((st = check_launch())) return st;
+    atm::launch_coarse(c1, s);
+    if ((st = check_launch())) return st;
+    if ((st = do_level_sweep(a1, 1, u1, e2, y1a, s))) return st;
+    *psi_steps += a1.nt + sweeps * a1.nt + a1.NT + window_psi_count(a1.NT, a1.k);
+    return ATM_OK;
+}
+
 }  // namespace
 
 
@@ -689,6 +807,7 @@ atm_status describe(int32_t n, const atm_problem* probs, const atm_options* opts
         if (learned(&in.o)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches use the plain coarse propagator", i);
         if (large_grid(&in.p)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take grids up to 128 x 128", i);
         if (in.p.source) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take no PDE source", i);
+        if (three_level(&in.o)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches run two levels", i);
         in.cls = in.p.kind == ATM_HEAT1D ? CLS_1D : (in.p.kind == ATM_AC2D ? CLS_2DP : CLS_2D);
         if (in.cls == CLS_1D && in.p.nx > 512)
             return fail(ATM_ERR_UNSUPPORTED, "instance %d: 1D batch instances take nx <= 512", i);
@@ -1105,6 +1224,12 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
     double* ya = (double*)(base + L.ya);
     double* yb = (double*)(base + L.yb);
     double* e = (double*)(base + L.e);
+    const bool ml = three_level(opts);
+    const atm::KArgs a1 = ml ? level1_args(a, prob, opts, L, base) : a;
+    double* u1 = (double*)(base + L.u1);
+    double* y1a = (double*)(base + L.y1a);
+    double* y1b = (double*)(base + L.y1b);
+    double* e2 = (double*)(base + L.e2);
     hipStream_t s = as_stream(stream);
     atm::launch_reset(a.hdr, s);
     if ((st = check_launch())) return st;
@@ -1172,6 +1297,9 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
             if (st) break;
             S.coarse_steps += window_psi_count(NT, opts->k) + NT;
             S.learned_cycles += 1;
+        } else if (ml) {
+            ATM_TIMED(kPhCoarse, do_lower_levels(a, a1, opts, u, ycur, u1, a.tau, y1a, y1b, e2, s, &S.coarse_steps));
+            if (st) break;
         } else {
             ATM_TIMED(kPhCoarse, do_coarse(a, u, ycur, e, s));
             if (st) break;
@@ -1179,7 +1307,11 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
         }
         // correction u_{pm} += e_p and F-interpolation; y_a receives Phi of every last F-point
         // (intervals that are skipped take theirs from y_b, the CF sweep's output)
-        ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 1, u, e, ya, s, skip, opts->relax == 1 ? yb : nullptr));
+        // (three levels: the fine C-points take level 1's values, i.e. u_{pm} += u1_p - v_p)
+        if (ml)
+            ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 2, u, u1, ya, s, skip, opts->relax == 1 ? yb : nullptr));
+        else
+            ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 1, u, e, ya, s, skip, opts->relax == 1 ? yb : nullptr));
         if (st) break;
         S.fine_steps += prob->nt;
         S.n_sweeps += 1;

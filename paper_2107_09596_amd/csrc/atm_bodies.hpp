@@ -33,7 +33,8 @@ __device__ __forceinline__ void sweep1d_body(const KArgs& a, int64_t j, double* 
     }
     for (int64_t t = 1; t <= total; ++t) {
         if (a.src && act) x = x + a.dt * a.src[(j * a.m + t) * a.n + i];
-        x = pcr_solve(f, a.nx, x, lds);
+        for (int q = 0; q < a.fine_substeps; ++q) x = pcr_solve(f, a.nx, x, lds);
+        if (a.gadd && act) x = x + a.gadd[(j * a.m + t) * a.n + i];
         if (act) {
             if (t < a.m)
                 a.u[(j * a.m + t) * a.n + i] = x;
@@ -92,7 +93,9 @@ __device__ __forceinline__ int step2d(const KArgs& a, const StepCoef& c, double 
     return cg2d<double, S, EX, PER, true>(a.g, c, st, v.x, v.r, v.q, lp, red, slot, rtol2, a.maxit, a.fail);
 }
 
-template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2>
+// LV: a level below the finest (substeps and the additive FAS right-hand side of the multilevel
+// cycle); a separate instantiation keeps the finest level's kernel as it is
+template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2, bool LV = false>
 __device__ __forceinline__ void sweep2d_body(const KArgs& a, int64_t j, double* lp, double* red)
 {
     int slot = 0;
@@ -119,7 +122,15 @@ __device__ __forceinline__ void sweep2d_body(const KArgs& a, int64_t j, double* 
     }
     long long its = 0;
     for (int64_t t = 1; t <= total; ++t) {
-        its += step2d<S, EX, PER>(a, a.fine, a.rtol2, st, v, lp, red, slot);
+        if constexpr (LV) {
+            for (int q = 0; q < a.fine_substeps; ++q) its += step2d<S, EX, PER>(a, a.fine, a.rtol2, st, v, lp, red, slot);
+            const double* g = a.gadd + (j * a.m + t) * a.n;
+#pragma unroll
+            for (int s = 0; s < S; ++s)
+                if (row_ok<EX, S>(st, s)) v.x[s] = v.x[s] + g[(int64_t)(st.gbase + s * nx)];
+        } else {
+            its += step2d<S, EX, PER>(a, a.fine, a.rtol2, st, v, lp, red, slot);
+        }
         double* dst = (t < a.m) ? a.u + (j * a.m + t) * a.n : a.y + (j + 1) * a.n;
         strip_store<S, EX>(dst, st, nx, v.x);
     }

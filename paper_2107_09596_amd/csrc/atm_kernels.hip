@@ -73,6 +73,15 @@ __global__ __launch_bounds__(kBlock2D) void sweep2d_kernel(KArgs a)
     sweep2d_body<S, EX, PER>(a, blockIdx.x, lp, red);
 }
 
+// a level below the finest of the multilevel cycle (substeps, additive FAS right-hand side)
+template <int S, bool EX, bool PER>
+__global__ __launch_bounds__(kBlock2D) void sweep2d_lv_kernel(KArgs a)
+{
+    __shared__ __align__(16) double lp[Lds2D<double>::size];
+    __shared__ double red[4 * kWaves2D];
+    sweep2d_body<S, EX, PER, kMaxSide2D + 2, true>(a, blockIdx.x, lp, red);
+}
+
 template <int S, bool EX, bool PER>
 __global__ __launch_bounds__(kBlock2D) void coarse2d_kernel(KArgs a)
 {
@@ -207,8 +216,30 @@ void launch_sweep(const KArgs& a, int64_t n_tasks, hipStream_t s)
 {
     if (a.is1d)
         hipLaunchKernelGGL(sweep1d_kernel, dim3(n_tasks), dim3(block1d(a)), 0, s, a);
+    else if (a.gadd)
+        ATM_LAUNCH_2D(sweep2d_lv_kernel, n_tasks, s, a);
     else
         ATM_LAUNCH_2D(sweep2d_kernel, n_tasks, s, a);
+}
+
+// dst[r] = src[r * stride_rows] for rows r = 0..rows-1 of n doubles (injection to C-points)
+__global__ __launch_bounds__(256) void gather_rows_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                                          int64_t n, int64_t stride_rows, int64_t rows)
+{
+    const int64_t total = n * rows;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256) {
+        const int64_t r = q / n, x = q - r * n;
+        dst[q] = src[r * stride_rows * n + x];
+    }
+}
+
+void launch_gather(const double* src, double* dst, int64_t n, int64_t stride_rows, int64_t rows, hipStream_t s)
+{
+    const int64_t total = n * rows;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) return;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3(blocks), dim3(256), 0, s, src, dst, n, stride_rows, rows);
 }
 
 void launch_tau(const KArgs& a, hipStream_t s)

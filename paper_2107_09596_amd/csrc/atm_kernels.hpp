@@ -38,6 +38,11 @@ struct KArgs {
     // right-hand side
     const double* src;
     double dt;
+    // levels below the finest (the multilevel V-cycle): each fine step is fine_substeps steps with
+    // the coefficients `fine`, and gadd [nt+1][n] (the level's FAS right-hand side) is added after
+    // it: u_i = Phi(u_{i-1}) + gadd_i.  fine_substeps = 1 and gadd = null on the finest level.
+    const double* gadd;
+    int fine_substeps;
     Grid2D g;
     StepCoef fine, coarse;
     double rtol2;         // squared CG tolerance of Phi
@@ -131,6 +136,7 @@ void launch_tau(const KArgs& a, hipStream_t s);
 void launch_coarse(const KArgs& a, hipStream_t s);
 void launch_norm(const KArgs& a, hipStream_t s);
 void launch_sequential(const KArgs& a, hipStream_t s);
+void launch_gather(const double* src, double* dst, int64_t n, int64_t stride_rows, int64_t rows, hipStream_t s);
 
 // mixed-precision form (atm_mixed.hip)
 constexpr int64_t kResidBlocks = 2048;  // most workgroups of the implicit-residual kernel

@@ -1,0 +1,148 @@
+"""GPU parity of the three-level FAS AT-MGRIT V-cycle (section 2.2, Alg. 2)
+through the C-ABI against the oracle's multilevel cycle.
+
+Bars as for two levels: iterates to 1e-12 relative to the largest magnitude,
+with CG-based integrators at cg_rtol 1e-14 on both sides for iterate-by-iterate
+comparisons; residual histories to 1e-11 relative down to a floor of 1e-13 of
+the initial residual.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+@pytest.fixture(scope="module")
+def atm():
+    import paper_2107_09596_amd as atm
+    return atm
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def assert_close(got, ref, rtol=1e-12, what=""):
+    scale = max(float(np.max(np.abs(ref))), 1e-300)
+    err = float(np.max(np.abs(got - ref)))
+    assert err <= rtol * scale, f"{what}: max|diff| = {err:.3e} > {rtol:.1e} * {scale:.3e}"
+
+
+CASES = [
+    # (kind, nx, ny, nt, m, m_coarse, k)
+    (W.HEAT1D, 9, 1, 96, 4, 3, 2),
+    (W.HEAT1D, 63, 1, 203, 4, 5, 3),      # ragged on both levels: 203 = 50 * 4 + 3, 50 = 10 * 5
+    (W.HEAT2D, 12, 9, 48, 4, 3, 2),
+    (W.HEAT2D, 64, 64, 50, 4, 3, 100),    # exactly tiled strips; k beyond the coarsest grid (MGRIT)
+    (W.HEAT2D, 100, 37, 53, 4, 2, 2),     # masked rows and columns, ragged
+    (W.AC2D, 16, 16, 48, 4, 3, 2),
+    (W.AC2D, 24, 20, 61, 3, 4, 3),        # ragged: 61 = 20 * 3 + 1, 20 = 5 * 4
+]
+
+
+def small(kind, nx, ny, nt, seed=5):
+    if kind == W.HEAT1D:
+        return W.small_problem(kind, seed=seed, nt=nt, nx=nx)
+    return W.small_problem(kind, seed=seed, nt=nt, nx=nx, ny=ny, cg_rtol=1e-14)
+
+
+def case_id(c):
+    return f"k{c[0]}-{c[1]}x{c[2]}-nt{c[3]}-m{c[4]}x{c[5]}-k{c[6]}"
+
+
+@pytest.mark.parametrize("relax", [0, 1])
+@pytest.mark.parametrize("case", CASES, ids=case_id)
+def test_vcycles_match_oracle(atm, orc, case, relax):
+    """After K V-cycles (K = 1, 3) the GPU iterate and history equal the oracle's."""
+    kind, nx, ny, nt, m, mc, k = case
+    p, u0 = small(kind, nx, ny, nt)
+    for K in (1, 3):
+        o = W.Options(m=m, k=k, relax=relax, tol=0.0, max_iter=K, levels=3, m_coarse=mc,
+                      coarse_substeps=2 if kind == W.AC2D else 1)
+        g = W.initial_guess(p, u0)
+        ref, hist, st = orc.ml_solve(p, o, g, allow_status=(orc.NOT_CONVERGED, orc.OK))
+        ud = dev(g)
+        status, ghist, gst = atm.atm_solve(p, o, ud)
+        assert gst["iterations"] == st["iterations"] == K
+        assert_close(host(ud), ref, what=f"u after {K} V-cycles")
+        np.testing.assert_allclose(ghist, hist[: len(ghist)], rtol=1e-11, atol=1e-13 * hist[0])
+
+
+@pytest.mark.parametrize("case", CASES, ids=case_id)
+def test_converged_solve_matches_oracle(atm, orc, case):
+    kind, nx, ny, nt, m, mc, k = case
+    p, u0 = small(kind, nx, ny, nt)
+    o = W.Options(m=m, k=k, relax=1, tol=1e-9, max_iter=60, levels=3, m_coarse=mc,
+                  coarse_substeps=2 if kind == W.AC2D else 1)
+    g = W.initial_guess(p, u0)
+    ref, hist, st = orc.ml_solve(p, o, g)
+    ud = dev(g)
+    status, ghist, gst = atm.atm_solve(p, o, ud)
+    assert status == atm.ATM_OK
+    assert gst["iterations"] == st["iterations"]
+    assert_close(host(ud), ref, what="converged three-level iterate")
+
+
+@pytest.mark.parametrize("relax,mc,k", [(0, 4, 32), (1, 8, 16), (0, 2, 200)])
+def test_k_study_problem_three_levels_full_size(atm, orc, relax, mc, k):
+    """The forced 1D heat problem at 1023 x 16384 (random guess, tol 1e-7), m = 64 and m_coarse as
+    given: same V-cycle count, iterate and history as the oracle."""
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    p, u0, src, ug = W.heat1d_forced()
+    o = W.Options(m=64, k=k, relax=relax, tol=1e-7, max_iter=100, levels=3, m_coarse=mc)
+    ref, hist, st = orc.ml_solve(p, o, ug, source=src)
+    orc.set_threads(1)
+    ud = dev(ug)
+    status, ghist, gst = atm.atm_solve(p, o, ud, source=dev(src))
+    assert status == atm.ATM_OK
+    assert gst["iterations"] == st["iterations"]
+    assert_close(host(ud), ref, what="k-study problem, three levels")
+    np.testing.assert_allclose(ghist, hist, rtol=1e-9, atol=1e-10)
+
+
+def test_heat2d_three_levels_full_size(atm, orc):
+    """2D heat 128 x 128, dt = 1/4096, 16384 steps, m = 64 (256 level-1 points), m_coarse 4, k = 32,
+    FCF, tol 1e-8: the oracle's residual of the returned iterate (every step solved from zero by CG)
+    meets the tolerance and agrees with the library's, and the iterate is sequential stepping's to
+    the accuracy that the residual bounds."""
+    p, o, u0 = W.three_level_config(4)
+    ud = dev(W.initial_guess(p, u0))
+    status, ghist, gst = atm.atm_solve(p, o, ud)
+    assert status == atm.ATM_OK and ghist[-1] <= o.tol
+    got = host(ud)
+    orc.set_threads(min(16, os.cpu_count() or 1))
+    r = orc.step_residual(p, got)
+    seq = orc.sequential(p, u0)
+    orc.set_threads(1)
+    res = float(np.sqrt(np.sum(r ** 2)))
+    assert res <= o.tol
+    # the library's norm takes each C-point residual from a CG solve to cg_rtol relative to its
+    # right-hand side, which moves each entry by at most cg_rtol |u_{jm-1}|
+    assert abs(res - gst["final_residual"]) <= p.cg_rtol * float(np.sqrt(np.sum(got ** 2))) + 1e-3 * res
+    # |u - u*| <= |A^-1| |r| with |A^-1| <= nt + 1 in the 2-norm (|Phi| <= 1)
+    assert np.sqrt(np.sum((got - seq) ** 2)) <= (p.nt + 1) * res
+
+
+def test_three_level_argument_checks(atm):
+    import torch
+    p, u0 = W.small_problem(W.HEAT1D, nt=16, nx=7)
+    u = torch.zeros((p.nt + 1, p.n), dtype=torch.float64, device="cuda")
+    for bad, code in [(dict(levels=3, m_coarse=1), atm.ATM_ERR_INVALID_ARG),
+                      (dict(levels=3, m_coarse=5), atm.ATM_ERR_INVALID_ARG),  # floor(16/4) = 4 < 5
+                      (dict(levels=4, m_coarse=2), atm.ATM_ERR_UNSUPPORTED)]:
+        o = W.Options(m=4, k=2, **bad)
+        with pytest.raises(atm.AtmError) as ei:
+            atm.atm_solve(p, o, u, ws=atm.workspace(1 << 20))
+        assert ei.value.status == code

@@ -209,6 +209,19 @@ def k_study_options(m: int, k: int, tol: float = 1e-7, max_iter: int = 200):
     return Options(m=m, k=k, relax=0, tol=tol, max_iter=max_iter, coarse_form=1)
 
 
+def three_level_config(m_coarse: int, k: int = None, relax: int = 1):
+    """The three-level workload: 2D heat as in c2 (128 x 128 interior, nu 0.1, dt 1/4096, CG rtol
+    1e-12, seed-2 initial field) over 16384 steps (t in [0, 4]), m = 64 so that level 1 has 256
+    points, m_coarse from level 1 to the coarsest level, k = N_2 / 2 by default (half the coarsest
+    points, the choice of section 5 for its three-level runs), FCF, tol 1e-8.
+    Returns (Problem, Options, u0)."""
+    p = Problem(HEAT2D, nx=128, ny=128, length=1.0, nu=0.1, t0=0.0, tf=4.0, nt=16384, cg_rtol=1e-12)
+    n2 = (16384 // 64) // m_coarse
+    o = Options(m=64, k=max(1, n2 // 2) if k is None else k, relax=relax, tol=1e-8, levels=3, m_coarse=m_coarse)
+    u0, _ = heat2d_u0(128, 128, seed=2)
+    return p, o, u0
+
+
 def small_problem(kind: int, seed: int = 0, nt: int = 48, nx: int = 7, ny: int = None, **kw):
     """A tiny problem of the given kind with seeded initial data, for oracle pins and parity."""
     if kind == HEAT1D:
