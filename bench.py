@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-solve leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the c1 and c3 solves")
     ap.add_argument("--no-k-study", action="store_true", help="skip the 1D heat k-study leg")
+    ap.add_argument("--no-three-level", action="store_true", help="skip the three-level V-cycle leg")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline solves only (no context solves, no other legs): for profiling runs")
     ap.add_argument("--batch-count", type=int, default=256,
@@ -258,6 +259,59 @@ def k_study_leg(runs=2):
     return {"workload": "1D heat u_t - u_xx = b on [0,3] x [0,pi], u = sin(pi x) cos t, 1023 unknowns, "
                         "nt 16383, random guess U[-1,1], F-relaxation, tol 1e-7, FP64",
             "unit": "space-time point-updates/s", "by_m": table}
+
+
+def three_level_leg(runs=2):
+    """Three-level FAS AT-MGRIT (Alg. 2) against three-level MGRIT (the coarsest grid global) as in
+    the paper's three-level table: 2D heat 128 x 128, dt 1/4096, 16384 steps, m = 64 (256 level-1
+    points), m_coarse in {2, 4, 8, 16}, k = N_2 / 2, FCF, tol 1e-8; plus two-level AT-MGRIT with the
+    same m.  Each entry: V-cycles, best wall time of `runs` solves, phase split of one more solve."""
+    import torch
+    import paper_2107_09596_amd as atm
+    import workloads as W
+    dev = torch.device("cuda:0")
+
+    def timed(p, o, guess, u):
+        ws = atm.workspace(atm.atm_workspace_bytes(p, o), device=dev)
+        best = None
+        for _ in range(runs):
+            u.copy_(guess)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            status, hist, st = atm.atm_solve(p, o, u, ws=ws, allow=(atm.ATM_OK,))
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            best = ms if best is None else min(best, ms)
+        o2 = W.Options(**{**o.__dict__, "profile": 1})
+        u.copy_(guess)
+        _, _, sp = atm.atm_solve(p, o2, u, ws=ws, allow=(atm.ATM_OK,))
+        return {"k": o.k, "cycles": st["iterations"], "ms": best, "value": p.n * p.nt / (best / 1e3),
+                "final_residual": hist[-1], "phase_ms": {key: sp[key] for key in ("ms_sweep", "ms_coarse", "ms_norm")}}
+
+    rows = []
+    p = None
+    for mc in (2, 4, 8, 16):
+        p, o, u0 = W.three_level_config(mc)
+        guess = torch.from_numpy(W.initial_guess(p, u0)).to(dev)
+        u = torch.empty_like(guess)
+        n2 = (p.nt // o.m) // mc
+        at = timed(p, o, guess, u)
+        mg = timed(p, W.Options(**{**o.__dict__, "k": n2 + 1}), guess, u)
+        rows.append({"m_coarse": mc, "coarsest_points": n2 + 1, "at_mgrit": at, "mgrit": mg,
+                     "speedup_vs_mgrit": mg["ms"] / at["ms"]})
+        print(f"# three levels m_coarse={mc}: AT-MGRIT k={o.k} {at['cycles']} cycles {at['ms']:.1f} ms, "
+              f"MGRIT {mg['cycles']} cycles {mg['ms']:.1f} ms", file=sys.stderr, flush=True)
+    p, o, u0 = W.three_level_config(4)
+    guess = torch.from_numpy(W.initial_guess(p, u0)).to(dev)
+    u = torch.empty_like(guess)
+    two = {}
+    for k in (W.default_k(p.nt // o.m), (p.nt // o.m) // 2):
+        two[str(k)] = timed(p, W.Options(**{**o.__dict__, "levels": 2, "k": k, "coarse_solver": 1}), guess, u)
+        print(f"# two levels m=64 k={k}: {two[str(k)]['cycles']} cycles {two[str(k)]['ms']:.1f} ms", file=sys.stderr,
+              flush=True)
+    return {"workload": "2D heat 128x128 interior, nu=0.1, dt=1/4096, Nt=16384, m=64, FCF, tol 1e-8, FP64, "
+                        "Psi by CG to 1e-12",
+            "unit": "space-time point-updates/s", "three_level": rows, "two_level_m64": two}
 
 
 def batch_leg(count, sample):
@@ -461,6 +515,8 @@ def main():
         out["other_configs"] = {"c1": config_leg("c1", 4), "c3": config_leg("c3", 1)}
     if not args.no_k_study:
         out["k_study"] = k_study_leg()
+    if not args.no_three_level:
+        out["three_level"] = three_level_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, u0, min(args.cpu_steps, p.nt))
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
