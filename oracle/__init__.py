@@ -49,7 +49,7 @@ class OrMlOptions(ctypes.Structure):
         ("tol", ctypes.c_double), ("coarse_cg_rtol", ctypes.c_double),
         ("levels", ctypes.c_int32), ("m", ctypes.c_int32 * (OR_MAX_LEVELS - 1)),
         ("k", ctypes.c_int32), ("relax", ctypes.c_int32), ("max_iter", ctypes.c_int32),
-        ("coarse_substeps", ctypes.c_int32),
+        ("coarse_substeps", ctypes.c_int32), ("nested", ctypes.c_int32),
     ]
 
 
@@ -102,6 +102,7 @@ def lib():
             "or_window_start": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int32]),
             "or_ml_cycle": (ctypes.c_int, [P, ctypes.POINTER(OrMlOptions), dp, dp, i64p]),
             "or_ml_solve": (ctypes.c_int, [P, ctypes.POINTER(OrMlOptions), dp, dp, ctypes.c_int32, S]),
+            "or_ml_nested": (ctypes.c_int, [P, ctypes.POINTER(OrMlOptions), dp, i64p]),
             "or_set_threads": (None, [ctypes.c_int]),
             "or_get_max_threads": (ctypes.c_int, []),
         }
@@ -137,7 +138,8 @@ def _ml_opts(o) -> OrMlOptions:
     the coarser levels), k, relax, tol, max_iter, coarse_substeps and coarse_cg_rtol as for two levels."""
     ms = (ctypes.c_int32 * (OR_MAX_LEVELS - 1))(*([o.m] + [o.m_coarse] * (OR_MAX_LEVELS - 2)))
     return OrMlOptions(tol=o.tol, coarse_cg_rtol=getattr(o, "coarse_cg_rtol", 0.0), levels=o.levels, m=ms, k=o.k,
-                       relax=o.relax, max_iter=o.max_iter, coarse_substeps=o.coarse_substeps)
+                       relax=o.relax, max_iter=o.max_iter, coarse_substeps=o.coarse_substeps,
+                       nested=int(getattr(o, "nested", 0)))
 
 
 def _ptr(a: np.ndarray):
@@ -316,3 +318,10 @@ def ml_solve(p, o, u, hist_cap=1000, allow_status=(OK,), source=None):
         raise OracleError(status, "ml_solve")
     stats = {name: getattr(st, name) for name, _ in OrStats._fields_}
     return u, hist[: st.iterations + 1].copy(), stats
+
+
+def ml_nested(p, o, u):
+    """The nested-iteration initial guess (o.levels levels) built from a copy of u (u[0] = g_0)."""
+    u = np.array(u, dtype=np.float64, order="C")
+    _check(lib().or_ml_nested(ctypes.byref(_prob(p)), ctypes.byref(_ml_opts(o)), _ptr(u), None), "ml_nested")
+    return u

@@ -848,6 +848,7 @@ typedef struct {
     int32_t levels;
     int32_t m[OR_MAX_LEVELS - 1];
     int32_t k, relax, max_iter, coarse_substeps;
+    int32_t nested; /* 1: start from the nested-iteration guess (or_ml_nested) */
 } or_ml_options;
 
 typedef struct {
@@ -1085,6 +1086,58 @@ static int ml_vcycle(const or_problem* P, const or_ml_options* O, const ml_level
     return st;
 }
 
+/* Nested iteration (section 2.2; the setup phase of section 5): an improved initial guess built
+   from the coarsest level up.  The guess u (u_0 = g_0) is injected to every level; on the coarsest
+   level the local problems of the re-discretised system A_{L-1}(w) = g_{L-1} (g: u_0 at the first
+   point, zero elsewhere) are solved from the injected guess v in FAS form, i.e. with the coarse
+   residual g - A_{L-1}(v) as right-hand side; then each finer level takes the coarser level's
+   values at its C-points and F-relaxes them (ideal interpolation), and every level between gets one
+   V-cycle for its own re-discretised system.  The fine iterate returned is F-relaxed.  No source:
+   the coarse levels would need it re-discretised too. */
+int or_ml_nested(const or_problem* P, const or_ml_options* O, double* u, int64_t* cg)
+{
+    if (P->src) return OR_INVALID;
+    ml_level lv[OR_MAX_LEVELS];
+    int st = ml_levels(P, O, lv);
+    if (st) return st;
+    const int64_t n = nspace(P);
+    const int Lc = O->levels - 1;
+    double* lu[OR_MAX_LEVELS];
+    lu[0] = u;
+    for (int l = 1; l <= Lc; ++l) {
+        lu[l] = malloc(sizeof(double) * (lv[l].nt + 1) * n);
+        for (int64_t j = 0; j <= lv[l].nt; ++j)
+            memcpy(lu[l] + j * n, lu[l - 1] + j * lv[l - 1].m * n, sizeof(double) * n);
+    }
+    /* coarsest level: residual of the injected guess, then the local problems */
+    {
+        const ml_level* L = &lv[Lc];
+        double* g = malloc(sizeof(double) * (L->nt + 1) * n);
+        double* w = malloc(sizeof(double) * (L->nt + 1) * n);
+        double* work = malloc(sizeof(double) * coarse_work_len(P));
+        const double* v = lu[Lc];
+        for (int64_t x = 0; x < n; ++x) g[x] = u[x] - v[x];
+        for (int64_t j = 1; j <= L->nt && !st; ++j) {
+            st = ml_step(P, L, j, v + (j - 1) * n, g + j * n, work, cg);
+            for (int64_t x = 0; x < n; ++x) g[j * n + x] = g[j * n + x] - v[j * n + x];
+        }
+        free(work);
+        if (!st) st = ml_local_solves(P, L, O->k, v, g, w, cg);
+        if (!st) memcpy(lu[Lc], w, sizeof(double) * (L->nt + 1) * n);
+        free(w);
+        free(g);
+    }
+    /* up the hierarchy: ideal interpolation, and one V-cycle on every level between */
+    for (int l = Lc - 1; l >= 0 && !st; --l) {
+        for (int64_t j = 0; j <= lv[l + 1].nt; ++j)
+            memcpy(lu[l] + j * lv[l].m * n, lu[l + 1] + j * n, sizeof(double) * n);
+        st = ml_f_relax(P, &lv[l], lu[l], NULL, cg);
+        if (!st && l > 0) st = ml_vcycle(P, O, lv, l, lu[l], NULL, u, cg);
+    }
+    for (int l = 1; l <= Lc; ++l) free(lu[l]);
+    return st;
+}
+
 int or_ml_cycle(const or_problem* P, const or_ml_options* O, double* u, const double* g0, int64_t* cg)
 {
     ml_level lv[OR_MAX_LEVELS];
@@ -1106,7 +1159,8 @@ int or_ml_solve(const or_problem* P, const or_ml_options* O, double* u, double* 
     double* g0 = malloc(sizeof(double) * n);
     double* r = malloc(sizeof(double) * (P->nt + 1) * n);
     memcpy(g0, u, sizeof(double) * n);
-    st = ml_f_relax(P, &lv[0], u, NULL, &S->cg_iters);
+    if (O->nested) st = or_ml_nested(P, O, u, &S->cg_iters);
+    if (!st) st = ml_f_relax(P, &lv[0], u, NULL, &S->cg_iters);
     double res = 0.0;
     if (!st) st = or_residual(P, u, g0, r, &S->cg_iters);
     if (!st) res = or_norm2((P->nt + 1) * n, r);

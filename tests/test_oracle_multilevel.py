@@ -139,3 +139,74 @@ def test_three_levels_with_source(orc):
     u, hist, st = orc.ml_solve(p, o, ug, source=src)
     assert hist[-1] <= o.tol
     assert np.abs(u - orc.sequential(p, u0, source=src)).max() <= 1e-9
+
+
+# ---------------------------------------------------------------------------
+# nested iteration (section 2.2): the initial guess from the coarse levels up
+# ---------------------------------------------------------------------------
+
+def nested_windows(Psi, v, k, n):
+    """Local problems of the re-discretised coarse system A(w) = g (g = u_0, 0, ..) from the injected
+    guess v in FAS form: window p starts at s = max(0, p-k+1) from v_s + r_s, r the coarse residual
+    (r_0 = 0, r_s = Psi v_{s-1} - v_s), and steps with Psi; its last value is w_p."""
+    N = v.shape[0]
+    w = np.zeros_like(v)
+    for p in range(N):
+        s = max(0, p - k + 1)
+        x = v[0] if s == 0 else Psi @ v[s - 1]
+        for _ in range(s + 1, p + 1):
+            x = Psi @ x
+        w[p] = x
+    return w
+
+
+def interpolate(Phi, uc, N, m):
+    """Ideal interpolation: C-point j takes uc_j, point jm+i takes Phi^i uc_j."""
+    out = np.zeros((N, uc.shape[1]))
+    for t in range(N):
+        j, i = divmod(t, m)
+        out[t] = np.linalg.matrix_power(Phi, i) @ uc[j]
+    return out
+
+
+@pytest.mark.parametrize("k", [2, 3, 50])
+def test_nested_two_levels_closed_form(orc, k):
+    p, u0 = W.small_problem(W.HEAT1D, seed=4, nt=29, nx=3, tf=0.3)   # ragged: 29 = 9 * 3 + 2
+    o = W.Options(m=3, k=k, relax=1, levels=2, coarse_form=2)
+    g = W.initial_guess(p, u0, "random", seed=2)
+    Phi, Psi = phi_1d(p, p.dt), phi_1d(p, p.dt * o.m)
+    v = g[::o.m][: p.nt // o.m + 1]
+    ref = interpolate(Phi, nested_windows(Psi, v, k, p.n), p.nt + 1, o.m)
+    got = orc.ml_nested(p, o, g)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("relax", [0, 1])
+@pytest.mark.parametrize("nt,m0,m1,k", [(24, 2, 3, 2), (27, 2, 3, 3), (36, 3, 2, 9)])
+def test_nested_three_levels_assembled(orc, relax, nt, m0, m1, k):
+    p, u0 = W.small_problem(W.HEAT1D, seed=4, nt=nt, nx=2, tf=0.3)
+    o = W.Options(m=m0, k=k, relax=relax, levels=3, m_coarse=m1, coarse_form=2)
+    g = W.initial_guess(p, u0, "random", seed=2)
+    n = p.n
+    Phi0, Phi1, Phi2 = phi_1d(p, p.dt), phi_1d(p, p.dt * m0), phi_1d(p, p.dt * m0 * m1)
+    N1 = p.nt // m0
+    N2 = N1 // m1
+    v2 = g[::m0][: N1 + 1][::m1][: N2 + 1]
+    u1 = interpolate(Phi1, nested_windows(Phi2, v2, k, n), N1 + 1, m1)
+    # one level-1 V-cycle for A_1(u) = (u_0, 0, ..): u1 <- u1* + E_1 (u1 - u1*), u1* its sequential solution
+    star = np.array([np.linalg.matrix_power(Phi1, i) @ u0 for i in range(N1 + 1)])
+    E1 = two_level_E(Phi1, Phi2, N1 + 1, m1, k, n, relax)
+    u1 = star + (E1 @ (u1 - star).reshape(-1)).reshape(N1 + 1, n)
+    ref = interpolate(Phi0, u1, p.nt + 1, m0)
+    got = orc.ml_nested(p, o, g)
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+@pytest.mark.parametrize("kind", [W.HEAT1D, W.HEAT2D, W.AC2D])
+def test_nested_solve_reaches_sequential(orc, levels, kind):
+    p, u0 = W.small_problem(kind, seed=3, nt=97, nx=6)
+    o = W.Options(m=4, k=2, relax=1, tol=1e-10, max_iter=100, levels=levels, m_coarse=3, coarse_form=2, nested=1)
+    u, hist, st = orc.ml_solve(p, o, W.initial_guess(p, u0))
+    assert hist[-1] <= o.tol
+    assert np.abs(u - orc.sequential(p, u0)).max() <= 1e-9
