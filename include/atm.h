@@ -127,6 +127,14 @@ typedef struct atm_options {
                               not apply (the cycle is the FAS form, Psi by CG) */
     int32_t m_coarse;      /* levels 3: coarsening factor from level 1 to level 2, >= 2, with
                               floor(nt / m) >= m_coarse */
+    int32_t nested;        /* 1: nested iteration (section 2.2) replaces the initial guess before the
+                              first cycle: the guess at the coarse levels' points is injected, the
+                              coarsest level's local problems of the re-discretised system are solved
+                              from it (each window starting from the coarse residual of the injected
+                              guess), and every finer level takes the coarser values at its C-points and
+                              F-relaxes them, a level between getting one V-cycle of its own system.
+                              Precision 0, grids up to 128 per side, no source, not the learned
+                              propagator; its time is atm_stats.ms_setup */
 } atm_options;
 
 typedef struct atm_stats {
@@ -146,6 +154,7 @@ typedef struct atm_stats {
     int32_t iterations;    /* cycles applied (number of coarse corrections) */
     int32_t n_sweeps;      /* sweep launches */
     int32_t learned_cycles; /* coarse_form 3: cycles whose correction came from the learned propagator */
+    double ms_setup;       /* nested = 1: wall time of the nested-iteration setup (included in ms_total) */
 } atm_stats;
 
 /* Number of coarse intervals N_T = floor(nt / m); C-points are 0..N_T. */

@@ -42,7 +42,7 @@ class AtmOptions(ctypes.Structure):
         ("m", ctypes.c_int32), ("k", ctypes.c_int32), ("relax", ctypes.c_int32),
         ("max_iter", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32), ("coarse_form", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("profile", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
-        ("levels", ctypes.c_int32), ("m_coarse", ctypes.c_int32),
+        ("levels", ctypes.c_int32), ("m_coarse", ctypes.c_int32), ("nested", ctypes.c_int32),
     ]
 
 
@@ -53,6 +53,7 @@ class AtmStats(ctypes.Structure):
         ("fine_steps", ctypes.c_int64), ("coarse_steps", ctypes.c_int64), ("cg_fine", ctypes.c_int64),
         ("cg_coarse", ctypes.c_int64), ("fine_steps_skipped", ctypes.c_int64),
         ("iterations", ctypes.c_int32), ("n_sweeps", ctypes.c_int32), ("learned_cycles", ctypes.c_int32),
+        ("ms_setup", ctypes.c_double),
     ]
 
 
@@ -157,4 +158,4 @@ def options(o) -> AtmOptions:
                       max_iter=o.max_iter, coarse_substeps=o.coarse_substeps, coarse_form=o.coarse_form,
                       precision=getattr(o, "precision", 0), profile=int(getattr(o, "profile", 0)),
                       coarse_solver=int(getattr(o, "coarse_solver", 0)), levels=int(getattr(o, "levels", 2)),
-                      m_coarse=int(getattr(o, "m_coarse", 0)))
+                      m_coarse=int(getattr(o, "m_coarse", 0)), nested=int(getattr(o, "nested", 0)))

@@ -172,6 +172,13 @@ atm_status validate(const atm_problem* p, const atm_options* o)
         if (o->coarse_form == 3) return fail(ATM_ERR_UNSUPPORTED, "levels 3 uses the plain coarse propagator");
         if (large_grid(p)) return fail(ATM_ERR_UNSUPPORTED, "levels 3 takes grids up to 128 x 128");
     }
+    if (o->nested != 0 && o->nested != 1) return fail(ATM_ERR_INVALID_ARG, "nested must be 0 or 1");
+    if (o->nested == 1) {
+        if (p->source) return fail(ATM_ERR_UNSUPPORTED, "nested iteration takes no PDE source");
+        if (o->precision != 0) return fail(ATM_ERR_UNSUPPORTED, "nested iteration runs in precision 0");
+        if (o->coarse_form == 3) return fail(ATM_ERR_UNSUPPORTED, "nested iteration uses the plain coarse propagator");
+        if (large_grid(p)) return fail(ATM_ERR_UNSUPPORTED, "nested iteration takes grids up to 128 x 128");
+    }
     if (!(o->tol >= 0.0)) return fail(ATM_ERR_INVALID_ARG, "tol must be >= 0");
     if (o->precision != 0 && o->precision != 1) return fail(ATM_ERR_INVALID_ARG, "precision must be 0 or 1");
     if (o->precision == 1 && p->kind == ATM_HEAT1D)
@@ -236,6 +243,7 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
     a.dt = dt;
     a.gadd = nullptr;
     a.fine_substeps = 1;
+    a.psi_only = 0;
     a.fine = step_coef(p, dt);
     a.coarse = step_coef(p, dt * o->m / o->coarse_substeps);
     a.rtol2 = p->cg_rtol * p->cg_rtol;
@@ -616,26 +624,14 @@ atm_status do_level_sweep(atm::KArgs a, int mode, double* u, const double* aux, 
     return check_launch();
 }
 
-// Everything of one V-cycle below the fine level, given the relaxed fine iterate u and y0_j =
-// Phi(u_{jm-1}) (so the fine residual at C-point j is y0_j - u_{jm}): inject the iterate (u1 = v),
-// level 1's FAS right-hand side tau1_j = (v_j - Phi_1(v_{j-1})) + r_j, F(CF)^nu relaxation of level 1,
-// its C-point residuals and the local FAS problems of the coarsest level (windows), and level 1's
-// correction by ideal interpolation.  On return u1 holds level 1's corrected iterate; the fine
-// correction (e = u1 - v at the fine C-points, then F-interpolation) is the caller's sweep.
-atm_status do_lower_levels(const atm::KArgs& a0, const atm::KArgs& a1, const atm_options* o, double* u, double* y0,
-                           double* u1, double* tau1, double* y1a, double* y1b, double* e2, hipStream_t s,
-                           int64_t* psi_steps)
+// One cycle of level 1 for its system (right-hand side a1.gadd: level 1's FAS right-hand side, or
+// null for the re-discretised system of nested iteration): F(CF)^nu relaxation, its C-point
+// residuals and the local FAS problems of the coarsest level (windows), and the correction by ideal
+// interpolation.
+atm_status level1_cycle(const atm::KArgs& a1, const atm_options* o, double* u1, double* y1a, double* y1b, double* e2,
+                        hipStream_t s, int64_t* psi_steps)
 {
-    atm::launch_gather(u, u1, a0.n, a0.m, a1.nt + 1, s);
-    atm_status st = check_launch();
-    if (st) return st;
-    atm::KArgs t0 = a0;
-    t0.u = u;
-    t0.y = y0;
-    t0.tau = tau1;  // a1.gadd
-    t0.cg_count = &a0.hdr->cg_coarse;
-    atm::launch_tau(t0, s);
-    if ((st = check_launch())) return st;
+    atm_status st;
     if ((st = do_level_sweep(a1, 0, u1, nullptr, y1a, s))) return st;
     double* y1 = y1a;
     int sweeps = 2;
@@ -653,8 +649,88 @@ atm_status do_lower_levels(const atm::KArgs& a0, const atm::KArgs& a1, const atm
     atm::launch_coarse(c1, s);
     if ((st = check_launch())) return st;
     if ((st = do_level_sweep(a1, 1, u1, e2, y1a, s))) return st;
-    *psi_steps += a1.nt + sweeps * a1.nt + a1.NT + window_psi_count(a1.NT, a1.k);
+    *psi_steps += sweeps * a1.nt + a1.NT + window_psi_count(a1.NT, a1.k);
     return ATM_OK;
+}
+
+// Everything of one V-cycle below the fine level, given the relaxed fine iterate u and y0_j =
+// Phi(u_{jm-1}) (so the fine residual at C-point j is y0_j - u_{jm}): inject the iterate (u1 = v),
+// level 1's FAS right-hand side tau1_j = (v_j - Phi_1(v_{j-1})) + r_j, and level 1's cycle.  On
+// return u1 holds level 1's corrected iterate; the fine correction (e = u1 - v at the fine C-points,
+// then F-interpolation) is the caller's sweep.
+atm_status do_lower_levels(const atm::KArgs& a0, const atm::KArgs& a1, const atm_options* o, double* u, double* y0,
+                           double* u1, double* tau1, double* y1a, double* y1b, double* e2, hipStream_t s,
+                           int64_t* psi_steps)
+{
+    atm::launch_gather(u, u1, a0.n, a0.m, a1.nt + 1, s);
+    atm_status st = check_launch();
+    if (st) return st;
+    atm::KArgs t0 = a0;
+    t0.u = u;
+    t0.y = y0;
+    t0.tau = tau1;  // a1.gadd
+    t0.cg_count = &a0.hdr->cg_coarse;
+    atm::launch_tau(t0, s);
+    if ((st = check_launch())) return st;
+    *psi_steps += a1.nt;
+    return level1_cycle(a1, o, u1, y1a, y1b, e2, s, psi_steps);
+}
+
+// Nested iteration (section 2.2): the initial guess rebuilt from the coarse levels up.  Two levels:
+// the windows of the re-discretised coarse system from the injected guess, then the correction
+// (C-points take the windows' values) with F-interpolation.  Three levels: inject to level 1, the
+// coarsest windows, interpolation to level 1, one cycle of level 1's own system, interpolation to
+// the fine level.  u ends F-relaxed.
+atm_status nested_setup(const atm::KArgs& a, const atm::KArgs& a1, const atm_problem* p, const atm_options* o, double* u,
+                        double* ya, double* e, double* u1, double* y1a, double* y1b, double* e2, hipStream_t s,
+                        atm_stats& S);
+
+// The coarsest level of nested iteration: y_j = Psi(v_{j-1}) for the injected guess v (the C-points
+// of c.u), then the windows, which read the coarse residual y_j - v_j, into e (FAS: w_p - v_p).
+atm_status nested_coarsest(atm::KArgs c, double* u, double* y, double* e, hipStream_t s)
+{
+    c.cg_count = &c.hdr->cg_coarse;
+    c.u = u;
+    c.y = y;
+    c.e = e;
+    if (c.spectral) atm::launch_spectral_tables(c, s);
+    atm::KArgs q = c;
+    q.psi_only = 1;
+    atm::launch_tau(q, s);
+    atm_status st = check_launch();
+    if (st) return st;
+    if (c.fas) {
+        atm::launch_tau(c, s);
+        if ((st = check_launch())) return st;
+    }
+    atm::launch_coarse(c, s);
+    return check_launch();
+}
+
+atm_status nested_setup(const atm::KArgs& a, const atm::KArgs& a1, const atm_problem* p, const atm_options* o, double* u,
+                        double* ya, double* e, double* u1, double* y1a, double* y1b, double* e2, hipStream_t s,
+                        atm_stats& S)
+{
+    atm_status st;
+    if (!three_level(o)) {
+        if ((st = nested_coarsest(a, u, ya, e, s))) return st;
+        S.coarse_steps += a.NT * (a.fas ? 2 : 1) + window_psi_count(a.NT, a.k);
+        S.fine_steps += p->nt;
+        S.n_sweeps += 1;
+        return do_sweep(a, p, o, 1, u, e, ya, s);
+    }
+    atm::launch_gather(u, u1, a.n, a.m, a1.nt + 1, s);
+    if ((st = check_launch())) return st;
+    atm::KArgs b1 = a1;
+    b1.gadd = nullptr;  // level 1's own re-discretised system
+    if ((st = nested_coarsest(b1, u1, y1a, e2, s))) return st;
+    if ((st = do_level_sweep(b1, 1, u1, e2, y1b, s))) return st;
+    int64_t steps = 2 * b1.NT + window_psi_count(b1.NT, b1.k) + b1.nt;
+    if ((st = level1_cycle(b1, o, u1, y1a, y1b, e2, s, &steps))) return st;
+    S.coarse_steps += steps;
+    S.fine_steps += p->nt;
+    S.n_sweeps += 1;
+    return do_sweep(a, p, o, 2, u, u1, ya, s);
 }
 
 }  // namespace
@@ -1256,6 +1332,12 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
     auto stop_norm = [&](double* yv, double* out) {
         return mixed ? do_implicit_norm(a, u, s, out, &h) : do_norm(a, u, yv, s, out, &h);
     };
+    if (opts->nested == 1) {
+        const auto t_setup = std::chrono::steady_clock::now();
+        if ((st = nested_setup(a, a1, prob, opts, u, ya, e, u1, y1a, y1b, e2, s, S))) return st;
+        ATM_HIP(hipStreamSynchronize(s));
+        S.ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup).count();
+    }
     // F-relax the initial guess, then its residual
     ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 0, u, nullptr, ya, s));
     if (st) return st;

@@ -124,10 +124,12 @@ __device__ __forceinline__ void sweep2d_body(const KArgs& a, int64_t j, double* 
     for (int64_t t = 1; t <= total; ++t) {
         if constexpr (LV) {
             for (int q = 0; q < a.fine_substeps; ++q) its += step2d<S, EX, PER>(a, a.fine, a.rtol2, st, v, lp, red, slot);
-            const double* g = a.gadd + (j * a.m + t) * a.n;
+            if (a.gadd) {
+                const double* g = a.gadd + (j * a.m + t) * a.n;
 #pragma unroll
-            for (int s = 0; s < S; ++s)
-                if (row_ok<EX, S>(st, s)) v.x[s] = v.x[s] + g[(int64_t)(st.gbase + s * nx)];
+                for (int s = 0; s < S; ++s)
+                    if (row_ok<EX, S>(st, s)) v.x[s] = v.x[s] + g[(int64_t)(st.gbase + s * nx)];
+            }
         } else {
             its += step2d<S, EX, PER>(a, a.fine, a.rtol2, st, v, lp, red, slot);
         }
@@ -330,8 +332,12 @@ __device__ __forceinline__ void tau2d_body(const KArgs& a, int64_t j, double* lp
     for (int s = 0; s < S; ++s)
         if (row_ok<EX, S>(st, s)) {
             const int64_t idx = (int64_t)(st.gbase + s * nx);
-            const double vj = a.u[(j * a.m) * a.n + idx];
-            a.tau[j * a.n + idx] = (vj - v.x[s]) + cpoint_residual(a, j, idx);
+            if (a.psi_only) {
+                a.y[j * a.n + idx] = v.x[s];
+            } else {
+                const double vj = a.u[(j * a.m) * a.n + idx];
+                a.tau[j * a.n + idx] = (vj - v.x[s]) + cpoint_residual(a, j, idx);
+            }
         }
     count_cg(a, its);
 }

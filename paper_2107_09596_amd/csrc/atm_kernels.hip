@@ -40,8 +40,12 @@ __global__ __launch_bounds__(1024) void tau1d_kernel(KArgs a)
     double v = act ? a.u[((j - 1) * a.m) * a.n + i] : 0.0;
     v = psi1d(a, fc, v, lds);
     if (act) {
-        const double vj = a.u[(j * a.m) * a.n + i];
-        a.tau[j * a.n + i] = (vj - v) + cpoint_residual(a, j, i);
+        if (a.psi_only) {
+            a.y[j * a.n + i] = v;
+        } else {
+            const double vj = a.u[(j * a.m) * a.n + i];
+            a.tau[j * a.n + i] = (vj - v) + cpoint_residual(a, j, i);
+        }
     }
 }
 
@@ -216,7 +220,7 @@ void launch_sweep(const KArgs& a, int64_t n_tasks, hipStream_t s)
 {
     if (a.is1d)
         hipLaunchKernelGGL(sweep1d_kernel, dim3(n_tasks), dim3(block1d(a)), 0, s, a);
-    else if (a.gadd)
+    else if (a.gadd || a.fine_substeps > 1)
         ATM_LAUNCH_2D(sweep2d_lv_kernel, n_tasks, s, a);
     else
         ATM_LAUNCH_2D(sweep2d_kernel, n_tasks, s, a);

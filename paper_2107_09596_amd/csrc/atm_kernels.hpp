@@ -43,6 +43,9 @@ struct KArgs {
     // it: u_i = Phi(u_{i-1}) + gadd_i.  fine_substeps = 1 and gadd = null on the finest level.
     const double* gadd;
     int fine_substeps;
+    // FAS right-hand-side kernels: 1 writes y_j = Psi(u_{(j-1)m}) instead of tau_j, so that the
+    // window kernels see the coarse residual y_j - u_{jm} of the injected iterate (nested iteration)
+    int psi_only;
     Grid2D g;
     StepCoef fine, coarse;
     double rtol2;         // squared CG tolerance of Phi

@@ -146,3 +146,58 @@ def test_three_level_argument_checks(atm):
         with pytest.raises(atm.AtmError) as ei:
             atm.atm_solve(p, o, u, ws=atm.workspace(1 << 20))
         assert ei.value.status == code
+
+
+# ---------------------------------------------------------------------------
+# nested iteration (the initial guess from the coarse levels up)
+# ---------------------------------------------------------------------------
+
+NESTED = [
+    # (kind, nx, ny, nt, m, m_coarse, k, levels, coarse_solver)
+    (W.HEAT1D, 9, 1, 97, 4, 3, 2, 2, 1),
+    (W.HEAT1D, 63, 1, 203, 4, 5, 3, 3, 1),
+    (W.HEAT2D, 12, 9, 48, 4, 3, 3, 2, 1),
+    (W.HEAT2D, 12, 9, 48, 4, 3, 3, 2, 0),     # Psi in the eigenbasis
+    (W.HEAT2D, 100, 37, 53, 4, 2, 2, 3, 1),
+    (W.AC2D, 16, 16, 48, 4, 3, 100, 2, 1),
+    (W.AC2D, 24, 20, 61, 3, 4, 2, 3, 1),
+]
+
+
+def nested_id(c):
+    return f"k{c[0]}-{c[1]}x{c[2]}-nt{c[3]}-m{c[4]}x{c[5]}-k{c[6]}-L{c[7]}-s{c[8]}"
+
+
+def nested_opts(c, **kw):
+    kind, nx, ny, nt, m, mc, k, levels, solver = c
+    return W.Options(m=m, k=k, relax=1, levels=levels, m_coarse=mc, nested=1, coarse_solver=solver,
+                     coarse_form=2 if kind == W.AC2D else 0, coarse_substeps=2 if kind == W.AC2D else 1, **kw)
+
+
+@pytest.mark.parametrize("case", NESTED, ids=nested_id)
+def test_nested_setup_matches_oracle(atm, orc, case):
+    kind, nx, ny, nt = case[:4]
+    p, u0 = small(kind, nx, ny, nt)
+    o = nested_opts(case, tol=0.0, max_iter=0)
+    g = W.initial_guess(p, u0)
+    ref = orc.ml_nested(p, o, g)
+    _, hist, _ = orc.ml_solve(p, o, g, allow_status=(orc.NOT_CONVERGED,))
+    ud = dev(g)
+    status, ghist, gst = atm.atm_solve(p, o, ud)
+    assert status == atm.ATM_NOT_CONVERGED and gst["iterations"] == 0 and gst["ms_setup"] > 0
+    assert_close(host(ud), ref, what="nested-iteration guess")
+    np.testing.assert_allclose(ghist[0], hist[0], rtol=1e-11)
+
+
+@pytest.mark.parametrize("case", NESTED, ids=nested_id)
+def test_nested_solve_matches_oracle(atm, orc, case):
+    kind, nx, ny, nt = case[:4]
+    p, u0 = small(kind, nx, ny, nt)
+    o = nested_opts(case, tol=1e-9, max_iter=60)
+    g = W.initial_guess(p, u0)
+    ref, hist, st = orc.ml_solve(p, o, g)
+    ud = dev(g)
+    status, ghist, gst = atm.atm_solve(p, o, ud)
+    assert status == atm.ATM_OK
+    assert gst["iterations"] == st["iterations"]
+    assert_close(host(ud), ref, what="converged nested solve")
