@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--no-configs", action="store_true", help="skip the c1 and c3 solves")
     ap.add_argument("--no-k-study", action="store_true", help="skip the 1D heat k-study leg")
     ap.add_argument("--no-three-level", action="store_true", help="skip the three-level V-cycle leg")
+    ap.add_argument("--no-nested", action="store_true", help="skip the nested-iteration leg")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline solves only (no context solves, no other legs): for profiling runs")
     ap.add_argument("--batch-count", type=int, default=256,
@@ -314,6 +315,44 @@ def three_level_leg(runs=2):
             "unit": "space-time point-updates/s", "three_level": rows, "two_level_m64": two}
 
 
+def nested_leg(runs=2):
+    """Nested iteration (section 2.2) against the plain zero guess: the headline 2D heat solve (two
+    levels) and the three-level workload with m_coarse 4; setup time, cycles and total time."""
+    import torch
+    import paper_2107_09596_amd as atm
+    import workloads as W
+    dev = torch.device("cuda:0")
+    out = {}
+    p2, o2, u02 = W.config("c2")
+    o2.coarse_solver, o2.coarse_cg_rtol = 1, 1e-3
+    p3, o3, u03 = W.three_level_config(4)
+    for name, p, o, u0 in (("c2_two_level", p2, o2, u02), ("three_level_m_coarse4", p3, o3, u03)):
+        guess = torch.from_numpy(W.initial_guess(p, u0)).to(dev)
+        u = torch.empty_like(guess)
+        row = {}
+        for nested in (0, 1):
+            oo = W.Options(**{**o.__dict__, "nested": nested})
+            ws = atm.workspace(atm.atm_workspace_bytes(p, oo), device=dev)
+            best = None
+            for _ in range(runs):
+                u.copy_(guess)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                status, hist, st = atm.atm_solve(p, oo, u, ws=ws, allow=(atm.ATM_OK,))
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3
+                if best is None or ms < best[0]:
+                    best = (ms, hist, st)
+            ms, hist, st = best
+            row["nested" if nested else "zero_guess"] = {
+                "cycles": st["iterations"], "ms": ms, "ms_setup": st["ms_setup"], "initial_residual": hist[0],
+                "final_residual": hist[-1], "value": p.n * p.nt / (ms / 1e3)}
+            print(f"# nested={nested} {name}: {st['iterations']} cycles, setup {st['ms_setup']:.1f} ms, "
+                  f"total {ms:.1f} ms, initial residual {hist[0]:.2e}", file=sys.stderr, flush=True)
+        out[name] = row
+    return out
+
+
 def batch_leg(count, sample):
     """Batched solves: the first `count` instances of the seeded batch (1D heat, 2D heat and 2D Allen-Cahn of
     uneven sizes; FP32-fine / FP64-residual for 2D), one captured cycle per graph replay.  The first run
@@ -517,6 +556,8 @@ def main():
         out["k_study"] = k_study_leg()
     if not args.no_three_level:
         out["three_level"] = three_level_leg()
+    if not args.no_nested:
+        out["nested_iteration"] = nested_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, u0, min(args.cpu_steps, p.nt))
         out["cpu_baseline"]["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
