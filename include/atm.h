@@ -114,7 +114,11 @@ typedef struct atm_options {
                               eigenbasis of the constant-coefficient operator where built (grids with
                               more than 128 points per side), CG elsewhere; 1 CG everywhere (to
                               coarse_cg_rtol).  Both take the same step: the eigenbasis solve is exact to
-                              rounding, CG to its tolerance */
+                              rounding, CG to its tolerance.  2: the eigenbasis solve on the BF16 matrix
+                              cores with split operands (each value hi + lo in BF16, products in FP32),
+                              accurate to about 1e-5 relative; the linear coarse form only (a FAS
+                              difference Psi(w) - Psi(v) would keep that error), nx and ny multiples of
+                              32 up to 128, not in the batch API */
     int32_t levels;        /* 0 or 2: two-level AT-MGRIT (Alg. 1).  3: the multilevel FAS V-cycle of
                               Alg. 2 (section 2.2) over three levels: level 1 takes every m-th point of
                               the fine grid and steps with dt m in coarse_substeps substeps (CG to

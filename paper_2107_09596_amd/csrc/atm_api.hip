@@ -49,7 +49,7 @@ constexpr double kLearnedGrowthLimit = 1e6;  // learned coarse solve: give up be
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t header, partials, ya, yb, e, tau, pk, d1, d2, large, spec, u1, y1a, y1b, tau2, e2, total;
+    size_t header, partials, ya, yb, e, tau, pk, d1, d2, large, spec, cres, u1, y1a, y1b, tau2, e2, total;
 };
 
 int64_t n_intervals(const atm_problem* p, const atm_options* o) { return p->nt / o->m; }
@@ -79,7 +79,7 @@ bool learned(const atm_options* o) { return o->coarse_form == 3; }
 // Psi's implicit solve by the eigenbasis of the constant-coefficient operator (2D kinds, coarse_solver 0)
 bool spectral(const atm_problem* p, const atm_options* o)
 {
-    return p->kind != ATM_HEAT1D && o->coarse_solver == 0 && !three_level(o);
+    return p->kind != ATM_HEAT1D && (o->coarse_solver == 0 || o->coarse_solver == 2) && !three_level(o);
 }
 
 Layout layout(const atm_problem* p, const atm_options* o)
@@ -111,7 +111,12 @@ Layout layout(const atm_problem* p, const atm_options* o)
     L.large = off;
     off += large_grid(p) ? align_up((NT + 1) * 5 * (size_t)n_space(p) * sizeof(double)) : 0;
     L.spec = off;
-    off += spectral(p, o) ? align_up(atm::spectral_table_doubles(p->nx, p->ny) * sizeof(double)) : 0;
+    off += spectral(p, o) ? align_up((atm::spectral_table_doubles(p->nx, p->ny) +
+                                      (o->coarse_solver == 2 ? atm::spectral_bf16_doubles(p->nx, p->ny) : 0)) *
+                                     sizeof(double))
+                          : 0;
+    L.cres = off;  // coarse_solver 2: the windows' C-point residuals
+    off += (spectral(p, o) && o->coarse_solver == 2) ? align_up(slab) : 0;
     // three levels: the level-1 iterate [N_T+1][n]; the level-1 sweeps' y (two), the level-2 FAS
     // right-hand side and corrections, [N_2+1][n] each
     const size_t slab2 = three_level(o) ? (size_t)(n_level2(p, o) + 1) * (size_t)n_space(p) * sizeof(double) : 0;
@@ -150,8 +155,14 @@ atm_status validate(const atm_problem* p, const atm_options* o)
     if (o->relax != 0 && o->relax != 1) return fail(ATM_ERR_INVALID_ARG, "relax must be 0 (F) or 1 (FCF)");
     if (o->coarse_substeps < 1) return fail(ATM_ERR_INVALID_ARG, "coarse_substeps must be >= 1");
     if (o->coarse_form < 0 || o->coarse_form > 3) return fail(ATM_ERR_INVALID_ARG, "coarse_form must be 0, 1, 2 or 3");
-    if (o->coarse_solver != 0 && o->coarse_solver != 1)
-        return fail(ATM_ERR_INVALID_ARG, "coarse_solver must be 0 (auto) or 1 (CG)");
+    if (o->coarse_solver < 0 || o->coarse_solver > 2)
+        return fail(ATM_ERR_INVALID_ARG, "coarse_solver must be 0 (auto), 1 (CG) or 2 (eigenbasis on BF16 matrix cores)");
+    if (o->coarse_solver == 2 && o->levels != 3) {
+        if (p->kind == ATM_HEAT1D || use_fas(p, o) || o->coarse_form == 3)
+            return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 is built for the linear coarse form of the 2D kinds");
+        if (large_grid(p) || p->nx % 32 != 0 || p->ny % 32 != 0)
+            return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 needs nx and ny multiples of 32, at most 128");
+    }
     if (o->coarse_form == 3) {
         if (p->kind != ATM_AC2D)
             return fail(ATM_ERR_UNSUPPORTED, "the learned coarse propagator is built for the periodic ATM_AC2D grid");
@@ -252,8 +263,9 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
     const double mrtol = o->mixed_cg_rtol > 0.0 ? o->mixed_cg_rtol : kMixedRtolDefault;
     a.rtol2_mixed = mrtol * mrtol;
     a.maxit = p->cg_max_iter;
-    a.spectral = spectral(p, o) ? 1 : 0;
+    a.spectral = spectral(p, o) ? (o->coarse_solver == 2 ? 2 : 1) : 0;
     a.spec = a.spectral ? (double*)(base + L.spec) : nullptr;
+    a.cres = a.spectral == 2 ? (double*)(base + L.cres) : nullptr;
     if (large_grid(p)) {
         a.large = 1;
         a.large_scratch = (double*)(base + L.large);
@@ -884,6 +896,7 @@ atm_status describe(int32_t n, const atm_problem* probs, const atm_options* opts
         if (large_grid(&in.p)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take grids up to 128 x 128", i);
         if (in.p.source) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take no PDE source", i);
         if (three_level(&in.o)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches run two levels", i);
+        if (in.o.coarse_solver == 2) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches solve Psi in FP64", i);
         in.cls = in.p.kind == ATM_HEAT1D ? CLS_1D : (in.p.kind == ATM_AC2D ? CLS_2DP : CLS_2D);
         if (in.cls == CLS_1D && in.p.nx > 512)
             return fail(ATM_ERR_UNSUPPORTED, "instance %d: 1D batch instances take nx <= 512", i);

@@ -111,6 +111,15 @@ __global__ __launch_bounds__(kBlock2D) void coarse2d_spec_kernel(KArgs a)
     coarse2d_body<S, EX, PER, kMaxSide2D + 2, true>(a, blockIdx.x, lp, red);
 }
 
+// Psi in the eigenbasis on the BF16 matrix cores (linear form)
+template <int S, bool EX, bool PER>
+__global__ __launch_bounds__(kBlock2D) void coarse2d_bf_kernel(KArgs a)
+{
+    __shared__ __align__(16) double lp[Lds2D<double>::size];
+    __shared__ double red[4 * kWaves2D];
+    coarse2d_body<S, EX, PER, kMaxSide2D + 2, false, true>(a, blockIdx.x, lp, red);
+}
+
 template <int S, bool EX, bool PER>
 __global__ __launch_bounds__(kBlock2D) void tau2d_spec_kernel(KArgs a)
 {
@@ -237,6 +246,25 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(const double* __restri
     }
 }
 
+// r_j = y_j - u_{jm} for j = 1..N_T, r_0 = 0 (the C-point residuals of the windows, coarse_solver 2)
+__global__ __launch_bounds__(256) void cpoint_residuals_kernel(KArgs a)
+{
+    const int64_t total = a.n * (a.NT + 1);
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < total; q += (int64_t)gridDim.x * 256) {
+        const int64_t j = q / a.n, x = q - j * a.n;
+        a.cres[q] = cpoint_residual(a, j, x);
+    }
+}
+
+void launch_cpoint_residuals(const KArgs& a, hipStream_t s)
+{
+    const int64_t total = a.n * (a.NT + 1);
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) return;
+    hipLaunchKernelGGL(cpoint_residuals_kernel, dim3(blocks), dim3(256), 0, s, a);
+}
+
 void launch_gather(const double* src, double* dst, int64_t n, int64_t stride_rows, int64_t rows, hipStream_t s)
 {
     const int64_t total = n * rows;
@@ -261,6 +289,10 @@ void launch_coarse(const KArgs& a, hipStream_t s)
 {
     if (a.is1d)
         hipLaunchKernelGGL(coarse1d_kernel, dim3(a.NT + 1), dim3(block1d(a)), 0, s, a);
+    else if (a.spectral == 2) {
+        launch_cpoint_residuals(a, s);
+        ATM_LAUNCH_2D(coarse2d_bf_kernel, a.NT + 1, s, a);
+    }
     else if (a.spectral)
         ATM_LAUNCH_2D(coarse2d_spec_kernel, a.NT + 1, s, a);
     else
@@ -323,9 +355,32 @@ __global__ __launch_bounds__(256) void spectral_tables_kernel(KArgs a)
 
 size_t spectral_table_doubles(int nx, int ny) { return 2 * (size_t)nx * nx + 2 * (size_t)ny * ny + nx + ny; }
 
+// the BF16 hi/lo planes of qyt, qxt, qy, qx (4 planes of n^2 BF16 per axis: n^2 doubles)
+size_t spectral_bf16_doubles(int nx, int ny) { return (size_t)nx * nx + (size_t)ny * ny; }
+
+__global__ __launch_bounds__(256) void spectral_bf16_kernel(KArgs a)
+{
+    const int64_t nx = a.g.nx, ny = a.g.ny;
+    const double* src[4] = {a.spec + 2 * nx * nx + ny * ny, a.spec + nx * nx, a.spec + 2 * nx * nx,
+                            a.spec};  // qyt, qxt, qy, qx
+    const int64_t sz[4] = {ny * ny, nx * nx, ny * ny, nx * nx};
+    __bf16* dst = reinterpret_cast<__bf16*>(a.spec + 2 * nx * nx + 2 * ny * ny + nx + ny);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int t = 0; t < 4; ++t) {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < sz[t]; i += stride) {
+            const double v = src[t][i];
+            const __bf16 h = (__bf16)v;
+            dst[i] = h;
+            dst[sz[t] + i] = (__bf16)(v - (double)h);
+        }
+        dst += 2 * sz[t];
+    }
+}
+
 void launch_spectral_tables(const KArgs& a, hipStream_t s)
 {
     hipLaunchKernelGGL(spectral_tables_kernel, dim3(64), dim3(256), 0, s, a);
+    if (a.spectral == 2) hipLaunchKernelGGL(spectral_bf16_kernel, dim3(64), dim3(256), 0, s, a);
 }
 
 }  // namespace atm

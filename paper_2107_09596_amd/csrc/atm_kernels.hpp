@@ -66,6 +66,9 @@ struct KArgs {
     // step, built on the device before the windows
     int spectral;
     double* spec;
+    // spectral 2: the C-point residuals r_j = y_j - u_{jm} (r_0 = 0), [N_T+1][n], formed once per
+    // coarse solve so that each window step reads one row
+    double* cres;
 };
 
 // ---------------------------------------------------------------------------
@@ -140,6 +143,7 @@ void launch_coarse(const KArgs& a, hipStream_t s);
 void launch_norm(const KArgs& a, hipStream_t s);
 void launch_sequential(const KArgs& a, hipStream_t s);
 void launch_gather(const double* src, double* dst, int64_t n, int64_t stride_rows, int64_t rows, hipStream_t s);
+void launch_cpoint_residuals(const KArgs& a, hipStream_t s);
 
 // mixed-precision form (atm_mixed.hip)
 constexpr int64_t kResidBlocks = 2048;  // most workgroups of the implicit-residual kernel
@@ -154,6 +158,7 @@ void launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t
 void launch_coarse_large(const KArgs& a, hipStream_t s);
 // doubles of the eigenbasis tables of an nx x ny grid (KArgs::spec), and their construction
 size_t spectral_table_doubles(int nx, int ny);
+size_t spectral_bf16_doubles(int nx, int ny);
 void launch_spectral_tables(const KArgs& a, hipStream_t s);
 void launch_sequential_large(const KArgs& a, hipStream_t s);
 void launch_step_residual_large(const KArgs& a, int64_t n_tasks, hipStream_t s);

@@ -60,4 +60,94 @@ __device__ __forceinline__ double basis(int n, bool periodic, int x, int k, doub
     return sqrt(2.0 / (double)n) * ((k & 1) ? cos(ang) : sin(ang));
 }
 
+// ---------------------------------------------------------------------------
+// The same solve on the BF16 matrix cores with split operands (coarse_solver 2; grids with nx, ny
+// multiples of 32 up to 128).  Every operand is a pair hi + lo of BF16 values (hi = bf16(v),
+// lo = bf16(v - hi)), and each product takes hi*hi + hi*lo + lo*hi in FP32 on
+// v_mfma_f32_16x16x32_bf16: about 16 significant bits per operand, so the step is accurate to about
+// 1e-5 relative, an approximation of the coarse propagator like an inexact CG (Psi only approximates
+// Phi^m).  The tables are the four FP64 tables above in the same layouts, as hi and lo planes.
+// ---------------------------------------------------------------------------
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kBfPitch = 136;                    // BF16 per LDS row: 16-byte fragments of 16 rows on distinct banks
+constexpr int kBfPlane = kMaxSide2D * kBfPitch;  // one matrix of up to 128 rows
+
+// BF16 planes after the FP64 tables: for t = qyt, qxt, qy, qx in turn, its hi plane then its lo plane
+__device__ __forceinline__ const __bf16* bf_table(const KArgs& a, int t, int lo)
+{
+    const int64_t nx = a.g.nx, ny = a.g.ny;
+    const __bf16* base = reinterpret_cast<const __bf16*>(a.spec + 2 * nx * nx + 2 * ny * ny + nx + ny);
+    const int64_t sz[4] = {ny * ny, nx * nx, ny * ny, nx * nx};
+    int64_t off = 0;
+    for (int q = 0; q < t; ++q) off += 2 * sz[q];
+    return base + off + (lo ? sz[t] : 0);
+}
+
+// out[col][row] = epi(row, col, sum_k in[row][k] T[col][k]) for row < M, col < N (M, N multiples of
+// 16, K of 32, N <= 128): `in` and `out` are LDS hi/lo planes with row pitch kBfPitch, T a global
+// table [N][ldt].  Wave w owns output columns 16w .. 16w+15
+// and walks the row blocks; no barrier inside.
+template <typename E>
+__device__ __forceinline__ void bf_mm(const __bf16* ih, const __bf16* il, const __bf16* __restrict__ th,
+                                      const __bf16* __restrict__ tl, int ldt, int M, int N, int K, __bf16* oh,
+                                      __bf16* ol, E&& epi)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    if (16 * wave >= N) return;  // uniform over the wave
+    const int col = 16 * wave + li;
+    const int nk = K >> 5;
+    // one accumulator per row block: the blocks' product chains are independent and interleave; the
+    // k-steps stay a loop so that only one step's fragments are live, the next step's table
+    // fragments being loaded while the current step's products run
+    const int mb = M >> 4;
+    f32x4_t acc[8];
+#pragma unroll
+    for (int ib = 0; ib < 8; ++ib) acc[ib] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    uint32_t to = (uint32_t)col * (uint32_t)ldt + (uint32_t)(8 * lk);
+    bf16x8_t bh = *reinterpret_cast<const bf16x8_t*>(th + to);
+    bf16x8_t bl = *reinterpret_cast<const bf16x8_t*>(tl + to);
+#pragma unroll 1
+    for (int kk = 0; kk < nk; ++kk) {
+        bf16x8_t nh = bh, nl = bl;
+        if (kk + 1 < nk) {
+            to += 32;
+            nh = *reinterpret_cast<const bf16x8_t*>(th + to);
+            nl = *reinterpret_cast<const bf16x8_t*>(tl + to);
+        }
+#pragma unroll
+        for (int ib = 0; ib < 8; ++ib)
+            if (ib < mb) {
+                const int o = (16 * ib + li) * kBfPitch + 32 * kk + 8 * lk;
+                const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(ih + o);
+                const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(il + o);
+                acc[ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[ib], 0, 0, 0);
+                acc[ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[ib], 0, 0, 0);
+                acc[ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[ib], 0, 0, 0);
+            }
+        bh = nh;
+        bl = nl;
+    }
+    // item r of the lane: row 16 ib + 4 lk + r, column col
+#pragma unroll
+    for (int ib = 0; ib < 8; ++ib)
+        if (ib < mb) {
+            bf16x4_t vh, vl;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float v = epi(16 * ib + 4 * lk + r, col, acc[ib][r]);
+                const __bf16 h = (__bf16)v;
+                vh[r] = h;
+                vl[r] = (__bf16)(v - (float)h);
+            }
+            const int o = col * kBfPitch + 16 * ib + 4 * lk;
+            *reinterpret_cast<bf16x4_t*>(oh + o) = vh;
+            *reinterpret_cast<bf16x4_t*>(ol + o) = vl;
+        }
+}
+
 }  // namespace atm

@@ -61,7 +61,7 @@ def test_num_intervals_and_workspace(abi):
 
 @pytest.mark.parametrize("field,value,status", [
     ("m", 1, -1), ("k", 0, -1), ("relax", 2, -1), ("coarse_substeps", 0, -1), ("max_iter", -1, -1),
-    ("precision", 3, -1), ("mixed_cg_rtol", -1.0, -1), ("mixed_cg_rtol", 1.0, -1), ("coarse_solver", 2, -1),
+    ("precision", 3, -1), ("mixed_cg_rtol", -1.0, -1), ("mixed_cg_rtol", 1.0, -1), ("coarse_solver", 3, -1),
     ("precision", 1, -2),  # the FP32 fine form is built for the 2D kinds only
 ])
 def test_invalid_options_rejected_before_launch(abi, field, value, status):
@@ -146,3 +146,19 @@ def test_source_accepted_for_1d_only(abi):
     assert abi.lib().atm_workspace_bytes(ctypes.byref(P2), ctypes.byref(O)) == 0
     st = abi.lib().atm_solve(ctypes.byref(P2), ctypes.byref(O), None, None, 0, None, 0, None, None)
     assert st == abi.ATM_ERR_UNSUPPORTED
+
+
+def test_bf16_psi_restrictions(abi):
+    """coarse_solver 2 is built for the linear form of the 2D kinds on grids with sides multiple of 32."""
+    ok = W.Problem(W.HEAT2D, nx=64, ny=96, nt=64)
+    for p, o, expect in [
+            (ok, W.Options(m=4, k=2, coarse_solver=2), True),
+            (W.Problem(W.HEAT2D, nx=48, ny=64, nt=64), W.Options(m=4, k=2, coarse_solver=2), False),
+            (ok, W.Options(m=4, k=2, coarse_solver=2, coarse_form=2), False),
+            (W.Problem(W.HEAT1D, nx=64, nt=64), W.Options(m=4, k=2, coarse_solver=2), False),
+            (W.Problem(W.AC2D, nx=64, ny=64, nt=64), W.Options(m=4, k=2, coarse_solver=2), False),
+            (ok, W.Options(m=4, k=2, coarse_solver=3), False)]:
+        n = abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(o)))
+        assert (n > 0) == expect, (p, o)
+    P, O = abi.problem(ok), abi.options(W.Options(m=4, k=2, coarse_solver=2))
+    assert abi.lib().atm_batch_workspace_bytes(1, ctypes.byref(P), ctypes.byref(O)) == 0

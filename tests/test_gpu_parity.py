@@ -208,11 +208,13 @@ def test_c1_k_extremes(atm, orc, k):
     assert_close(host(ud), ref, what=f"c1 k={k}")
 
 
-def test_c2_full_size_sampled(atm, orc):
-    """2D heat 128^2 x 4096, m = 32, FCF, CG rtol 1e-12, Psi's CG to 1e-3 (the benchmarked launch): converge on
-    the GPU, then check sampled intervals and every C-point residual with the oracle's integrator."""
+@pytest.mark.parametrize("solver", [1, 2], ids=["psi-cg-1e-3", "psi-bf16-eigenbasis"])
+def test_c2_full_size_sampled(atm, orc, solver):
+    """2D heat 128^2 x 4096, m = 32, FCF, CG rtol 1e-12, Psi by CG to 1e-3 or in the eigenbasis on the BF16
+    matrix cores (the benchmarked launches): converge on the GPU, then check sampled intervals and every
+    C-point residual with the oracle's integrator."""
     p, o, u0 = W.config("c2")
-    o.coarse_solver, o.coarse_cg_rtol = 1, 1e-3
+    o.coarse_solver, o.coarse_cg_rtol = solver, 1e-3
     ud = dev(W.initial_guess(p, u0))
     status, hist, st = atm.atm_solve(p, o, ud)
     assert status == atm.ATM_OK and hist[-1] <= o.tol
@@ -291,3 +293,45 @@ def test_c2_loose_coarse_tolerance_same_fixed_point(atm, orc):
     r2 = sum(float(np.sum((orc.step(p, p.dt, u[j * o.m - 1]) - u[j * o.m]) ** 2)) for j in range(1, NT + 1))
     assert np.sqrt(r2) <= o.tol
     assert np.max(np.abs(u - host(strict))) <= 1e-7
+
+
+# ---------------------------------------------------------------------------
+# Psi in the eigenbasis on the BF16 matrix cores (coarse_solver 2): split operands give about 2^-17
+# per product and per rounded stage; four stages with orthonormal bases and mu >= 1 keep one step
+# within 10 * 2^-17 < 1e-4 of the exact step, relative in the 2-norm
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nx,ny", [(32, 32), (64, 96), (128, 128)])
+def test_bf16_eigenbasis_psi_step(atm, orc, nx, ny):
+    p, u0 = W.small_problem(W.HEAT2D, seed=6, nt=40, nx=nx, ny=ny, cg_rtol=1e-14)
+    o = W.Options(m=4, k=2, relax=1, coarse_form=1, coarse_solver=2)
+    NT = p.nt // o.m
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((p.nt + 1, p.n))
+    u[0] = u0
+    y = rng.standard_normal((NT + 1, p.n))
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o))
+    ed = dev(np.zeros((NT + 1, p.n)))
+    atm.atm_coarse_solve(p, o, dev(u), dev(y), ed, ws)
+    got = host(ed)
+    rc = np.zeros((NT + 1, p.n))
+    for j in range(1, NT + 1):
+        rc[j] = y[j] - u[j * o.m]
+    ref = orc.local_solves(p, W.Options(m=4, k=2, coarse_form=1), rc, u[:: o.m][: NT + 1])
+    for pp in range(2, NT + 1):  # window p: e_p = Psi(r_{p-1}) + r_p
+        err = np.linalg.norm(got[pp] - ref[pp])
+        assert err <= 1e-4 * np.linalg.norm(rc[pp - 1]), f"window {pp}: {err:.3e}"
+
+
+def test_bf16_eigenbasis_psi_same_fixed_point(atm, orc):
+    """A solve with the BF16 Psi converges to the oracle's fixed point (the fine problem's solution)."""
+    p, u0 = W.small_problem(W.HEAT2D, seed=7, nt=64, nx=64, ny=64, cg_rtol=1e-14)
+    o = W.Options(m=4, k=3, relax=1, tol=1e-10, max_iter=60, coarse_solver=2)
+    g = W.initial_guess(p, u0)
+    ref, hist, st = orc.solve(p, W.Options(**{**o.__dict__, "coarse_solver": 1}), g)
+    ud = dev(g)
+    status, ghist, gst = atm.atm_solve(p, o, ud)
+    assert status == atm.ATM_OK and ghist[-1] <= o.tol
+    assert gst["iterations"] <= st["iterations"] + 1
+    # both iterates have residual <= tol; |u - u*| <= (nt + 1) |r| (|Phi| <= 1)
+    assert np.sqrt(np.sum((host(ud) - ref) ** 2)) <= 2 * (p.nt + 1) * o.tol
