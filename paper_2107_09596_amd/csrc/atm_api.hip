@@ -342,7 +342,9 @@ atm_status do_sweep(atm::KArgs a, const atm_problem* p, const atm_options* o, in
     return check_launch();
 }
 
-atm_status do_coarse(atm::KArgs a, double* u, double* y, double* e, hipStream_t s)
+// tables_ready: the eigenbasis tables of the grid are already in the workspace (a solve builds them
+// once before its cycles)
+atm_status do_coarse(atm::KArgs a, double* u, double* y, double* e, hipStream_t s, bool tables_ready = false)
 {
     a.cg_count = &a.hdr->cg_coarse;
     a.u = u;
@@ -352,7 +354,7 @@ atm_status do_coarse(atm::KArgs a, double* u, double* y, double* e, hipStream_t 
         atm::launch_coarse_large(a, s);
         return check_launch();
     }
-    if (a.spectral) atm::launch_spectral_tables(a, s);
+    if (a.spectral && !tables_ready) atm::launch_spectral_tables(a, s);
     if (a.fas) {
         atm::launch_tau(a, s);
         atm_status st = check_launch();
@@ -1351,6 +1353,11 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
         ATM_HIP(hipStreamSynchronize(s));
         S.ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup).count();
     }
+    // the eigenbasis tables depend on the grid only: built once for every coarse solve below
+    if (a.spectral && !a.large) {
+        atm::launch_spectral_tables(a, s);
+        if ((st = check_launch())) return st;
+    }
     // F-relax the initial guess, then its residual
     ATM_TIMED(kPhSweep, do_sweep(a, prob, opts, 0, u, nullptr, ya, s));
     if (st) return st;
@@ -1396,7 +1403,7 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
             ATM_TIMED(kPhCoarse, do_lower_levels(a, a1, opts, u, ycur, u1, a.tau, y1a, y1b, e2, s, &S.coarse_steps));
             if (st) break;
         } else {
-            ATM_TIMED(kPhCoarse, do_coarse(a, u, ycur, e, s));
+            ATM_TIMED(kPhCoarse, do_coarse(a, u, ycur, e, s, true));
             if (st) break;
             S.coarse_steps += window_psi_count(NT, opts->k) + (a.fas ? NT : 0);
         }
