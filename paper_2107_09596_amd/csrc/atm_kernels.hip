@@ -152,31 +152,43 @@ __global__ __launch_bounds__(kBlock2D) void seq2d_kernel(KArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// residual norm: deterministic two-stage sum of ||y_j - u_{jm}||^2, j = 1..N_T
+// residual norm: deterministic two-stage sum of ||y_j - u_{jm}||^2, j = 1..N_T; each C-point row is
+// cut into `chunks` pieces so that the first stage fills the chip (2048 workgroups at most, the size
+// of the partials array)
 // ---------------------------------------------------------------------------
 
 constexpr int kNormBlock = 256;
 
-__global__ __launch_bounds__(kNormBlock) void norm_partial_kernel(KArgs a)
+static int64_t norm_chunks(const KArgs& a)
+{
+    int64_t c = kResidBlocks / (a.NT > 0 ? a.NT : 1);
+    const int64_t by_size = (a.n + kNormBlock - 1) / kNormBlock;  // at least one element per thread
+    if (c > by_size) c = by_size;
+    if (c > 16) c = 16;
+    return c < 1 ? 1 : c;
+}
+
+__global__ __launch_bounds__(kNormBlock) void norm_partial_kernel(KArgs a, int64_t chunks)
 {
     __shared__ double red[2 * 2 * (kNormBlock / 64)];
     int slot = 0;
-    const int64_t j = blockIdx.x + 1;
+    const int64_t j = blockIdx.x / chunks + 1, q = blockIdx.x % chunks;
+    const int64_t lo = q * a.n / chunks, hi = (q + 1) * a.n / chunks;
     double acc = 0.0, unused = 0.0;
-    for (int64_t idx = threadIdx.x; idx < a.n; idx += kNormBlock) {
+    for (int64_t idx = lo + threadIdx.x; idx < hi; idx += kNormBlock) {
         const double r = a.y[j * a.n + idx] - a.u[(j * a.m) * a.n + idx];
         acc += r * r;
     }
     block_sum2(acc, unused, red, slot, kNormBlock / 64);
-    if (threadIdx.x == 0) a.partials[j] = acc;
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = acc;
 }
 
-__global__ __launch_bounds__(kNormBlock) void norm_final_kernel(KArgs a)
+__global__ __launch_bounds__(kNormBlock) void norm_final_kernel(KArgs a, int64_t count)
 {
     __shared__ double red[2 * 2 * (kNormBlock / 64)];
     int slot = 0;
     double acc = 0.0, unused = 0.0;
-    for (int64_t j = 1 + threadIdx.x; j <= a.NT; j += kNormBlock) acc += a.partials[j];
+    for (int64_t j = threadIdx.x; j < count; j += kNormBlock) acc += a.partials[j];
     block_sum2(acc, unused, red, slot, kNormBlock / 64);
     if (threadIdx.x == 0) a.hdr->norm2 = acc;
 }
@@ -301,8 +313,10 @@ void launch_coarse(const KArgs& a, hipStream_t s)
 
 void launch_norm(const KArgs& a, hipStream_t s)
 {
-    if (a.NT >= 1) hipLaunchKernelGGL(norm_partial_kernel, dim3(a.NT), dim3(kNormBlock), 0, s, a);
-    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kNormBlock), 0, s, a);
+    const int64_t chunks = norm_chunks(a);
+    const int64_t blocks = a.NT >= 1 ? a.NT * chunks : 0;
+    if (blocks > 0) hipLaunchKernelGGL(norm_partial_kernel, dim3(blocks), dim3(kNormBlock), 0, s, a, chunks);
+    hipLaunchKernelGGL(norm_final_kernel, dim3(1), dim3(kNormBlock), 0, s, a, blocks);
 }
 
 void launch_sequential(const KArgs& a, hipStream_t s)
