@@ -117,8 +117,8 @@ typedef struct atm_options {
                               rounding, CG to its tolerance.  2: the eigenbasis solve on the BF16 matrix
                               cores with split operands (each value hi + lo in BF16, products in FP32),
                               accurate to about 1e-5 relative; the linear coarse form only (a FAS
-                              difference Psi(w) - Psi(v) would keep that error), nx and ny multiples of
-                              32 up to 128, not in the batch API */
+                              difference Psi(w) - Psi(v) would keep that error), grids up to 128 per
+                              side */
     int32_t levels;        /* 0 or 2: two-level AT-MGRIT (Alg. 1).  3: the multilevel FAS V-cycle of
                               Alg. 2 (section 2.2) over three levels: level 1 takes every m-th point of
                               the fine grid and steps with dt m in coarse_substeps substeps (CG to

@@ -160,8 +160,7 @@ atm_status validate(const atm_problem* p, const atm_options* o)
     if (o->coarse_solver == 2 && o->levels != 3) {
         if (p->kind == ATM_HEAT1D || use_fas(p, o) || o->coarse_form == 3)
             return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 is built for the linear coarse form of the 2D kinds");
-        if (large_grid(p) || p->nx % 32 != 0 || p->ny % 32 != 0)
-            return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 needs nx and ny multiples of 32, at most 128");
+        if (large_grid(p)) return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 takes grids up to 128 x 128");
     }
     if (o->coarse_form == 3) {
         if (p->kind != ATM_AC2D)

@@ -261,19 +261,22 @@ __device__ __forceinline__ void spectral_step2d(const KArgs& a, const Strip& st,
 }
 
 // one Psi substep in the eigenbasis on the BF16 matrix cores with split operands (the four products
-// of spectral_step2d; LDS holds two hi/lo plane pairs, which ping-pong between the products, and
-// behind them the mode factors ex, ey as floats).  With `ay` non-null the step returns Psi(x) + ay at
-// the strip's points; those loads are issued before the products, into the strip registers (free
-// while the products run), so that their latency hides behind them.
-template <int S, bool EX>
+// of spectral_step2d, on dimensions padded to 16 and 32; LDS holds two hi/lo plane pairs of the
+// geometry BfGeom<R>, which ping-pong between the products, and behind them the mode factors).  With
+// `ay` non-null the step returns Psi(x) + ay at the strip's points; those loads are issued before the
+// products, into the strip registers (free while the products run), so that their latency hides
+// behind them.
+template <int S, bool EX, int R>
 __device__ __forceinline__ void bf_step2d(const KArgs& a, const Strip& st, double (&x)[S], double* lp,
                                           const double* ay)
 {
+    typedef BfGeom<R> G;
     __bf16* L = reinterpret_cast<__bf16*>(lp);
-    __bf16 *r0h = L, *r0l = L + kBfPlane, *r1h = L + 2 * kBfPlane, *r1l = L + 3 * kBfPlane;
-    const float* fex = reinterpret_cast<const float*>(L + 4 * kBfPlane);
-    const float* fey = fex + kMaxSide2D;
+    __bf16 *r0h = L, *r0l = L + G::plane, *r1h = L + 2 * G::plane, *r1l = L + 3 * G::plane;
+    const float* fex = reinterpret_cast<const float*>(L + 4 * G::plane);
+    const float* fey = fex + R;
     const int nx = a.g.nx, ny = a.g.ny;
+    const int mx = bf_r16(nx), my = bf_r16(ny), kx = bf_r32(nx), ky = bf_r32(ny);
     const float cx2 = (float)(2.0 * a.coarse.cx), cy2 = (float)(2.0 * a.coarse.cy);
     auto same = [](int, int, float v) { return v; };
     __syncthreads();  // earlier readers of the LDS block are done
@@ -283,7 +286,7 @@ __device__ __forceinline__ void bf_step2d(const KArgs& a, const Strip& st, doubl
         if (row_ok<EX, S>(st, s)) {
             const double b = explicit_part(a.coarse, x[s]);
             const __bf16 h = (__bf16)b;
-            const int o = st.tx * kBfPitch + st.y0 + s;
+            const int o = st.tx * G::P + st.y0 + s;
             r0h[o] = h;
             r0l[o] = (__bf16)(b - (double)h);
         }
@@ -294,31 +297,35 @@ __device__ __forceinline__ void bf_step2d(const KArgs& a, const Strip& st, doubl
             x[s] = row_ok<EX, S>(st, s) ? ay[off + (int64_t)s * nx] : 0.0;
     }
     __syncthreads();
-    bf_mm(r0h, r0l, bf_table(a, 0, 0), bf_table(a, 0, 1), ny, nx, ny, ny, r1h, r1l, same);  // (Qy^T b)^T
+    bf_mm<G::P>(r0h, r0l, bf_table(a, 0, 0), bf_table(a, 0, 1), ky, mx, my, ky, r1h, r1l, same);  // (Qy^T b)^T
     __syncthreads();
-    bf_mm(r1h, r1l, bf_table(a, 1, 0), bf_table(a, 1, 1), nx, ny, nx, nx, r0h, r0l,           // .. Qx ./ mu
-          [&](int i, int j, float v) { return v / (1.0f + (cx2 * fex[j] + cy2 * fey[i])); });
+    bf_mm<G::P>(r1h, r1l, bf_table(a, 1, 0), bf_table(a, 1, 1), kx, my, mx, kx, r0h, r0l,         // .. Qx ./ mu
+                [&](int i, int j, float v) { return v / (1.0f + (cx2 * fex[j] + cy2 * fey[i])); });
     __syncthreads();
-    bf_mm(r0h, r0l, bf_table(a, 2, 0), bf_table(a, 2, 1), ny, nx, ny, ny, r1h, r1l, same);  // (Qy ..)^T
+    bf_mm<G::P>(r0h, r0l, bf_table(a, 2, 0), bf_table(a, 2, 1), ky, mx, my, ky, r1h, r1l, same);  // (Qy ..)^T
     __syncthreads();
-    bf_mm(r1h, r1l, bf_table(a, 3, 0), bf_table(a, 3, 1), nx, ny, nx, nx, r0h, r0l, same);  // .. Qx^T
+    bf_mm<G::P>(r1h, r1l, bf_table(a, 3, 0), bf_table(a, 3, 1), kx, my, mx, kx, r0h, r0l, same);  // .. Qx^T
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const int o = st.tx * kBfPitch + st.y0 + s;
+        const int o = st.tx * G::P + st.y0 + s;
         const double v = (double)(float)r0h[o] + (double)(float)r0l[o];
         x[s] = row_ok<EX, S>(st, s) ? (ay ? v + x[s] : v) : 0.0;
     }
     __syncthreads();  // the LDS block is free again
 }
 
-// the mode factors of the BF16 eigenbasis step, staged as floats behind its LDS planes (once per task)
+// the mode factors of the BF16 eigenbasis step, staged as floats behind its LDS planes (once per
+// task; zero beyond the grid, so that the padding keeps mu = 1)
+template <int R>
 __device__ __forceinline__ void bf_stage_modes(const KArgs& a, double* lp)
 {
-    float* fex = reinterpret_cast<float*>(reinterpret_cast<__bf16*>(lp) + 4 * kBfPlane);
+    float* fex = reinterpret_cast<float*>(reinterpret_cast<__bf16*>(lp) + 4 * BfGeom<R>::plane);
     const SpecTables T = spec_tables(a);
-    for (int i = threadIdx.x; i < a.g.nx; i += blockDim.x) fex[i] = (float)T.ex[i];
-    for (int i = threadIdx.x; i < a.g.ny; i += blockDim.x) fex[kMaxSide2D + i] = (float)T.ey[i];
+    for (int i = threadIdx.x; i < R; i += blockDim.x) {
+        fex[i] = i < a.g.nx ? (float)T.ex[i] : 0.0f;
+        fex[R + i] = i < a.g.ny ? (float)T.ey[i] : 0.0f;
+    }
 }
 
 // Psi: s substeps, by CG, (SP) in the eigenbasis, or (BF) in the eigenbasis on the BF16 matrix
@@ -330,7 +337,7 @@ __device__ __forceinline__ long long psi2d(const KArgs& a, const Strip& st, Stri
     long long its = 0;
     for (int q = 0; q < a.substeps; ++q) {
         if constexpr (BF)
-            bf_step2d<S, EX>(a, st, v.x, lp, nullptr);
+            bf_step2d<S, EX, COLS - 2>(a, st, v.x, lp, nullptr);
         else if constexpr (SP)
             spectral_step2d<S, EX, COLS - 1>(a, st, v.x, lp);
         else
@@ -339,7 +346,9 @@ __device__ __forceinline__ long long psi2d(const KArgs& a, const Strip& st, Stri
     return its;
 }
 
-template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2, bool SP = false, bool BF = false>
+// BF: Psi in the eigenbasis on the BF16 matrix cores (linear form); BFC: with the residual rows a.cres
+// formed beforehand (the single-instance launch), else r = y - u read after each step (the batch)
+template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2, bool SP = false, bool BF = false, bool BFC = true>
 __device__ __forceinline__ void coarse2d_body(const KArgs& a, int64_t p, double* lp, double* red)
 {
     int slot = 0;
@@ -353,17 +362,26 @@ __device__ __forceinline__ void coarse2d_body(const KArgs& a, int64_t p, double*
         v.x[s] = 0.0;
         if (row_ok<EX, S>(st, s)) {
             const int64_t idx = (int64_t)(st.gbase + s * nx);
-            const double r = BF ? a.cres[s0 * a.n + idx] : cpoint_residual(a, s0, idx);
+            const double r = (BF && BFC) ? a.cres[s0 * a.n + idx] : cpoint_residual(a, s0, idx);
             v.x[s] = a.fas ? a.u[(s0 * a.m) * a.n + idx] + r : r;
         }
     }
     long long its = 0;
     if constexpr (BF) {
-        // linear form: e_jj = Psi(e_{jj-1}) + (y_jj - u_{jj m}), the last substep fused with the add
-        bf_stage_modes(a, lp);
+        // linear form: e_jj = Psi(e_{jj-1}) + r_jj; with the residual rows formed beforehand (BFC) the
+        // last substep loads r_jj during its products, otherwise r_jj = y_jj - u_{jj m} is read after
+        bf_stage_modes<COLS - 2>(a, lp);
         for (int64_t jj = s0 + 1; jj <= p; ++jj) {
-            for (int q = 0; q + 1 < a.substeps; ++q) bf_step2d<S, EX>(a, st, v.x, lp, nullptr);
-            bf_step2d<S, EX>(a, st, v.x, lp, a.cres + jj * a.n);
+            for (int q = 0; q + 1 < a.substeps; ++q) bf_step2d<S, EX, COLS - 2>(a, st, v.x, lp, nullptr);
+            if constexpr (BFC) {
+                bf_step2d<S, EX, COLS - 2>(a, st, v.x, lp, a.cres + jj * a.n);
+            } else {
+                bf_step2d<S, EX, COLS - 2>(a, st, v.x, lp, nullptr);
+                const int64_t off = opaque_off(st.gbase);
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    if (row_ok<EX, S>(st, s)) v.x[s] = v.x[s] + cpoint_residual(a, jj, off + (int64_t)s * nx);
+            }
         }
     } else {
         for (int64_t jj = s0 + 1; jj <= p; ++jj) {

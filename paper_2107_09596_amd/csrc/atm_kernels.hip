@@ -369,25 +369,33 @@ __global__ __launch_bounds__(256) void spectral_tables_kernel(KArgs a)
 
 size_t spectral_table_doubles(int nx, int ny) { return 2 * (size_t)nx * nx + 2 * (size_t)ny * ny + nx + ny; }
 
-// the BF16 hi/lo planes of qyt, qxt, qy, qx (4 planes of n^2 BF16 per axis: n^2 doubles)
-size_t spectral_bf16_doubles(int nx, int ny) { return (size_t)nx * nx + (size_t)ny * ny; }
+// the BF16 hi/lo planes of qyt, qxt, qy, qx ([r16(n)][r32(n)] each, zero padded), after the FP64
+// tables rounded up to an even number of doubles: in doubles, counted from the FP64 tables' start
+size_t spectral_bf16_doubles(int nx, int ny)
+{
+    const size_t sx = (size_t)bf_r16(nx) * bf_r32(nx), sy = (size_t)bf_r16(ny) * bf_r32(ny);
+    return (size_t)(bf_table_offset(nx, ny) - (int64_t)spectral_table_doubles(nx, ny)) + sx + sy;
+}
 
 __global__ __launch_bounds__(256) void spectral_bf16_kernel(KArgs a)
 {
-    const int64_t nx = a.g.nx, ny = a.g.ny;
-    const double* src[4] = {a.spec + 2 * nx * nx + ny * ny, a.spec + nx * nx, a.spec + 2 * nx * nx,
-                            a.spec};  // qyt, qxt, qy, qx
-    const int64_t sz[4] = {ny * ny, nx * nx, ny * ny, nx * nx};
-    __bf16* dst = reinterpret_cast<__bf16*>(a.spec + 2 * nx * nx + 2 * ny * ny + nx + ny);
+    const int nx = a.g.nx, ny = a.g.ny;
+    const double* src[4] = {a.spec + 2 * (int64_t)nx * nx + (int64_t)ny * ny, a.spec + (int64_t)nx * nx,
+                            a.spec + 2 * (int64_t)nx * nx, a.spec};  // qyt, qxt, qy, qx
+    __bf16* dst = reinterpret_cast<__bf16*>(a.spec + bf_table_offset(nx, ny));
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int t = 0; t < 4; ++t) {
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < sz[t]; i += stride) {
-            const double v = src[t][i];
+        const int n = (t & 1) ? nx : ny;
+        const int rows = bf_r16(n), cols = bf_r32(n);
+        const int64_t sz = (int64_t)rows * cols;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < sz; i += stride) {
+            const int r = (int)(i / cols), c = (int)(i % cols);
+            const double v = (r < n && c < n) ? src[t][(int64_t)r * n + c] : 0.0;
             const __bf16 h = (__bf16)v;
             dst[i] = h;
-            dst[sz[t] + i] = (__bf16)(v - (double)h);
+            dst[sz + i] = (__bf16)(v - (double)h);
         }
-        dst += 2 * sz[t];
+        dst += 2 * sz;
     }
 }
 

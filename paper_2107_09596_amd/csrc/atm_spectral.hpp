@@ -61,8 +61,10 @@ __device__ __forceinline__ double basis(int n, bool periodic, int x, int k, doub
 }
 
 // ---------------------------------------------------------------------------
-// The same solve on the BF16 matrix cores with split operands (coarse_solver 2; grids with nx, ny
-// multiples of 32 up to 128).  Every operand is a pair hi + lo of BF16 values (hi = bf16(v),
+// The same solve on the BF16 matrix cores with split operands (coarse_solver 2; grids up to 128 per
+// side, padded with zeros to multiples of 16 (rows, columns) and 32 (the products' inner dimension)).
+// Padding stays zero through the four products: the task clears its LDS first, the table planes are
+// zero beyond n, and the mode factors beyond n are zero (mu = 1).  Every operand is a pair hi + lo of BF16 values (hi = bf16(v),
 // lo = bf16(v - hi)), and each product takes hi*hi + hi*lo + lo*hi in FP32 on
 // v_mfma_f32_16x16x32_bf16: about 16 significant bits per operand, so the step is accurate to about
 // 1e-5 relative, an approximation of the coarse propagator like an inexact CG (Psi only approximates
@@ -73,25 +75,40 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kBfPitch = 136;                    // BF16 per LDS row: 16-byte fragments of 16 rows on distinct banks
-constexpr int kBfPlane = kMaxSide2D * kBfPitch;  // one matrix of up to 128 rows
+__host__ __device__ inline int bf_r16(int n) { return (n + 15) & ~15; }
+__host__ __device__ inline int bf_r32(int n) { return (n + 31) & ~31; }
 
-// BF16 planes after the FP64 tables: for t = qyt, qxt, qy, qx in turn, its hi plane then its lo plane
+// LDS geometry for grids of at most R points per side (R = 128, or 64 in the small-LDS variant): row
+// pitch R + 8 BF16, so that the 16-byte fragments of 16 consecutive rows fall on distinct banks; four
+// planes, then the mode factors ex, ey as R floats each
+template <int R>
+struct BfGeom {
+    static constexpr int P = R + 8;
+    static constexpr int plane = R * P;
+};
+
+// the BF16 planes start after the FP64 tables, at an even number of doubles (16-byte aligned)
+__host__ __device__ inline int64_t bf_table_offset(int nx, int ny)
+{
+    const int64_t d = 2 * (int64_t)nx * nx + 2 * (int64_t)ny * ny + nx + ny;
+    return (d + 1) & ~(int64_t)1;
+}
+
+// table t = qyt, qxt, qy, qx in turn (n = ny, nx, ny, nx): a [r16(n)][r32(n)] hi plane then lo plane
 __device__ __forceinline__ const __bf16* bf_table(const KArgs& a, int t, int lo)
 {
-    const int64_t nx = a.g.nx, ny = a.g.ny;
-    const __bf16* base = reinterpret_cast<const __bf16*>(a.spec + 2 * nx * nx + 2 * ny * ny + nx + ny);
-    const int64_t sz[4] = {ny * ny, nx * nx, ny * ny, nx * nx};
-    int64_t off = 0;
-    for (int q = 0; q < t; ++q) off += 2 * sz[q];
-    return base + off + (lo ? sz[t] : 0);
+    const int nx = a.g.nx, ny = a.g.ny;
+    const __bf16* base = reinterpret_cast<const __bf16*>(a.spec + bf_table_offset(nx, ny));
+    const int64_t sy = (int64_t)bf_r16(ny) * bf_r32(ny), sx = (int64_t)bf_r16(nx) * bf_r32(nx);
+    const int64_t sz = (t & 1) ? sx : sy;
+    const int64_t off = (t == 0) ? 0 : (t == 1) ? 2 * sy : (t == 2) ? 2 * sy + 2 * sx : 4 * sy + 2 * sx;
+    return base + off + (lo ? sz : 0);
 }
 
 // out[col][row] = epi(row, col, sum_k in[row][k] T[col][k]) for row < M, col < N (M, N multiples of
-// 16, K of 32, N <= 128): `in` and `out` are LDS hi/lo planes with row pitch kBfPitch, T a global
-// table [N][ldt].  Wave w owns output columns 16w .. 16w+15
-// and walks the row blocks; no barrier inside.
-template <typename E>
+// 16, K of 32, N <= 128): `in` and `out` are LDS hi/lo planes with row pitch P, T a global table
+// [N][ldt].  Wave w owns output columns 16w .. 16w+15 and walks the row blocks; no barrier inside.
+template <int P, typename E>
 __device__ __forceinline__ void bf_mm(const __bf16* ih, const __bf16* il, const __bf16* __restrict__ th,
                                       const __bf16* __restrict__ tl, int ldt, int M, int N, int K, __bf16* oh,
                                       __bf16* ol, E&& epi)
@@ -122,7 +139,7 @@ __device__ __forceinline__ void bf_mm(const __bf16* ih, const __bf16* il, const 
 #pragma unroll
         for (int ib = 0; ib < 8; ++ib)
             if (ib < mb) {
-                const int o = (16 * ib + li) * kBfPitch + 32 * kk + 8 * lk;
+                const int o = (16 * ib + li) * P + 32 * kk + 8 * lk;
                 const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(ih + o);
                 const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(il + o);
                 acc[ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[ib], 0, 0, 0);
@@ -144,7 +161,7 @@ __device__ __forceinline__ void bf_mm(const __bf16* ih, const __bf16* il, const 
                 vh[r] = h;
                 vl[r] = (__bf16)(v - (float)h);
             }
-            const int o = col * kBfPitch + 16 * ib + 4 * lk;
+            const int o = col * P + 16 * ib + 4 * lk;
             *reinterpret_cast<bf16x4_t*>(oh + o) = vh;
             *reinterpret_cast<bf16x4_t*>(ol + o) = vl;
         }

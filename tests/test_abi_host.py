@@ -149,16 +149,15 @@ def test_source_accepted_for_1d_only(abi):
 
 
 def test_bf16_psi_restrictions(abi):
-    """coarse_solver 2 is built for the linear form of the 2D kinds on grids with sides multiple of 32."""
+    """coarse_solver 2 is built for the linear form of the 2D kinds on grids up to 128 per side."""
     ok = W.Problem(W.HEAT2D, nx=64, ny=96, nt=64)
     for p, o, expect in [
             (ok, W.Options(m=4, k=2, coarse_solver=2), True),
-            (W.Problem(W.HEAT2D, nx=48, ny=64, nt=64), W.Options(m=4, k=2, coarse_solver=2), False),
+            (W.Problem(W.HEAT2D, nx=48, ny=37, nt=64), W.Options(m=4, k=2, coarse_solver=2), True),
+            (W.Problem(W.HEAT2D, nx=200, ny=64, nt=64), W.Options(m=4, k=2, coarse_solver=2), False),
             (ok, W.Options(m=4, k=2, coarse_solver=2, coarse_form=2), False),
             (W.Problem(W.HEAT1D, nx=64, nt=64), W.Options(m=4, k=2, coarse_solver=2), False),
             (W.Problem(W.AC2D, nx=64, ny=64, nt=64), W.Options(m=4, k=2, coarse_solver=2), False),
             (ok, W.Options(m=4, k=2, coarse_solver=3), False)]:
         n = abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(o)))
         assert (n > 0) == expect, (p, o)
-    P, O = abi.problem(ok), abi.options(W.Options(m=4, k=2, coarse_solver=2))
-    assert abi.lib().atm_batch_workspace_bytes(1, ctypes.byref(P), ctypes.byref(O)) == 0

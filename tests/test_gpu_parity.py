@@ -301,7 +301,8 @@ def test_c2_loose_coarse_tolerance_same_fixed_point(atm, orc):
 # within 10 * 2^-17 < 1e-4 of the exact step, relative in the 2-norm
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("nx,ny,sub", [(32, 32, 1), (64, 96, 1), (128, 128, 1), (64, 96, 2), (128, 32, 3)])
+@pytest.mark.parametrize("nx,ny,sub", [(32, 32, 1), (64, 96, 1), (128, 128, 1), (64, 96, 2), (128, 32, 3),
+                                       (12, 9, 1), (100, 37, 1), (33, 128, 2), (127, 65, 1)])
 def test_bf16_eigenbasis_psi_step(atm, orc, nx, ny, sub):
     """One window step e_p = Psi(r_{p-1}) + r_p (k = 2); with s substeps the errors of s steps add up
     (Psi does not amplify them)."""
