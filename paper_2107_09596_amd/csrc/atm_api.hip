@@ -812,7 +812,10 @@ Body phase_body(const Inst& in, int ph)
         case PH_S2:
         case PH_S1: return in.cls == CLS_1D ? kSweep1D : (in.mixed ? kSweep2D : kSweep2D64);
         case PH_TAU: return spectral(&in.p, &in.o) ? kTau2DSpec : kTau2D;
-        case PH_C: return in.cls == CLS_1D ? kCoarse1D : (spectral(&in.p, &in.o) ? kCoarse2DSpec : kCoarse2D);
+        case PH_C:
+            if (in.cls == CLS_1D) return kCoarse1D;
+            if (spectral(&in.p, &in.o)) return in.o.coarse_solver == 2 ? kCoarse2DBf : kCoarse2DSpec;
+            return kCoarse2D;
         case PH_N0:
         case PH_N: return in.mixed ? kNormI : kNormC;
         default: return in.mixed ? kNormFinalI : kNormFinalC;
@@ -897,7 +900,6 @@ atm_status describe(int32_t n, const atm_problem* probs, const atm_options* opts
         if (large_grid(&in.p)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take grids up to 128 x 128", i);
         if (in.p.source) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take no PDE source", i);
         if (three_level(&in.o)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches run two levels", i);
-        if (in.o.coarse_solver == 2) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches solve Psi in FP64", i);
         in.cls = in.p.kind == ATM_HEAT1D ? CLS_1D : (in.p.kind == ATM_AC2D ? CLS_2DP : CLS_2D);
         if (in.cls == CLS_1D && in.p.nx > 512)
             return fail(ATM_ERR_UNSUPPORTED, "instance %d: 1D batch instances take nx <= 512", i);

@@ -47,6 +47,7 @@ enum Body {
     kNormFinalI,
     kCoarse2DSpec,  // windows with Psi in the eigenbasis
     kTau2DSpec,
+    kCoarse2DBf,    // windows with Psi in the eigenbasis on the BF16 matrix cores (linear form)
 };
 
 // launch body over the task table with strip template S (2D), periodic flag and small flag (every

@@ -70,7 +70,7 @@ class Options:
     coarse_form: int = 0    # 0 auto (linear for heat, FAS for Allen-Cahn), 1 linear, 2 FAS, 3 learned
     precision: int = 0      # 0 FP64 throughout, 1 FP32 fine sweeps + FP64 residual/correction
     profile: int = 0        # 1: the GPU solve times every kernel launch with HIP events
-    coarse_solver: int = 0  # Psi's implicit solve: 0 auto (eigenbasis solve on large grids), 1 CG
+    coarse_solver: int = 0  # Psi's implicit solve: 0 auto (FP64 eigenbasis where built), 1 CG, 2 BF16 eigenbasis
     levels: int = 2         # 2: two-level AT-MGRIT (Alg. 1); 3: the FAS V-cycle of Alg. 2 over three levels
     m_coarse: int = 0       # levels 3: coarsening factor between level 1 and the coarsest level 2
     nested: int = 0         # 1: start from the nested-iteration guess built from the coarse levels
@@ -299,7 +299,8 @@ def batch_config(count: int = 256, seed: int = 4):
     t in [0, 1], FP64); 2D heat: n x n, n in U{32..128} (the 2D heat recipe, nu 0.1,
     t in [0, 1]); 2D Allen-Cahn: periodic n x n, eps 0.02, dt 1e-5, u0 ~ U[-0.05, 0.05],
     coarse substeps s = ceil(m dt / eps^2 / 0.4) so that each coarse step keeps
-    dT / (s eps^2) <= 0.4.  2D instances run the FP32-fine / FP64-residual form.
+    dT / (s eps^2) <= 0.4.  2D instances run the FP32-fine / FP64-residual form; the 2D heat
+    instances solve Psi in the eigenbasis on the BF16 matrix cores (linear coarse form).
     Instance b draws its initial field with seed 1000 + b.  FCF, tol 1e-8,
     k = max(2, ceil(0.1 (N_T + 1))).  Returns a list of (Problem, Options, u0).
     """
@@ -319,7 +320,7 @@ def batch_config(count: int = 256, seed: int = 4):
             n = int(rng.integers(32, 129))
             p = Problem(HEAT2D, nx=n, ny=n, length=1.0, nu=0.1, t0=0.0, tf=1.0, nt=nt, cg_rtol=1e-12)
             u0, _ = heat2d_u0(n, n, seed=1000 + b)
-            o = Options(m=m, k=k, relax=1, tol=1e-8, precision=1)
+            o = Options(m=m, k=k, relax=1, tol=1e-8, precision=1, coarse_solver=2)
         else:
             n = int(rng.integers(32, 129))
             dt, eps = 1e-5, 0.02
