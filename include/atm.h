@@ -116,9 +116,11 @@ typedef struct atm_options {
                               coarse_cg_rtol).  Both take the same step: the eigenbasis solve is exact to
                               rounding, CG to its tolerance.  2: the eigenbasis solve on the BF16 matrix
                               cores with split operands (each value hi + lo in BF16, products in FP32),
-                              accurate to about 1e-5 relative; the linear coarse form only (a FAS
-                              difference Psi(w) - Psi(v) would keep that error), grids up to 128 per
-                              side */
+                              accurate to about 1e-5 relative; grids up to 128 per side.  In the FAS
+                              form (coarse_substeps 1) the windows carry e = w - v:
+                              e_j = M^-1 (psi(v_{j-1} + e_{j-1}) - psi(v_{j-1})) + r_j, the explicit
+                              parts' difference in FP64, so that the solve's error scales with e (a
+                              plain Psi(w) - Psi(v) would keep it) */
     int32_t levels;        /* 0 or 2: two-level AT-MGRIT (Alg. 1).  3: the multilevel FAS V-cycle of
                               Alg. 2 (section 2.2) over three levels: level 1 takes every m-th point of
                               the fine grid and steps with dt m in coarse_substeps substeps (CG to

@@ -158,8 +158,10 @@ atm_status validate(const atm_problem* p, const atm_options* o)
     if (o->coarse_solver < 0 || o->coarse_solver > 2)
         return fail(ATM_ERR_INVALID_ARG, "coarse_solver must be 0 (auto), 1 (CG) or 2 (eigenbasis on BF16 matrix cores)");
     if (o->coarse_solver == 2 && o->levels != 3) {
-        if (p->kind == ATM_HEAT1D || use_fas(p, o) || o->coarse_form == 3)
-            return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 is built for the linear coarse form of the 2D kinds");
+        if (p->kind == ATM_HEAT1D || o->coarse_form == 3)
+            return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 is built for the plain coarse propagator of the 2D kinds");
+        if (use_fas(p, o) && o->coarse_substeps != 1)
+            return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 takes the FAS form with coarse_substeps 1");
         if (large_grid(p)) return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 takes grids up to 128 x 128");
     }
     if (o->coarse_form == 3) {
@@ -354,7 +356,7 @@ atm_status do_coarse(atm::KArgs a, double* u, double* y, double* e, hipStream_t 
         return check_launch();
     }
     if (a.spectral && !tables_ready) atm::launch_spectral_tables(a, s);
-    if (a.fas) {
+    if (a.fas && a.spectral != 2) {  // the BF16 windows take FAS in terms of e and need no tau
         atm::launch_tau(a, s);
         atm_status st = check_launch();
         if (st) return st;
@@ -712,7 +714,7 @@ atm_status nested_coarsest(atm::KArgs c, double* u, double* y, double* e, hipStr
     atm::launch_tau(q, s);
     atm_status st = check_launch();
     if (st) return st;
-    if (c.fas) {
+    if (c.fas && c.spectral != 2) {
         atm::launch_tau(c, s);
         if ((st = check_launch())) return st;
     }
@@ -791,7 +793,7 @@ size_t control_bytes(int n, size_t ntasks)
 int phase_tasks(const Inst& in, int ph)
 {
     const int64_t NT = n_intervals(&in.p, &in.o);
-    const bool fas = use_fas(&in.p, &in.o) && in.cls != CLS_1D;
+    const bool fas = use_fas(&in.p, &in.o) && in.cls != CLS_1D && in.o.coarse_solver != 2;
     switch (ph) {
         case PH_S0:
         case PH_S1: return (int)(NT + 1);
@@ -814,7 +816,8 @@ Body phase_body(const Inst& in, int ph)
         case PH_TAU: return spectral(&in.p, &in.o) ? kTau2DSpec : kTau2D;
         case PH_C:
             if (in.cls == CLS_1D) return kCoarse1D;
-            if (spectral(&in.p, &in.o)) return in.o.coarse_solver == 2 ? kCoarse2DBf : kCoarse2DSpec;
+            if (spectral(&in.p, &in.o))
+                return in.o.coarse_solver == 2 ? (use_fas(&in.p, &in.o) ? kCoarse2DBfFas : kCoarse2DBf) : kCoarse2DSpec;
             return kCoarse2D;
         case PH_N0:
         case PH_N: return in.mixed ? kNormI : kNormC;

@@ -101,7 +101,19 @@ __global__ __launch_bounds__(kBlock2D) void coarse2d_bf_batch(const KArgs* __res
     __shared__ __align__(16) double lds[COLS * Lds2D<double>::H];
     __shared__ double red[4 * kWaves2D];
     BATCH_TASK_PRELUDE
-    coarse2d_body<S, false, PER, COLS, false, true, false>(a, t.idx, lds, red);
+    coarse2d_body<S, false, PER, COLS, false, true, false, false>(a, t.idx, lds, red);
+}
+
+template <int S, bool PER, bool SMALL>
+__global__ __launch_bounds__(kBlock2D) void coarse2d_bf_fas_batch(const KArgs* __restrict__ args,
+                                                             const Task* __restrict__ tasks,
+                                                             const InstCtl* __restrict__ ctl)
+{
+    constexpr int COLS = SMALL ? kSmallCols : kMaxSide2D + 2;
+    __shared__ __align__(16) double lds[COLS * Lds2D<double>::H];
+    __shared__ double red[4 * kWaves2D];
+    BATCH_TASK_PRELUDE
+    coarse2d_body<S, false, PER, COLS, false, true, false, true>(a, t.idx, lds, red);
 }
 
 template <int S, bool PER, bool SMALL>
@@ -292,6 +304,7 @@ void launch_tasks(Body body, int S, bool per, bool small, const Launch& l, hipSt
         case kCoarse2DSpec: BATCH_SP(coarse2d_spec_batch, l, s); break;
         case kTau2DSpec: BATCH_SP(tau2d_spec_batch, l, s); break;
         case kCoarse2DBf: BATCH_SP(coarse2d_bf_batch, l, s); break;
+        case kCoarse2DBfFas: BATCH_SP(coarse2d_bf_fas_batch, l, s); break;
         case kNormC:
             hipLaunchKernelGGL(normc_batch, dim3(l.ntasks), dim3(kNormThreads), 0, s, l.args, l.tasks, l.ctl);
             break;

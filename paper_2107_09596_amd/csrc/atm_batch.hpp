@@ -48,6 +48,7 @@ enum Body {
     kCoarse2DSpec,  // windows with Psi in the eigenbasis
     kTau2DSpec,
     kCoarse2DBf,    // windows with Psi in the eigenbasis on the BF16 matrix cores (linear form)
+    kCoarse2DBfFas, // the same in the FAS form (in terms of e = w - v)
 };
 
 // launch body over the task table with strip template S (2D), periodic flag and small flag (every

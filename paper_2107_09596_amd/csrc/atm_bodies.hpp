@@ -265,8 +265,8 @@ __device__ __forceinline__ void spectral_step2d(const KArgs& a, const Strip& st,
 // geometry BfGeom<R>, which ping-pong between the products, and behind them the mode factors).  With
 // `ay` non-null the step returns Psi(x) + ay at the strip's points; those loads are issued before the
 // products, into the strip registers (free while the products run), so that their latency hides
-// behind them.
-template <int S, bool EX, int R>
+// behind them.  LIN: x already is the right-hand side (M^-1 x, no explicit part).
+template <int S, bool EX, int R, bool LIN = false>
 __device__ __forceinline__ void bf_step2d(const KArgs& a, const Strip& st, double (&x)[S], double* lp,
                                           const double* ay)
 {
@@ -284,7 +284,7 @@ __device__ __forceinline__ void bf_step2d(const KArgs& a, const Strip& st, doubl
 #pragma unroll
     for (int s = 0; s < S; ++s)
         if (row_ok<EX, S>(st, s)) {
-            const double b = explicit_part(a.coarse, x[s]);
+            const double b = LIN ? x[s] : explicit_part(a.coarse, x[s]);
             const __bf16 h = (__bf16)b;
             const int o = st.tx * G::P + st.y0 + s;
             r0h[o] = h;
@@ -346,9 +346,11 @@ __device__ __forceinline__ long long psi2d(const KArgs& a, const Strip& st, Stri
     return its;
 }
 
-// BF: Psi in the eigenbasis on the BF16 matrix cores (linear form); BFC: with the residual rows a.cres
-// formed beforehand (the single-instance launch), else r = y - u read after each step (the batch)
-template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2, bool SP = false, bool BF = false, bool BFC = true>
+// BF: Psi in the eigenbasis on the BF16 matrix cores; BFC: with the residual rows a.cres formed
+// beforehand (the single-instance launch), else r = y - u read after each step (the batch); BFF: the
+// FAS form in terms of e = w - v (else the linear form)
+template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2, bool SP = false, bool BF = false, bool BFC = true,
+          bool BFF = false>
 __device__ __forceinline__ void coarse2d_body(const KArgs& a, int64_t p, double* lp, double* red)
 {
     int slot = 0;
@@ -363,7 +365,7 @@ __device__ __forceinline__ void coarse2d_body(const KArgs& a, int64_t p, double*
         if (row_ok<EX, S>(st, s)) {
             const int64_t idx = (int64_t)(st.gbase + s * nx);
             const double r = (BF && BFC) ? a.cres[s0 * a.n + idx] : cpoint_residual(a, s0, idx);
-            v.x[s] = a.fas ? a.u[(s0 * a.m) * a.n + idx] + r : r;
+            v.x[s] = (a.fas && !BF) ? a.u[(s0 * a.m) * a.n + idx] + r : r;  // BF carries e = w - v
         }
     }
     long long its = 0;
@@ -373,7 +375,29 @@ __device__ __forceinline__ void coarse2d_body(const KArgs& a, int64_t p, double*
         bf_stage_modes<COLS - 2>(a, lp);
         for (int64_t jj = s0 + 1; jj <= p; ++jj) {
             for (int q = 0; q + 1 < a.substeps; ++q) bf_step2d<S, EX, COLS - 2>(a, st, v.x, lp, nullptr);
-            if constexpr (BFC) {
+            if constexpr (BFF) {
+                // FAS in terms of e = w - v (one substep): e_jj = M^-1 (psi(v + e) - psi(v)) + r_jj with
+                // v = u_{(jj-1) m}; the explicit parts' difference e + react (e - e (3 v^2 + 3 v e + e^2))
+                // is formed in FP64, so the solve's error scales with e and vanishes with it
+                const double react = a.coarse.react;
+                const int64_t off = opaque_off(st.gbase);
+                const double* vrow = a.u + ((jj - 1) * a.m) * a.n;
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    if (row_ok<EX, S>(st, s)) {
+                        const double vv = vrow[off + (int64_t)s * nx], ee = v.x[s];
+                        v.x[s] = ee + react * (ee - ee * (3.0 * vv * vv + 3.0 * vv * ee + ee * ee));
+                    }
+                if constexpr (BFC) {
+                    bf_step2d<S, EX, COLS - 2, true>(a, st, v.x, lp, a.cres + jj * a.n);
+                } else {
+                    bf_step2d<S, EX, COLS - 2, true>(a, st, v.x, lp, nullptr);
+                    const int64_t o2 = opaque_off(st.gbase);
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        if (row_ok<EX, S>(st, s)) v.x[s] = v.x[s] + cpoint_residual(a, jj, o2 + (int64_t)s * nx);
+                }
+            } else if constexpr (BFC) {
                 bf_step2d<S, EX, COLS - 2>(a, st, v.x, lp, a.cres + jj * a.n);
             } else {
                 bf_step2d<S, EX, COLS - 2>(a, st, v.x, lp, nullptr);
@@ -399,7 +423,7 @@ __device__ __forceinline__ void coarse2d_body(const KArgs& a, int64_t p, double*
     for (int s = 0; s < S; ++s)
         if (row_ok<EX, S>(st, s)) {
             const int64_t idx = (int64_t)(st.gbase + s * nx);
-            a.e[p * a.n + idx] = a.fas ? v.x[s] - a.u[(p * a.m) * a.n + idx] : v.x[s];
+            a.e[p * a.n + idx] = (a.fas && !BF) ? v.x[s] - a.u[(p * a.m) * a.n + idx] : v.x[s];
         }
     count_cg(a, its);
 }

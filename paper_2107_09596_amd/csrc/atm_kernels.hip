@@ -111,13 +111,21 @@ __global__ __launch_bounds__(kBlock2D) void coarse2d_spec_kernel(KArgs a)
     coarse2d_body<S, EX, PER, kMaxSide2D + 2, true>(a, blockIdx.x, lp, red);
 }
 
-// Psi in the eigenbasis on the BF16 matrix cores (linear form)
+// Psi in the eigenbasis on the BF16 matrix cores: linear form, and FAS in terms of e = w - v
 template <int S, bool EX, bool PER>
 __global__ __launch_bounds__(kBlock2D) void coarse2d_bf_kernel(KArgs a)
 {
     __shared__ __align__(16) double lp[Lds2D<double>::size];
     __shared__ double red[4 * kWaves2D];
-    coarse2d_body<S, EX, PER, kMaxSide2D + 2, false, true>(a, blockIdx.x, lp, red);
+    coarse2d_body<S, EX, PER, kMaxSide2D + 2, false, true, true, false>(a, blockIdx.x, lp, red);
+}
+
+template <int S, bool EX, bool PER>
+__global__ __launch_bounds__(kBlock2D) void coarse2d_bf_fas_kernel(KArgs a)
+{
+    __shared__ __align__(16) double lp[Lds2D<double>::size];
+    __shared__ double red[4 * kWaves2D];
+    coarse2d_body<S, EX, PER, kMaxSide2D + 2, false, true, true, true>(a, blockIdx.x, lp, red);
 }
 
 template <int S, bool EX, bool PER>
@@ -303,7 +311,10 @@ void launch_coarse(const KArgs& a, hipStream_t s)
         hipLaunchKernelGGL(coarse1d_kernel, dim3(a.NT + 1), dim3(block1d(a)), 0, s, a);
     else if (a.spectral == 2) {
         launch_cpoint_residuals(a, s);
-        ATM_LAUNCH_2D(coarse2d_bf_kernel, a.NT + 1, s, a);
+        if (a.fas)
+            ATM_LAUNCH_2D(coarse2d_bf_fas_kernel, a.NT + 1, s, a);
+        else
+            ATM_LAUNCH_2D(coarse2d_bf_kernel, a.NT + 1, s, a);
     }
     else if (a.spectral)
         ATM_LAUNCH_2D(coarse2d_spec_kernel, a.NT + 1, s, a);

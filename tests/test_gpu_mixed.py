@@ -221,12 +221,15 @@ def test_c2_mixed_full_size(atm, orc):
     assert err <= 1e-9, f"max error against the FP64 oracle on the first 256 steps: {err:.2e}"
 
 
-def test_c5_full_size(atm, orc):
+@pytest.mark.parametrize("solver", [0, 2], ids=["psi-fp64-eigenbasis", "psi-bf16-eigenbasis-fas-in-e"])
+def test_c5_full_size(atm, orc, solver):
     """2D Allen-Cahn 128x128 periodic, eps 0.03, dt 1e-5, Nt 4096, m 32, k 13, FCF, FP32 fine solves, Psi in the
-    eigenbasis (the benchmarked plain solve of the learned-propagator comparison): converge to 1e-8; the stopping
-    norm is the oracle's implicit residual of the result, the paper-form residual is bracketed by it, and the
-    first 64 steps match the oracle's sequential stepping."""
+    FP64 eigenbasis (the benchmarked plain solve of the learned-propagator comparison) or on the BF16 matrix cores
+    (FAS in terms of e = w - v): converge to 1e-8; the stopping norm is the oracle's implicit residual of the
+    result, the paper-form residual is bracketed by it, and the first 64 steps match the oracle's sequential
+    stepping."""
     p, o, u0 = W.config("c5")
+    o.coarse_solver = solver
     ud = dev(W.initial_guess(p, u0))
     status, hist, st = atm.atm_solve(p, o, ud)
     print(f"cycles {st['iterations']}, residual {hist[-1]:.3e}, final {st['final_residual']:.3e}")

@@ -338,3 +338,43 @@ def test_bf16_eigenbasis_psi_same_fixed_point(atm, orc):
     assert gst["iterations"] <= st["iterations"] + 1
     # both iterates have residual <= tol; |u - u*| <= (nt + 1) |r| (|Phi| <= 1)
     assert np.sqrt(np.sum((host(ud) - ref) ** 2)) <= 2 * (p.nt + 1) * o.tol
+
+
+def test_bf16_eigenbasis_psi_fas_step(atm, orc):
+    """FAS windows on the BF16 matrix cores carry e = w - v: with k = 2, window p returns
+    e_p = Psi(v_{p-1} + r_{p-1}) - Psi(v_{p-1}) + r_p = M^-1 d + r_p, d = psi(v + r) - psi(v) the explicit
+    parts' difference, whose solve is within 1e-4 |d| (as for the linear form)."""
+    p, u0 = W.small_problem(W.AC2D, seed=6, nt=40, nx=64, ny=48, cg_rtol=1e-14, eps=0.1)
+    o = W.Options(m=4, k=2, relax=1, coarse_form=2, coarse_solver=2)
+    NT = p.nt // o.m
+    rng = np.random.default_rng(5)
+    u = 0.5 * rng.standard_normal((p.nt + 1, p.n))
+    u[0] = u0
+    y = u[:: o.m][: NT + 1] + 0.1 * rng.standard_normal((NT + 1, p.n))
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o))
+    ed = dev(np.zeros((NT + 1, p.n)))
+    atm.atm_coarse_solve(p, o, dev(u), dev(y), ed, ws)
+    got = host(ed)
+    vc = u[:: o.m][: NT + 1]
+    rc = np.zeros((NT + 1, p.n))
+    for j in range(1, NT + 1):
+        rc[j] = y[j] - vc[j]
+    ref = orc.local_solves(p, W.Options(m=4, k=2, coarse_form=2), rc, vc)
+    react = p.dt * o.m / p.eps ** 2
+    for pp in range(2, NT + 1):
+        v, r = vc[pp - 1], rc[pp - 1]
+        d = (r + react * ((v + r) - (v + r) ** 3)) - react * (v - v ** 3)
+        err = np.linalg.norm(got[pp] - ref[pp])
+        assert err <= 1e-4 * np.linalg.norm(d), f"window {pp}: {err:.3e} > 1e-4 * {np.linalg.norm(d):.3e}"
+
+
+def test_bf16_eigenbasis_psi_fas_same_fixed_point(atm, orc):
+    p, u0 = W.small_problem(W.AC2D, seed=7, nt=64, nx=32, ny=32, cg_rtol=1e-14)
+    o = W.Options(m=4, k=3, relax=1, tol=1e-10, max_iter=60, coarse_form=2, coarse_solver=2)
+    g = W.initial_guess(p, u0)
+    ref, hist, st = orc.solve(p, W.Options(**{**o.__dict__, "coarse_solver": 1}), g)
+    ud = dev(g)
+    status, ghist, gst = atm.atm_solve(p, o, ud)
+    assert status == atm.ATM_OK and ghist[-1] <= o.tol
+    assert gst["iterations"] <= st["iterations"] + 1
+    assert np.sqrt(np.sum((host(ud) - ref) ** 2)) <= 2 * (p.nt + 1) * o.tol

@@ -300,7 +300,8 @@ def batch_config(count: int = 256, seed: int = 4):
     t in [0, 1]); 2D Allen-Cahn: periodic n x n, eps 0.02, dt 1e-5, u0 ~ U[-0.05, 0.05],
     coarse substeps s = ceil(m dt / eps^2 / 0.4) so that each coarse step keeps
     dT / (s eps^2) <= 0.4.  2D instances run the FP32-fine / FP64-residual form; the 2D heat
-    instances solve Psi in the eigenbasis on the BF16 matrix cores (linear coarse form).
+    instances, and the Allen-Cahn instances with one coarse substep (FAS in terms of e = w - v), solve
+    Psi in the eigenbasis on the BF16 matrix cores.
     Instance b draws its initial field with seed 1000 + b.  FCF, tol 1e-8,
     k = max(2, ceil(0.1 (N_T + 1))).  Returns a list of (Problem, Options, u0).
     """
@@ -327,6 +328,6 @@ def batch_config(count: int = 256, seed: int = 4):
             p = Problem(AC2D, nx=n, ny=n, length=1.0, nu=1.0, eps=eps, t0=0.0, tf=nt * dt, nt=nt, cg_rtol=1e-12)
             u0 = ac2d_u0(n, n, seed=1000 + b)
             s = max(1, math.ceil(m * dt / eps ** 2 / 0.4))
-            o = Options(m=m, k=k, relax=1, tol=1e-8, precision=1, coarse_substeps=s)
+            o = Options(m=m, k=k, relax=1, tol=1e-8, precision=1, coarse_substeps=s, coarse_solver=2 if s == 1 else 0)
         out.append((p, o, u0))
     return out
