@@ -423,7 +423,8 @@ def batch_leg(count, sample):
         "one_at_a_time": {"sample": len(idx), "every": step, "ms_sample": one_ms, "ms_extrapolated": one_ms_all,
                           "speedup_of_batch": one_ms_all / wall},
         "workload": "seeded batch of %d: 1D heat nx 63..511 (FP64), 2D heat and periodic 2D Allen-Cahn n x n, "
-                    "n 32..128 (FP32 fine / FP64 residual; 2D heat Psi on BF16 matrix cores), Nt 512..8192, "
+                    "n 32..128 (FP32 fine / FP64 residual; Psi on BF16 matrix cores for 2D heat and one-substep "
+                    "Allen-Cahn), Nt 512..8192, "
                     "m in {8,16,32}, k = max(2, ceil(0.1 (N_T+1))), "
                     "FCF, tol 1e-8" % count,
     }
