@@ -258,6 +258,8 @@ def k_study_leg(runs=2):
             err = float((u - exact).abs().max())
             rows.append({"k": k, "k_over_C": k / (p.nt // m + 1), "cycles": st["iterations"], "ms": best,
                          "value": p.n * p.nt / (best / 1e3), "final_residual": hist[-1], "err_exact": err})
+            if m == 128:  # the residual histories of the paper's convergence figure (m = 128)
+                rows[-1]["history"] = list(hist)
             print(f"# k-study m={m} k={k}: {st['iterations']} cycles, {best:.1f} ms", file=sys.stderr, flush=True)
         par = rows[-1]["cycles"]
         sat = min(r["k"] for r in rows if r["cycles"] <= par)

@@ -9,12 +9,16 @@ substitution with the inverse assembled from the operator, and the statements
 the paper makes about its k-study (its Figs. of iterations against k and
 k / #C-points, and of residual histories and errors).
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
 
 import workloads as W
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "kstudy.json")))
 
 
 def lap1d(n, h):
@@ -122,13 +126,29 @@ def kstudy(orc):
     orc.set_threads(1)
 
 
+def test_k_study_grid_reading():
+    # the grid of the study as read (1025 points with both ends, 16384 time points on [0, pi]) makes
+    # k = 128 at m = 128 exactly Parareal: every window reaches back to C-point 0 and the deepest takes
+    # 127 coarse steps
+    g = GOLDEN["problem"]
+    p, _, _, _ = W.heat1d_forced()
+    assert p.nx + 2 == g["dof"] and p.nt + 1 == g["time_points"] and p.length == g["length"]
+    assert abs(p.tf - math.pi * g["tf_over_pi"]) < 1e-15
+    par = GOLDEN["parareal_equivalence"]
+    NT = p.nt // par["m"]
+    assert NT + 1 == par["k"]                     # k covers every C-point
+    assert max(min(q, par["k"] - 1) for q in range(NT + 1)) == par["sequential_coarse_steps"]
+    assert all(max(0, q - par["k"] + 1) == 0 for q in range(NT + 1))
+
+
 @pytest.mark.slow
 def test_k_study_k12_matches_parareal(kstudy):
     # m = 128: 128 C-points; k = 128 is Parareal (127 sequential coarse steps), and k = 12 needs
     # the same number of iterations
     run, _ = kstudy
-    assert run(128, 12)["its"] == run(128, 128)["its"]
-    assert run(128, 6)["its"] > run(128, 12)["its"]
+    g = GOLDEN["equal_convergence"]
+    assert run(g["m"], g["k_small"])["its"] == run(g["m"], g["k_parareal"])["its"]
+    assert run(g["m"], g["k_small"] // 2)["its"] > run(g["m"], g["k_small"])["its"]
 
 
 @pytest.mark.slow
@@ -136,8 +156,11 @@ def test_k_study_saturation_ratio(kstudy):
     # convergence stops improving at about the same k / #C-points (about 0.08) for each m:
     # m = 64 has 256 C-points, so k = 20 (0.078) already converges like Parareal, k = 12 (0.047) not
     run, _ = kstudy
+    ratio = GOLDEN["saturation_ratio"]["about"]
     par = run(64, 256)["its"]
-    assert run(64, 20)["its"] == par
+    k_sat = 20                                    # the first k of the study at or above ratio * 256
+    assert abs(k_sat / 256 - ratio) < 0.01
+    assert run(64, k_sat)["its"] == par
     assert run(64, 12)["its"] > par
 
 
