@@ -306,18 +306,25 @@ def three_level_leg(runs=2):
         n2 = (p.nt // o.m) // mc
         at = timed(p, o, guess, u)
         mg = timed(p, W.Options(**{**o.__dict__, "k": n2 + 1}), guess, u)
+        # the same with the coarsest windows on the BF16 matrix cores (level 1 by CG)
+        atb = timed(p, W.Options(**{**o.__dict__, "coarse_solver": 2}), guess, u)
+        mgb = timed(p, W.Options(**{**o.__dict__, "k": n2 + 1, "coarse_solver": 2}), guess, u)
         rows.append({"m_coarse": mc, "coarsest_points": n2 + 1, "at_mgrit": at, "mgrit": mg,
-                     "speedup_vs_mgrit": mg["ms"] / at["ms"]})
+                     "speedup_vs_mgrit": mg["ms"] / at["ms"], "at_mgrit_bf16_coarsest": atb,
+                     "mgrit_bf16_coarsest": mgb, "speedup_vs_mgrit_bf16_coarsest": mgb["ms"] / atb["ms"]})
         print(f"# three levels m_coarse={mc}: AT-MGRIT k={o.k} {at['cycles']} cycles {at['ms']:.1f} ms, "
-              f"MGRIT {mg['cycles']} cycles {mg['ms']:.1f} ms", file=sys.stderr, flush=True)
+              f"MGRIT {mg['cycles']} cycles {mg['ms']:.1f} ms; coarsest on BF16: AT-MGRIT {atb['cycles']} cycles "
+              f"{atb['ms']:.1f} ms, MGRIT {mgb['cycles']} cycles {mgb['ms']:.1f} ms", file=sys.stderr, flush=True)
     p, o, u0 = W.three_level_config(4)
     guess = torch.from_numpy(W.initial_guess(p, u0)).to(dev)
     u = torch.empty_like(guess)
     two = {}
     for k in (W.default_k(p.nt // o.m), (p.nt // o.m) // 2):
         two[str(k)] = timed(p, W.Options(**{**o.__dict__, "levels": 2, "k": k, "coarse_solver": 1}), guess, u)
-        print(f"# two levels m=64 k={k}: {two[str(k)]['cycles']} cycles {two[str(k)]['ms']:.1f} ms", file=sys.stderr,
-              flush=True)
+        two[str(k) + "_bf16"] = timed(p, W.Options(**{**o.__dict__, "levels": 2, "k": k, "coarse_solver": 2}), guess, u)
+        print(f"# two levels m=64 k={k}: {two[str(k)]['cycles']} cycles {two[str(k)]['ms']:.1f} ms (Psi by CG), "
+              f"{two[str(k) + '_bf16']['cycles']} cycles {two[str(k) + '_bf16']['ms']:.1f} ms (Psi on BF16)",
+              file=sys.stderr, flush=True)
     return {"workload": "2D heat 128x128 interior, nu=0.1, dt=1/4096, Nt=16384, m=64, FCF, tol 1e-8, FP64, "
                         "Psi by CG to 1e-12",
             "unit": "space-time point-updates/s", "three_level": rows, "two_level_m64": two}

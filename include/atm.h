@@ -129,8 +129,10 @@ typedef struct atm_options {
                               points.  F(CF)^nu relaxation on levels 0 and 1, injection of the iterate
                               and its residual, the FAS right-hand side A_1(v) + g on level 1, ideal
                               interpolation back.  Precision 0, grids up to 128 per side, not with the
-                              learned propagator or the batch API; coarse_form and coarse_solver do
-                              not apply (the cycle is the FAS form, Psi by CG) */
+                              learned propagator or the batch API; coarse_form does not apply (the
+                              cycle is the FAS form).  Level 1 steps by CG; the coarsest level's
+                              windows take Psi by CG, or with coarse_solver 2 (coarse_substeps 1) on the
+                              BF16 matrix cores in terms of e = w - v */
     int32_t m_coarse;      /* levels 3: coarsening factor from level 1 to level 2, >= 2, with
                               floor(nt / m) >= m_coarse */
     int32_t nested;        /* 1: nested iteration (section 2.2) replaces the initial guess before the

@@ -77,6 +77,13 @@ bool use_fas(const atm_problem* p, const atm_options* o)
 bool learned(const atm_options* o) { return o->coarse_form == 3; }
 
 // Psi's implicit solve by the eigenbasis of the constant-coefficient operator (2D kinds, coarse_solver 0)
+// three levels with coarse_solver 2: the coarsest level's windows on the BF16 matrix cores (level 1
+// keeps CG, so that its FAS right-hand side and relaxation share Phi_1 exactly)
+bool ml_bf(const atm_problem* p, const atm_options* o)
+{
+    return o->levels == 3 && o->coarse_solver == 2 && p->kind != ATM_HEAT1D;
+}
+
 bool spectral(const atm_problem* p, const atm_options* o)
 {
     return p->kind != ATM_HEAT1D && (o->coarse_solver == 0 || o->coarse_solver == 2) && !three_level(o);
@@ -110,16 +117,17 @@ Layout layout(const atm_problem* p, const atm_options* o)
     off += align_up((NT + 1) * act);
     L.large = off;
     off += large_grid(p) ? align_up((NT + 1) * 5 * (size_t)n_space(p) * sizeof(double)) : 0;
+    const size_t slab2 = three_level(o) ? (size_t)(n_level2(p, o) + 1) * (size_t)n_space(p) * sizeof(double) : 0;
     L.spec = off;
-    off += spectral(p, o) ? align_up((atm::spectral_table_doubles(p->nx, p->ny) +
-                                      (o->coarse_solver == 2 ? atm::spectral_bf16_doubles(p->nx, p->ny) : 0)) *
-                                     sizeof(double))
-                          : 0;
-    L.cres = off;  // coarse_solver 2: the windows' C-point residuals
-    off += (spectral(p, o) && o->coarse_solver == 2) ? align_up(slab) : 0;
+    off += (spectral(p, o) || ml_bf(p, o))
+               ? align_up((atm::spectral_table_doubles(p->nx, p->ny) +
+                           (o->coarse_solver == 2 ? atm::spectral_bf16_doubles(p->nx, p->ny) : 0)) *
+                          sizeof(double))
+               : 0;
+    L.cres = off;  // coarse_solver 2: the windows' C-point residuals (three levels: the coarsest level's)
+    off += ml_bf(p, o) ? align_up(slab2) : ((spectral(p, o) && o->coarse_solver == 2) ? align_up(slab) : 0);
     // three levels: the level-1 iterate [N_T+1][n]; the level-1 sweeps' y (two), the level-2 FAS
     // right-hand side and corrections, [N_2+1][n] each
-    const size_t slab2 = three_level(o) ? (size_t)(n_level2(p, o) + 1) * (size_t)n_space(p) * sizeof(double) : 0;
     L.u1 = off;
     off += three_level(o) ? align_up(slab) : 0;
     L.y1a = off;
@@ -183,6 +191,8 @@ atm_status validate(const atm_problem* p, const atm_options* o)
         if (o->precision != 0) return fail(ATM_ERR_UNSUPPORTED, "levels 3 runs in precision 0");
         if (o->coarse_form == 3) return fail(ATM_ERR_UNSUPPORTED, "levels 3 uses the plain coarse propagator");
         if (large_grid(p)) return fail(ATM_ERR_UNSUPPORTED, "levels 3 takes grids up to 128 x 128");
+        if (ml_bf(p, o) && o->coarse_substeps != 1)
+            return fail(ATM_ERR_UNSUPPORTED, "levels 3 with coarse_solver 2 takes coarse_substeps 1");
     }
     if (o->nested != 0 && o->nested != 1) return fail(ATM_ERR_INVALID_ARG, "nested must be 0 or 1");
     if (o->nested == 1) {
@@ -265,7 +275,7 @@ atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_
     a.rtol2_mixed = mrtol * mrtol;
     a.maxit = p->cg_max_iter;
     a.spectral = spectral(p, o) ? (o->coarse_solver == 2 ? 2 : 1) : 0;
-    a.spec = a.spectral ? (double*)(base + L.spec) : nullptr;
+    a.spec = (a.spectral || ml_bf(p, o)) ? (double*)(base + L.spec) : nullptr;
     a.cres = a.spectral == 2 ? (double*)(base + L.cres) : nullptr;
     if (large_grid(p)) {
         a.large = 1;
@@ -624,7 +634,8 @@ atm::KArgs level1_args(const atm::KArgs& a0, const atm_problem* p, const atm_opt
     a1.cg_count = &a0.hdr->cg_coarse;
     a1.skip_unchanged = 0;
     a1.skip_y_src = nullptr;
-    a1.spectral = 0;
+    a1.spectral = ml_bf(p, o) ? 2 : 0;
+    a1.cres = ml_bf(p, o) ? (double*)(base + L.cres) : nullptr;
     return a1;
 }
 
@@ -659,8 +670,10 @@ atm_status level1_cycle(const atm::KArgs& a1, const atm_options* o, double* u1, 
     c1.u = u1;
     c1.y = y1;
     c1.e = e2;
-    atm::launch_tau(c1, s);
-    if ((st = check_launch())) return st;
+    if (c1.spectral != 2) {  // the BF16 windows take FAS in terms of e and need no tau
+        atm::launch_tau(c1, s);
+        if ((st = check_launch())) return st;
+    }
     atm::launch_coarse(c1, s);
     if ((st = check_launch())) return st;
     if ((st = do_level_sweep(a1, 1, u1, e2, y1a, s))) return st;
@@ -1358,8 +1371,8 @@ atm_status atm_solve(const atm_problem* prob, const atm_options* opts, double* u
         S.ms_setup = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_setup).count();
     }
     // the eigenbasis tables depend on the grid only: built once for every coarse solve below
-    if (a.spectral && !a.large) {
-        atm::launch_spectral_tables(a, s);
+    if ((a.spectral || a1.spectral) && !a.large) {
+        atm::launch_spectral_tables(a.spectral ? a : a1, s);
         if ((st = check_launch())) return st;
     }
     // F-relax the initial guess, then its residual

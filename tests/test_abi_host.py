@@ -162,3 +162,14 @@ def test_bf16_psi_restrictions(abi):
             (ok, W.Options(m=4, k=2, coarse_solver=3), False)]:
         n = abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(o)))
         assert (n > 0) == expect, (p, o)
+
+
+def test_three_levels_bf16_coarsest_needs_one_substep(abi):
+    p = W.Problem(W.HEAT2D, nx=32, ny=32, nt=64)
+    ok = W.Options(m=4, k=2, levels=3, m_coarse=2, coarse_solver=2)
+    bad = W.Options(m=4, k=2, levels=3, m_coarse=2, coarse_solver=2, coarse_substeps=2)
+    n_ok = abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(ok)))
+    n_cg = abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)),
+                                         ctypes.byref(abi.options(W.Options(**{**ok.__dict__, "coarse_solver": 1}))))
+    assert n_ok > n_cg > 0  # the tables and the coarsest level's residual rows
+    assert abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(bad))) == 0

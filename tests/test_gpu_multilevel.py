@@ -201,3 +201,20 @@ def test_nested_solve_matches_oracle(atm, orc, case):
     assert status == atm.ATM_OK
     assert gst["iterations"] == st["iterations"]
     assert_close(host(ud), ref, what="converged nested solve")
+
+
+@pytest.mark.parametrize("case", [(W.HEAT2D, 64, 48, 97, 4, 3, 2), (W.HEAT2D, 100, 37, 53, 4, 2, 100),
+                                  (W.AC2D, 24, 20, 61, 3, 4, 3)], ids=case_id)
+def test_three_levels_bf16_coarsest_same_fixed_point(atm, orc, case):
+    """coarse_solver 2: the coarsest windows on the BF16 matrix cores (FAS in terms of e), level 1 by CG:
+    the solve converges to the oracle's fixed point (the oracle's multilevel cycle with CG everywhere)."""
+    kind, nx, ny, nt, m, mc, k = case
+    p, u0 = small(kind, nx, ny, nt)
+    o = W.Options(m=m, k=k, relax=1, tol=1e-10, max_iter=80, levels=3, m_coarse=mc, coarse_solver=2)
+    g = W.initial_guess(p, u0)
+    ref, hist, st = orc.ml_solve(p, W.Options(**{**o.__dict__, "coarse_solver": 1}), g)
+    ud = dev(g)
+    status, ghist, gst = atm.atm_solve(p, o, ud)
+    assert status == atm.ATM_OK and ghist[-1] <= o.tol
+    assert gst["iterations"] <= st["iterations"] + 1
+    assert np.sqrt(np.sum((host(ud) - ref) ** 2)) <= 2 * (p.nt + 1) * o.tol
