@@ -218,3 +218,21 @@ def test_three_levels_bf16_coarsest_same_fixed_point(atm, orc, case):
     assert status == atm.ATM_OK and ghist[-1] <= o.tol
     assert gst["iterations"] <= st["iterations"] + 1
     assert np.sqrt(np.sum((host(ud) - ref) ** 2)) <= 2 * (p.nt + 1) * o.tol
+
+
+@pytest.mark.parametrize("case", [(W.HEAT2D, 64, 48, 97, 4, 3, 2, 2, 2), (W.AC2D, 32, 32, 64, 4, 3, 3, 2, 2),
+                                  (W.HEAT2D, 64, 48, 97, 4, 3, 2, 3, 2)], ids=nested_id)
+def test_nested_bf16_psi_same_fixed_point(atm, orc, case):
+    """Nested iteration with Psi on the BF16 matrix cores (two levels, linear and FAS in terms of e; three
+    levels, the coarsest windows): the solve reaches the oracle's fixed point."""
+    kind, nx, ny, nt = case[:4]
+    p, u0 = small(kind, nx, ny, nt)
+    o = nested_opts(case, tol=1e-10, max_iter=80)
+    o.coarse_substeps = 1
+    g = W.initial_guess(p, u0)
+    ref, hist, st = orc.ml_solve(p, W.Options(**{**o.__dict__, "coarse_solver": 1}), g)
+    ud = dev(g)
+    status, ghist, gst = atm.atm_solve(p, o, ud)
+    assert status == atm.ATM_OK and ghist[-1] <= o.tol and gst["ms_setup"] > 0
+    assert gst["iterations"] <= st["iterations"] + 1
+    assert np.sqrt(np.sum((host(ud) - ref) ** 2)) <= 2 * (p.nt + 1) * o.tol
