@@ -12,7 +12,10 @@ split operands, about 1e-5 relative (--coarse-solver 2; Psi only approximates
 Phi^m, the fixed point does not depend on it, and the cycle count equals the
 strict solve's); --coarse-solver 1 takes CG to --coarse-rtol instead, and one
 extra solve with Psi's CG at the fine tolerance is reported as
-"strict_coarse".  The other legs (Allen-Cahn, the batch) take Psi's FP64
+"strict_coarse".  The fine CG of every F-point starts from the previous point's
+value; "extrapolated_cg_start" reports the same solve with the library option
+cg_guess 1 (the stored iterate moved by the change at the previous point: fewer
+CG iterations, but each step first waits for two loads).  The other legs (Allen-Cahn, the batch) take Psi's FP64
 eigenbasis solve, the library default.
 
 Prints one JSON line (see the keys below).  --gpus > 1 is refused: this build
@@ -56,6 +59,9 @@ def parse():
     ap.add_argument("--coarse-solver", type=int, default=2,
                     help="Psi's implicit solve on the heat workload: 2 the eigenbasis on the BF16 matrix cores "
                          "(28 ms), 1 CG to --coarse-rtol (35 ms), 0 the FP64 eigenbasis (46 ms)")
+    ap.add_argument("--cg-guess", type=int, default=0,
+                    help="start of the fine CG solves: 0 the previous point's value, 1 the extrapolated iterate "
+                         "(fewer CG iterations, a slower sweep here)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-coarse-propagator comparison")
     ap.add_argument("--learned-epochs", type=int, default=15)
@@ -457,6 +463,7 @@ def main():
     o.profile = 1
     o.coarse_cg_rtol = args.coarse_rtol
     o.coarse_solver = args.coarse_solver
+    o.cg_guess = args.cg_guess
     dev = torch.device("cuda:0")
     guess = torch.from_numpy(W.initial_guess(p, u0)).to(dev)
     u = torch.empty_like(guess)
@@ -490,7 +497,8 @@ def main():
     sweep_flops = p.n * (FLOPS_PER_CG_ITER_POINT * agg["cg_fine"] + FLOPS_PER_SOLVE_POINT * agg["fine_steps"])
     achieved = sweep_flops / (agg["ms_sweep"] / 1e3) / 1e12 if agg["ms_sweep"] > 0 else 0.0
     roofline = {
-        "kernel": "sweep2d_kernel (FCF/F relaxation + correction sweeps)",
+        "kernel": ("sweep2d_xg_kernel" if o.cg_guess == 1 else "sweep2d_kernel")
+                  + " (FCF/F relaxation + correction sweeps)",
         "bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
         "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": sum(SWEEP_TRAFFIC_BYTES),
         "traffic_read_write": list(SWEEP_TRAFFIC_BYTES),
@@ -507,7 +515,9 @@ def main():
                                f"k={o.k}, FCF, backward Euler + Jacobi-PCG rtol 1e-12 ("
                                + {0: "Psi solved in the eigenbasis",
                                   2: "Psi solved in the eigenbasis on BF16 matrix cores, split operands"}.get(
-                                   args.coarse_solver, f"Psi's CG rtol {args.coarse_rtol:g}") + "), tol 1e-8, FP64",
+                                   args.coarse_solver, f"Psi's CG rtol {args.coarse_rtol:g}") + ")"
+                               + (", fine CG started from the extrapolated iterate" if o.cg_guess == 1 else "")
+                               + ", tol 1e-8, FP64",
                    "global_batch": 1, "seq_len": p.nt, "parallelism": "time-parallel, 1 GPU"},
         "iterations": last[1]["iterations"], "final_residual": last[0][-1],
         "phase_ms_per_step": {k: agg[k] / args.steps for k in ("ms_sweep", "ms_coarse", "ms_norm")},
@@ -530,9 +540,25 @@ def main():
     strict["value"] = p.n * p.nt / (strict["ms"] / 1e3)
     u_strict = u.clone()
 
+    # context: the headline solve with the other start of the fine CG solves
+    o_other = W.Options(**{**o.__dict__, "cg_guess": 1 - o.cg_guess})
+    other_runs = []
+    for _ in range(2):  # the first run warms up
+        u.copy_(guess)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        _, hist_o, st_o = atm.atm_solve(p, o_other, u, ws=ws, allow=(atm.ATM_OK,))
+        torch.cuda.synchronize()
+        other_runs.append(((time.perf_counter() - ts) * 1e3, hist_o, st_o))
+    ms_o, hist_o, st_o = other_runs[-1]
+    other_start = {"cg_guess": o_other.cg_guess, "ms": ms_o, "value": p.n * p.nt / (ms_o / 1e3),
+                   "iterations": st_o["iterations"], "final_residual": hist_o[-1], "ms_sweep": st_o["ms_sweep"],
+                   "cg_fine": st_o["cg_fine"],
+                   "avg_sweep_launch_ms": st_o["ms_sweep"] / max(st_o["n_sweeps"], 1)}
+
     # the FP32-fine / FP64-residual form of the same solve (stops on the FP64 implicit residual, which
     # bounds the paper-form residual; the final paper-form residual is reported)
-    o_mixed = W.Options(**{**o.__dict__, "precision": 1})
+    o_mixed = W.Options(**{**o.__dict__, "precision": 1, "cg_guess": 0})
     ws_m = atm.workspace(atm.atm_workspace_bytes(p, o_mixed), device=dev)
     mixed_runs = []
     for _ in range(2):  # the first run warms up
@@ -561,6 +587,7 @@ def main():
     mixed["max_abs_diff_to_gpu_sequential"] = float((useq - u_mixed).abs().max())
 
     out["strict_coarse"] = strict
+    out["plain_cg_start" if o.cg_guess == 1 else "extrapolated_cg_start"] = other_start
     out["mixed_precision"] = mixed
     out["gpu_sequential"] = {"value": p.n * p.nt / seq_s, "ms": seq_s * 1e3,
                              "speedup_of_atmgrit": seq_s * 1e3 / ms_per_step, "max_abs_diff_to_atmgrit": max_diff}
