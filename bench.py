@@ -451,8 +451,8 @@ def main():
         calibrate_copy(args.calibrate_copy)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the time-parallel path is built "
+              "for a single GPU, and sharding its intervals over several GPUs is not built", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -26,7 +26,7 @@
  *     injection of the approximation and its residual, the next level's FAS
  *     system, local grids on the coarsest level, ideal interpolation back.
  *
- * Readings taken where the paper is silent (all repeated in the design doc):
+ * Readings taken where the paper is silent:
  *   - g_0 = u_0.  Without a forcing term g_i = 0 for i >= 1.  With a PDE source
  *     b(x, t) (the manufactured 1D heat problem of section 4.3) the backward
  *     Euler step takes it at the new time level, M u_i = psi(u_{i-1}) + dt b(t_i),
