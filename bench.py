@@ -43,6 +43,12 @@ PEAK_HBM_GBS = 8000.0
 #   per solve (initial residual r = b - M x, (b,b), (r,r), (r,z), p = z)       = 14
 FLOPS_PER_CG_ITER_POINT = 20
 FLOPS_PER_SOLVE_POINT = 14
+# LDS bytes per grid point per CG iteration of the sweep kernel: the stencil reads the direction at the
+# point and at its west and east neighbours (8 B each; north and south come from the same strip), the
+# direction update reads it once more and writes it once
+LDS_BYTES_PER_CG_ITER_POINT = 40
+# LDS bandwidth, assuming 128 B per clock per CU: 256 CUs x 2.4 GHz x 128 B
+PEAK_LDS_TBS = 78.6
 # HBM bytes per launch of the FP64 sweep kernel on this workload (read, written), from rocprofv3
 # FETCH_SIZE and WRITE_SIZE counters scaled by the same counters of a plain 1 GiB copy (x2.0, x1.0)
 SWEEP_TRAFFIC_BYTES = (40.8e6, 321.8e6)
@@ -504,7 +510,12 @@ def main():
         "traffic_read_write": list(SWEEP_TRAFFIC_BYTES),
         "avg_launch_ms": agg["ms_sweep"] / max(agg["n_sweeps"], 1),
         "launches": agg["n_sweeps"],
+        # the resource a busy workgroup saturates: LDS traffic of its CG iterations (whole chip)
+        "lds": {"achieved": (p.n * LDS_BYTES_PER_CG_ITER_POINT * agg["cg_fine"] / (agg["ms_sweep"] / 1e3) / 1e12
+                             if agg["ms_sweep"] > 0 else 0.0),
+                "peak": PEAK_LDS_TBS, "unit": "TB/s"},
     }
+    roofline["lds"]["frac"] = roofline["lds"]["achieved"] / PEAK_LDS_TBS
 
     out = {
         "metric": "space-time point-updates/s to 1e-8 residual",
