@@ -335,11 +335,20 @@ atm_status check_launch()
 // C-relaxation) and the F-points of a ragged tail after it (none when m | nt).
 int64_t sweep_tasks(const atm_problem* p, const atm_options* o) { return n_intervals(p, o) + 1; }
 
-// Read back the header (norm, failure flag, CG count) after synchronising.
+// Read back the header (norm, failure flag, CG count) after synchronising.  The copy lands in a
+// pinned host buffer of the calling thread (allocated on its first readback and kept for the
+// thread's life: 32 bytes), so the DMA writes it directly instead of staging a pageable copy.
 atm_status read_header(const atm::KArgs& a, hipStream_t s, atm::Header* out)
 {
-    ATM_HIP(hipMemcpyAsync(out, a.hdr, sizeof(atm::Header), hipMemcpyDeviceToHost, s));
+    static thread_local atm::Header* pinned = nullptr;
+    if (!pinned) {
+        void* ptr = nullptr;
+        ATM_HIP(hipHostMalloc(&ptr, sizeof(atm::Header), hipHostMallocDefault));
+        pinned = static_cast<atm::Header*>(ptr);
+    }
+    ATM_HIP(hipMemcpyAsync(pinned, a.hdr, sizeof(atm::Header), hipMemcpyDeviceToHost, s));
     ATM_HIP(hipStreamSynchronize(s));
+    *out = *pinned;
     return ATM_OK;
 }
 
