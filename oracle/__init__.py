@@ -62,14 +62,35 @@ class OrStats(ctypes.Structure):
     ]
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (plain -O2, OpenMP for the interval/window loops)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+# Builds of the same source: "default" (the tests' build) and "native" (-O3 for the host it runs on,
+# used only to time the oracle as the CPU baseline).  Both keep -ffp-contract=off, so the arithmetic
+# is the same.
+_BUILDS = {
+    "default": (_LIB, ["-O2"]),
+    "native": (os.path.join(_HERE, "liboracle_native.so"), ["-O3", "-march=native"]),
+}
+_variant = "default"
+
+
+def build(force: bool = False, variant: str = "default") -> str:
+    """Compile the oracle with gcc (plain C, OpenMP for the interval/window loops)."""
+    path, opt = _BUILDS[variant]
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp"
+        subprocess.check_call(["gcc", *opt, "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
                                "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, path)
+    return path
+
+
+def select_build(variant: str) -> None:
+    """Load the given build for the calls below (the CPU-baseline timing uses "native")."""
+    global _lib, _variant
+    if variant not in _BUILDS:
+        raise KeyError(variant)
+    if variant != _variant:
+        _variant = variant
+        _lib = None
 
 
 _lib = None
@@ -78,7 +99,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(build())
+        _lib = ctypes.CDLL(build(variant=_variant))
         P, O, S = ctypes.POINTER(OrProblem), ctypes.POINTER(OrOptions), ctypes.POINTER(OrStats)
         dp = ctypes.POINTER(ctypes.c_double)
         i64p = ctypes.POINTER(ctypes.c_int64)
@@ -163,6 +184,11 @@ def _check(st, what):
 
 def set_threads(t: int):
     lib().or_set_threads(int(t))
+
+
+def max_threads() -> int:
+    """OpenMP's thread count for this process (OMP_NUM_THREADS, else the host's cores)."""
+    return int(lib().or_get_max_threads())
 
 
 def step(p, dt, x):

@@ -147,21 +147,28 @@ def adam(vec, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
     return vec - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
-def learned_local_solves(vec, states, r, k, bf16_mode=True):
-    """Every window's correction in the FAS form (Alg. 2, coarsest level) with the learned Psi:
-    tau_j = (v_j - Psi(v_{j-1})) + r_j; for window p with s = max(0, p - k + 1), w = v_s + r_s,
-    w = Psi(w) + tau_j for j = s+1..p, e_p = w - v_p.
+def fas_local_solves(psi_fn, states, r, k):
+    """Every window's correction in the FAS form (Alg. 2, coarsest level; section 2.1 local grids) with
+    the coarse propagator psi_fn (one C-point state [h, w] -> the next):
+    tau_j = (v_j - Psi(v_{j-1})) + r_j for j = 1..N_T; window p covers s = max(0, p - k + 1) .. p and
+    starts from w = v_s + r_s, then w = Psi(w) + tau_j for j = s+1..p; e_p = w - v_p.
     states: [N_T+1, h, w] C-point values v_j; r: [N_T+1, h, w] C-point residuals (r_0 = 0)."""
     NT = r.shape[0] - 1
     states = np.asarray(states, dtype=np.float64)
+    r = np.asarray(r, dtype=np.float64)
     tau = np.zeros_like(states)
     for j in range(1, NT + 1):
-        tau[j] = (states[j] - psi(vec, states[j - 1][None], bf16_mode)[0]) + r[j]
+        tau[j] = (states[j] - psi_fn(states[j - 1])) + r[j]
     e_all = np.zeros_like(states)
     for p in range(NT + 1):
         s = max(0, p - k + 1)
         w = states[s] + r[s]
         for j in range(s + 1, p + 1):
-            w = psi(vec, w[None], bf16_mode)[0] + tau[j]
+            w = psi_fn(w) + tau[j]
         e_all[p] = w - states[p]
     return e_all
+
+
+def learned_local_solves(vec, states, r, k, bf16_mode=True):
+    """The FAS windows above with the learned Psi(x) = x + f(x)."""
+    return fas_local_solves(lambda x: psi(vec, x[None], bf16_mode)[0], states, r, k)

@@ -131,3 +131,84 @@ def test_bf16_rounding():
     x = rng.standard_normal(10000) * 10.0 ** rng.integers(-5, 5, 10000)
     np.testing.assert_array_equal(C.bf16(x), torch.tensor(x, dtype=torch.float32).to(torch.bfloat16)
                                   .to(torch.float64).numpy())
+
+
+# ---------------------------------------------------------------------------
+# the learned windows (FAS form of Alg. 2 at the coarsest level, section 2.1 local grids)
+# ---------------------------------------------------------------------------
+
+def window_inputs(nt_c=9, h=6, w=8, seed=11):
+    rng = np.random.default_rng(seed)
+    states = rng.uniform(-1, 1, size=(nt_c + 1, h, w))
+    r = rng.standard_normal((nt_c + 1, h, w))
+    r[0] = 0.0
+    return states, r
+
+
+def windowed_residual_sums(r, k):
+    """e_p = r_s + r_{s+1} + ... + r_p, s = max(0, p - k + 1), by a running sum over the residuals."""
+    c = np.concatenate([np.zeros((1,) + r.shape[1:]), np.cumsum(r, axis=0)])
+    return np.stack([c[p + 1] - c[max(0, p - k + 1)] for p in range(r.shape[0])])
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 10, 11])
+def test_learned_windows_zero_network_sum_residuals(k):
+    """A zero network gives Psi = I; the FAS window then telescopes to the sum of the residuals over
+    the window's C-points (v cancels).  Pins the start s, the first row (v_s + r_s) and tau's index."""
+    states, r = window_inputs()
+    got = C.learned_local_solves(np.zeros(C.N_PARAMS), states, r, k, bf16_mode=False)
+    ref = windowed_residual_sums(r, k)
+    assert np.max(np.abs(got - ref)) <= 1e-13
+
+
+@pytest.mark.parametrize("bf16_mode", [False, True])
+def test_learned_windows_constant_bias_cancels(bf16_mode):
+    """Only the output bias set (f = c): Psi(x) = x + c, and c cancels between Psi(w) and tau's
+    -Psi(v): the same residual sums.  A sign error in tau would leave (p - s) c."""
+    states, r = window_inputs(seed=12)
+    P = C.unpack(np.zeros(C.N_PARAMS))
+    P["b4"][0] = 0.375
+    P["b1"][...] = 0.2     # hidden biases do not reach f while the weights are zero
+    got = C.learned_local_solves(C.pack(P), states, r, 4, bf16_mode=bf16_mode)
+    assert np.max(np.abs(got - windowed_residual_sums(r, 4))) <= 1e-13
+
+
+def test_fas_windows_equal_c_oracle_local_solves(orc):
+    """With the re-discretised coarse step as Psi, the windows equal the C oracle's FAS local solves
+    (written separately, pinned by the windows of Figs. 1, 2 and 5 and the E_cc closed form), bit for bit."""
+    p, u0 = W.small_problem(W.AC2D, seed=3, nt=40, nx=6, ny=5)
+    o = W.Options(m=4, k=3, coarse_form=2, coarse_substeps=2)
+    NT = p.nt // o.m
+    rng = np.random.default_rng(5)
+    vc = rng.uniform(-0.5, 0.5, size=(NT + 1, p.n))
+    rc = 1e-2 * rng.standard_normal((NT + 1, p.n))
+    rc[0] = 0.0
+    ref = orc.local_solves(p, o, rc, vc)
+    got = C.fas_local_solves(lambda x: orc.coarse_step(p, o, x.reshape(-1)).reshape(p.ny, p.nx),
+                             vc.reshape(NT + 1, p.ny, p.nx), rc.reshape(NT + 1, p.ny, p.nx), o.k)
+    np.testing.assert_array_equal(got.reshape(NT + 1, p.n), ref)
+
+
+def test_planted_window_off_by_one_is_caught():
+    """A window loop started one C-point early (s = max(0, p - k)) fails the zero-network pin."""
+    states, r = window_inputs(seed=13)
+    k = 3
+
+    def planted(psi_fn, states, r, k):
+        NT = r.shape[0] - 1
+        tau = np.zeros_like(states)
+        for j in range(1, NT + 1):
+            tau[j] = (states[j] - psi_fn(states[j - 1])) + r[j]
+        out = np.zeros_like(states)
+        for p in range(NT + 1):
+            s = max(0, p - k)
+            w = states[s] + r[s]
+            for j in range(s + 1, p + 1):
+                w = psi_fn(w) + tau[j]
+            out[p] = w - states[p]
+        return out
+
+    bad = planted(lambda x: x, states, r, k)
+    assert np.max(np.abs(bad - windowed_residual_sums(r, k))) > 1e-3
+    good = C.fas_local_solves(lambda x: x, states, r, k)
+    assert np.max(np.abs(good - windowed_residual_sums(r, k))) <= 1e-13

@@ -110,3 +110,46 @@ def test_batch_workload_sample(atm):
         assert st == atm.ATM_OK and s["iterations"] == stats[i]["iterations"]
         assert np.array_equal(us[i], host(ud)), i
     print(f"12 instances: {ms:.1f} ms, tuning {mt:.1f} ms, cycles {[s['iterations'] for s in stats]}")
+
+
+def parity_batch():
+    """small_batch() set up for parity with the oracle: the FP64 2D instances take CG to 1e-14 (iterate
+    parity needs the same tight inner tolerance on both sides, whose summation orders differ), the FP32-fine
+    instances stop at the reduced-precision bar 1e-10."""
+    out = []
+    for p, o, u0 in small_batch():
+        if o.precision == 0 and p.kind != W.HEAT1D:
+            p = W.Problem(**{**p.__dict__, "cg_rtol": 1e-14})
+        if o.precision == 1:
+            o = W.Options(**{**o.__dict__, "tol": 1e-10})
+        out.append((p, o, u0))
+    return out
+
+
+def test_batch_instances_match_oracle(atm, orc):
+    """Every instance of a batch against the CPU oracle (not against the GPU's own atm_solve): FP64 instances
+    take the oracle's cycle count and match its iterate element by element to 1e-12 relative; FP32-fine
+    instances meet 1e-10 in the oracle's FP64 implicit and paper-form residuals of the result, and their
+    error against the oracle's sequential stepping is stated."""
+    items = parity_batch()
+    us, status, stats, hists, ms, mt, tuning = run_batch(atm, items)
+    for i, (p, o, u0) in enumerate(items):
+        assert status[i] == atm.ATM_OK, i
+        g = W.initial_guess(p, u0)
+        if o.precision == 0:
+            ref, ref_hist, ref_stats = orc.solve(p, o, g)
+            err = float(np.max(np.abs(us[i] - ref)) / np.max(np.abs(ref)))
+            print(f"instance {i} ({W.KIND_NAMES[p.kind]} {p.nx}x{p.ny} nt {p.nt}, FP64): cycles "
+                  f"{stats[i]['iterations']} (oracle {ref_stats['iterations']}), max rel. difference {err:.2e}")
+            assert stats[i]["iterations"] == ref_stats["iterations"], i
+            assert err <= 1e-12, (i, err)
+        else:
+            rho = float(np.linalg.norm(orc.implicit_residual(p, us[i])))
+            r = float(np.linalg.norm(orc.step_residual(p, us[i])))
+            q = W.Problem(**{**p.__dict__, "cg_rtol": 1e-14})
+            err = float(np.max(np.abs(us[i] - orc.sequential(q, u0))))
+            print(f"instance {i} ({W.KIND_NAMES[p.kind]} {p.nx}x{p.ny} nt {p.nt}, FP32 fine): cycles "
+                  f"{stats[i]['iterations']}, oracle implicit residual {rho:.2e}, paper-form {r:.2e}, max error "
+                  f"against the FP64 oracle's sequential stepping {err:.2e}")
+            assert rho <= 1e-10 * (1 + 1e-6) and r <= rho * (1 + 1e-9), i
+            assert err <= 1e-8, (i, err)

@@ -5,6 +5,7 @@ import pytest
 
 import workloads as W
 from tests.conftest import gpu_available
+from tests.test_gpu_mixed import rounding_floor
 from tests.test_gpu_parity import assert_close, dev, host, small, y_of
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -100,21 +101,26 @@ def test_large_sequential_and_solve(atm, orc, case):
 
 def test_ac256_full_size(atm, orc):
     """2D Allen-Cahn 256x256 periodic, eps 0.02, dt 1e-5, Nt 8192, m 64, k 13, FCF, 4 coarse substeps, FP32 fine
-    solves: converge to 1e-8 on the GPU; the stopping norm equals the oracle's implicit residual of the result,
-    and the first 64 steps match the oracle's sequential stepping."""
+    solves, to the reduced-precision bar 1e-10: the stopping norm equals the oracle's FP64 implicit residual of
+    the result at every one of the 5.4e8 space-time points, the paper-form residual is at most the stopping
+    norm, and the first 64 steps match the oracle's sequential stepping (its error is printed)."""
     p, o, u0 = W.config("c3")
+    o.tol = 1e-10
     ud = dev(W.initial_guess(p, u0))
     status, hist, st = atm.atm_solve(p, o, ud)
-    print(f"cycles {st['iterations']}, residual {hist[-1]:.3e}, final {st['final_residual']:.3e}, "
-          f"{st['ms_total']:.0f} ms")
-    assert status == atm.ATM_OK and hist[-1] <= o.tol and st["final_residual"] <= hist[-1] * (1 + 1e-9)
     u = host(ud)
+    floor = rounding_floor(p, u)
     rho = float(np.linalg.norm(orc.implicit_residual(p, u)))
-    assert abs(hist[-1] - rho) <= 1e-9 * rho + 1e-12
     q = W.Problem(**{**p.__dict__, "nt": 64, "tf": p.t0 + 64 * p.dt, "cg_rtol": 1e-14})
     ref = orc.sequential(q, u0)
     err = float(np.max(np.abs(u[:65] - ref)))
-    assert err <= 1e-8, f"max error against the FP64 oracle on the first 64 steps: {err:.2e}"
+    print(f"cycles {st['iterations']}, stopping norm {hist[-1]:.3e} (oracle {rho:.3e}, rounding floor {floor:.1e}), "
+          f"paper-form {st['final_residual']:.3e}, error against the FP64 oracle on the first 64 steps {err:.2e}, "
+          f"{st['ms_total']:.0f} ms")
+    assert status == atm.ATM_OK and hist[-1] <= 1e-10
+    assert abs(hist[-1] - rho) <= 1e-9 * rho + floor
+    assert st["final_residual"] <= hist[-1] * (1 + 1e-9) + floor
+    assert err <= 1e-9, f"max error against the FP64 oracle on the first 64 steps: {err:.2e}"
 
 
 @pytest.mark.parametrize("solver", [0, 1], ids=["eigenbasis", "cg"])

@@ -225,20 +225,22 @@ def test_c2_mixed_full_size(atm, orc):
 def test_c5_full_size(atm, orc, solver):
     """2D Allen-Cahn 128x128 periodic, eps 0.03, dt 1e-5, Nt 4096, m 32, k 13, FCF, FP32 fine solves, Psi in the
     FP64 eigenbasis (the benchmarked plain solve of the learned-propagator comparison) or on the BF16 matrix cores
-    (FAS in terms of e = w - v): converge to 1e-8; the stopping norm is the oracle's implicit residual of the
-    result, the paper-form residual is bracketed by it, and the first 64 steps match the oracle's sequential
-    stepping."""
+    (FAS in terms of e = w - v), to the reduced-precision bar 1e-10: the stopping norm is the oracle's implicit
+    residual of the result, the paper-form residual is bracketed by it, and the first 64 steps match the
+    oracle's sequential stepping (its error is printed)."""
     p, o, u0 = W.config("c5")
     o.coarse_solver = solver
+    o.tol = 1e-10
     ud = dev(W.initial_guess(p, u0))
     status, hist, st = atm.atm_solve(p, o, ud)
-    print(f"cycles {st['iterations']}, residual {hist[-1]:.3e}, final {st['final_residual']:.3e}")
-    assert status == atm.ATM_OK and hist[-1] <= o.tol
     u = host(ud)
     floor = rounding_floor(p, u)
     rho = float(np.linalg.norm(orc.implicit_residual(p, u)))
-    assert abs(hist[-1] - rho) <= 1e-12 * rho + floor
-    assert st["final_residual"] <= hist[-1] * (1 + 1e-9) + floor
     q = W.Problem(**{**p.__dict__, "nt": 64, "tf": p.t0 + 64 * p.dt, "cg_rtol": 1e-14})
     err = float(np.max(np.abs(u[:65] - orc.sequential(q, u0))))
-    assert err <= 1e-8, f"max error against the FP64 oracle on the first 64 steps: {err:.2e}"
+    print(f"cycles {st['iterations']}, stopping norm {hist[-1]:.3e} (oracle {rho:.3e}, floor {floor:.1e}), "
+          f"paper-form {st['final_residual']:.3e}, error against the FP64 oracle on the first 64 steps {err:.2e}")
+    assert status == atm.ATM_OK and hist[-1] <= 1e-10
+    assert abs(hist[-1] - rho) <= 1e-12 * rho + floor
+    assert st["final_residual"] <= hist[-1] * (1 + 1e-9) + floor
+    assert err <= 1e-9, f"max error against the FP64 oracle on the first 64 steps: {err:.2e}"
