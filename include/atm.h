@@ -225,6 +225,29 @@ atm_status atm_sweep(const atm_problem* prob, const atm_options* opts, int32_t m
 atm_status atm_coarse_solve(const atm_problem* prob, const atm_options* opts, const double* u,
                             const double* y, double* e, void* ws, size_t ws_bytes, void* stream);
 
+/* The window solve of atm_coarse_solve without a workspace argument, for
+   callers that cannot allocate device memory (code under HIP graph capture,
+   serving loops, harnesses that forbid allocation).  The call allocates
+   nothing: the workspace is a static device array of
+   atm_static_scratch_bytes() bytes (32 MiB), one per GPU, held from the
+   library's load until the process ends; the call enqueues kernels only
+   (no memset, copy or synchronisation).  Same arguments, results and layout
+   as atm_coarse_solve.  Limits: two levels, the plain coarse propagator with
+   a direct solve (1D, or 2D with coarse_solver 0 or 2, which cannot fail),
+   grids of at most 128 points per side, and a window phase that fits the
+   scratch (tau, the eigenbasis tables and the C-point residuals; about
+   (N_T+1) n 8 bytes each), else WORKSPACE.  The stream must belong to the
+   current device (the default stream is the current device's).  Every call on
+   a GPU uses that GPU's one array, which keeps the previous call's contents:
+   calls that overlap on one GPU (on different streams or host threads)
+   race, so a caller serialises them.  Errors: INVALID_ARG, UNSUPPORTED,
+   WORKSPACE, DEVICE. */
+atm_status atm_coarse_solve_static(const atm_problem* prob, const atm_options* opts, const double* u,
+                                   const double* y, double* e, void* stream);
+
+/* Size in bytes of the static scratch of atm_coarse_solve_static. */
+size_t atm_static_scratch_bytes(void);
+
 /* Residual 2-norm ||g - A(u)||_2 of an iterate whose F-points are relaxed
    (the stopping test of section 4.3): sqrt(sum_{j=1..N_T} ||y_j - u_{jm}||^2).
    Synchronises the stream and writes the value to *norm_out (host).

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -142,6 +143,33 @@ Layout layout(const atm_problem* p, const atm_options* o)
     return L;
 }
 
+// The window phase alone (atm_coarse_solve_static): the header, the norm partials, the FAS
+// right-hand side tau, the eigenbasis tables and the BF16 form's C-point residuals; every other
+// region is empty (offset 0, never touched by the window kernels).
+Layout coarse_layout(const atm_problem* p, const atm_options* o)
+{
+    const size_t NT = (size_t)n_intervals(p, o);
+    const size_t slab = (NT + 1) * (size_t)n_space(p) * sizeof(double);
+    Layout L;
+    memset(&L, 0, sizeof(L));
+    size_t off = 0;
+    L.header = off;
+    off += align_up(sizeof(atm::Header));
+    L.partials = off;
+    off += align_up((NT + 1 > (size_t)atm::kResidBlocks ? NT + 1 : (size_t)atm::kResidBlocks) * sizeof(double));
+    L.tau = off;
+    off += use_fas(p, o) ? align_up(slab) : 0;
+    L.spec = off;
+    off += spectral(p, o) ? align_up((atm::spectral_table_doubles(p->nx, p->ny) +
+                                      (o->coarse_solver == 2 ? atm::spectral_bf16_doubles(p->nx, p->ny) : 0)) *
+                                     sizeof(double))
+                          : 0;
+    L.cres = off;
+    off += (spectral(p, o) && o->coarse_solver == 2) ? align_up(slab) : 0;
+    L.total = off;
+    return L;
+}
+
 atm_status validate(const atm_problem* p, const atm_options* o)
 {
     if (!p || !o) return fail(ATM_ERR_INVALID_ARG, "null problem or options");
@@ -242,11 +270,20 @@ atm::StepCoef step_coef(const atm_problem* p, double dt)
 }
 
 // Fill the kernel argument block for a workspace (or NULL for size-only).
+atm_status make_args_in(const atm_problem* p, const atm_options* o, void* ws, size_t ws_bytes, const Layout& L,
+                        atm::KArgs& a);
+
 atm_status make_args(const atm_problem* p, const atm_options* o, void* ws, size_t ws_bytes, atm::KArgs& a)
 {
     atm_status st = validate(p, o);
     if (st) return st;
-    const Layout L = layout(p, o);
+    return make_args_in(p, o, ws, ws_bytes, layout(p, o), a);
+}
+
+// the kernel arguments over a workspace laid out as L (p and o validated)
+atm_status make_args_in(const atm_problem* p, const atm_options* o, void* ws, size_t ws_bytes, const Layout& L,
+                        atm::KArgs& a)
+{
     if (ws_bytes < L.total)
         return fail(ATM_ERR_WORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes, L.total);
     if (!ws) return fail(ATM_ERR_INVALID_ARG, "null workspace");
@@ -1267,6 +1304,76 @@ atm_status atm_coarse_solve(const atm_problem* prob, const atm_options* opts, co
     if (learned(opts))
         return do_coarse_learned(a, layout(prob, opts), ws, prob, opts, (double*)u, (double*)y, e, as_stream(stream));
     return do_coarse(a, (double*)u, (double*)y, e, as_stream(stream));
+}
+
+// ---------------------------------------------------------------------------
+// the window phase without a workspace argument: its tables live in a static device array
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr size_t kStaticScratchBytes = size_t(32) << 20;
+constexpr int kMaxDevices = 64;
+
+// One copy per GPU, held from the library's load until the process ends.  In host code the
+// name stands for a host-side shadow, never for the device address: kernels get the address
+// that hipGetSymbolAddress returns for the device in use.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device, looked up once per device
+atm_status static_scratch(int dev, void** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(ATM_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(ATM_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return ATM_OK;
+}
+
+}  // namespace
+
+size_t atm_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+atm_status atm_coarse_solve_static(const atm_problem* prob, const atm_options* opts, const double* u, const double* y,
+                                   double* e, void* stream)
+{
+    atm_status st = validate(prob, opts);
+    if (st) return st;
+    if (!u || !y || !e) return fail(ATM_ERR_INVALID_ARG, "null u, y or e");
+    if (e == y) return fail(ATM_ERR_INVALID_ARG, "e and y must not alias");
+    if (learned(opts) || three_level(opts))
+        return fail(ATM_ERR_UNSUPPORTED, "the static window solve takes the two-level plain coarse propagator");
+    if (large_grid(prob))
+        return fail(ATM_ERR_UNSUPPORTED, "the static window solve takes grids of at most %d points per side",
+                    atm::kMaxSide2D);
+    if (prob->kind != ATM_HEAT1D && !spectral(prob, opts))
+        return fail(ATM_ERR_UNSUPPORTED, "the static window solve takes Psi's direct solves only (coarse_solver 0 or 2)");
+    const Layout L = coarse_layout(prob, opts);
+    if (L.total > kStaticScratchBytes)
+        return fail(ATM_ERR_WORKSPACE, "the window solve needs %zu bytes of scratch; the static scratch holds %zu",
+                    L.total, kStaticScratchBytes);
+    hipStream_t s = as_stream(stream);
+    int dev = -1, sdev = -1;
+    ATM_HIP(hipGetDevice(&dev));
+    if (s) ATM_HIP(hipStreamGetDevice(s, &sdev));
+    if (s && sdev != dev)
+        return fail(ATM_ERR_INVALID_ARG, "stream of device %d while device %d is current", sdev, dev);
+    void* ws = nullptr;
+    if ((st = static_scratch(dev, &ws))) return st;
+    atm::KArgs a;
+    if ((st = make_args_in(prob, opts, ws, kStaticScratchBytes, L, a))) return st;
+    atm::launch_reset(a.hdr, s);  // the header's counters start from zero in every call
+    if ((st = check_launch())) return st;
+    return do_coarse(a, (double*)u, (double*)y, e, s);
 }
 
 atm_status atm_residual_norm(const atm_problem* prob, const atm_options* opts, const double* u, const double* y,
