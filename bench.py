@@ -46,8 +46,7 @@ FLOPS_PER_CG_ITER_POINT = 18
 # HBM traffic per launch of the headline's sweep kernel (bytes read, bytes written), from rocprofv3
 # FETCH_SIZE and WRITE_SIZE on the headline workload, scaled by the same counters of a plain device
 # copy; keyed by the kernel they were taken on (a kernel without counters reports null)
-SWEEP_TRAFFIC_BYTES = {}
-HEADLINE_SWEEP_KERNEL = "sweep_large_mixed_kernel"
+SWEEP_TRAFFIC_BYTES = {"sweep_large_mixed_kernel": (133.4e9, 87.2e9)}
 
 
 def parse():
@@ -500,10 +499,11 @@ def main():
     avg_ms = agg["ms_sweep"] / max(launches, 1)
     bytes_launch = SWEEP_MIXED_BYTES_PER_POINT * p.n * p.nt
     achieved = bytes_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = SWEEP_TRAFFIC_BYTES.get(HEADLINE_SWEEP_KERNEL)
+    kernel = atm.atm_sweep_kernel(p, o)
+    traffic = SWEEP_TRAFFIC_BYTES.get(kernel)
     cg_tflops = FLOPS_PER_CG_ITER_POINT * p.n * agg["cg_fine"] / (agg["ms_sweep"] / 1e3) / 1e12 if agg["ms_sweep"] else 0
     roofline = {
-        "kernel": HEADLINE_SWEEP_KERNEL, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+        "kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
         "traffic": None if traffic is None else sum(traffic),
         "bytes_per_launch": bytes_launch, "avg_launch_ms": round(avg_ms, 4), "launches_per_step": launches / args.steps,

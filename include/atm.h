@@ -248,6 +248,14 @@ atm_status atm_coarse_solve_static(const atm_problem* prob, const atm_options* o
 /* Size in bytes of the static scratch of atm_coarse_solve_static. */
 size_t atm_static_scratch_bytes(void);
 
+/* Name of the kernel that runs the relaxation sweeps of atm_sweep and atm_solve for
+   this problem and these options on the current device (static string; "" if
+   the arguments are invalid): sweep1d_kernel, sweep2d_kernel, sweep2d_mixed_kernel,
+   sweep_large_kernel, sweep_large_mixed_kernel, or sweep_pair_mixed_kernel (precision 1
+   on 256 x 256, 256 x 128 and 128 x 256 grids: two workgroups per interval, launched
+   cooperatively, when the device holds them all at once). */
+const char* atm_sweep_kernel(const atm_problem* prob, const atm_options* opts);
+
 /* Residual 2-norm ||g - A(u)||_2 of an iterate whose F-points are relaxed
    (the stopping test of section 4.3): sqrt(sum_{j=1..N_T} ||y_j - u_{jm}||^2).
    Synchronises the stream and writes the value to *norm_out (host).

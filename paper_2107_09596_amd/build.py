@@ -8,7 +8,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libatmgrit.so")
-SOURCES = ["atm_kernels.hip", "atm_mixed.hip", "atm_large.hip", "atm_batch.hip", "atm_cnn.hip", "atm_cnn_api.hip", "atm_api.hip"]
+SOURCES = ["atm_kernels.hip", "atm_mixed.hip", "atm_large.hip", "atm_pair.hip", "atm_batch.hip", "atm_cnn.hip", "atm_cnn_api.hip", "atm_api.hip"]
 HEADERS = ["atm_device.hpp", "atm_kernels.hpp"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -375,6 +375,18 @@ int64_t sweep_tasks(const atm_problem* p, const atm_options* o) { return n_inter
 // Read back the header (norm, failure flag, CG count) after synchronising.  The copy lands in a
 // pinned host buffer of the calling thread (allocated on its first readback and kept for the
 // thread's life: 32 bytes), so the DMA writes it directly instead of staging a pageable copy.
+// The failure flags of a header read back after a synchronisation: a workgroup pair of the large-grid
+// FP32 sweep that gave up waiting for its partner, or a CG solve that missed its tolerance.
+atm_status header_status(const atm::Header& h, int maxit)
+{
+    if (h.fail & atm::kFailPairTimeout)
+        return fail(ATM_ERR_DEVICE, "a workgroup pair of the relaxation sweep did not meet within its wait limit");
+    if (h.fail)
+        return fail(ATM_ERR_INNER_SOLVE, "a CG solve inside Phi or Psi did not reach its tolerance within %d iterations",
+                    maxit);
+    return ATM_OK;
+}
+
 atm_status read_header(const atm::KArgs& a, hipStream_t s, atm::Header* out)
 {
     static thread_local atm::Header* pinned = nullptr;
@@ -398,9 +410,10 @@ atm_status do_sweep(atm::KArgs a, const atm_problem* p, const atm_options* o, in
     a.u = u;
     a.aux = aux;
     a.y = y;
-    if (a.large)
-        atm::launch_sweep_large(a, sweep_tasks(p, o), o->precision == 1, s);
-    else if (o->precision == 1)
+    if (a.large) {
+        const hipError_t e = atm::launch_sweep_large(a, sweep_tasks(p, o), o->precision == 1, s);
+        if (e != hipSuccess) return fail(ATM_ERR_DEVICE, "sweep launch: %s", hipGetErrorString(e));
+    } else if (o->precision == 1)
         atm::launch_sweep_mixed(a, sweep_tasks(p, o), s);
     else
         atm::launch_sweep(a, sweep_tasks(p, o), s);
@@ -439,9 +452,7 @@ atm_status do_norm(atm::KArgs a, double* u, double* y, hipStream_t s, double* no
     st = read_header(a, s, hdr);
     if (st) return st;
     *norm_out = sqrt(hdr->norm2);
-    if (hdr->fail) return fail(ATM_ERR_INNER_SOLVE, "a CG solve inside Phi or Psi did not reach cg_rtol within %d iterations",
-                               a.maxit);
-    return ATM_OK;
+    return header_status(*hdr, a.maxit);
 }
 
 // The stopping norm of precision 1 (implicit residual) and the paper-form
@@ -453,9 +464,7 @@ atm_status finish_norm(const atm::KArgs& a, hipStream_t s, double* norm_out, atm
     st = read_header(a, s, hdr);
     if (st) return st;
     *norm_out = sqrt(hdr->norm2);
-    if (hdr->fail) return fail(ATM_ERR_INNER_SOLVE, "a CG solve inside Phi or Psi did not reach its tolerance within %d iterations",
-                               a.maxit);
-    return ATM_OK;
+    return header_status(*hdr, a.maxit);
 }
 
 atm_status do_implicit_norm(atm::KArgs a, const double* u, hipStream_t s, double* norm_out, atm::Header* hdr)
@@ -1376,6 +1385,23 @@ atm_status atm_coarse_solve_static(const atm_problem* prob, const atm_options* o
     return do_coarse(a, (double*)u, (double*)y, e, s);
 }
 
+const char* atm_sweep_kernel(const atm_problem* prob, const atm_options* opts)
+{
+    if (validate(prob, opts) != ATM_OK) return "";
+    if (prob->kind == ATM_HEAT1D) return "sweep1d_kernel";
+    const bool mixed = opts->precision == 1;
+    if (!large_grid(prob)) return mixed ? "sweep2d_mixed_kernel" : "sweep2d_kernel";
+    if (!mixed) return "sweep_large_kernel";
+    atm::KArgs a;
+    memset(&a, 0, sizeof(a));
+    a.large = 1;
+    a.g.nx = prob->nx;
+    a.g.ny = prob->ny;
+    a.n = n_space(prob);
+    a.NT = n_intervals(prob, opts);
+    return atm::sweep_pair_pairs(a, sweep_tasks(prob, opts)) > 0 ? "sweep_pair_mixed_kernel" : "sweep_large_mixed_kernel";
+}
+
 atm_status atm_residual_norm(const atm_problem* prob, const atm_options* opts, const double* u, const double* y,
                              double* norm_out, void* ws, size_t ws_bytes, void* stream)
 {
@@ -1433,8 +1459,7 @@ atm_status atm_sequential(const atm_problem* prob, double* u, void* ws, size_t w
     atm::Header h;
     st = read_header(a, s, &h);
     if (st) return st;
-    if (h.fail) return fail(ATM_ERR_INNER_SOLVE, "a CG solve did not reach cg_rtol within %d iterations", a.maxit);
-    return ATM_OK;
+    return header_status(h, a.maxit);
 }
 
 size_t atm_sequential_workspace_bytes(const atm_problem* prob)

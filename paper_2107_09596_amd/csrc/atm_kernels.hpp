@@ -157,7 +157,13 @@ void launch_step_residual(const KArgs& a, int64_t n_tasks, hipStream_t s);
 
 // large 2D grids (atm_large.hip)
 constexpr int kMaxSideLarge = 1024;
-void launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t s);
+hipError_t launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t s);
+// FP32-fine sweeps of the large grids on two CUs per interval (atm_pair.hip): the number of
+// workgroup pairs for this grid and workspace (0 if the pair kernel does not take it), and the
+// cooperative launch.  Header::fail bit 2 marks a pair whose partner did not arrive.
+constexpr int kFailPairTimeout = 2;
+int sweep_pair_pairs(const KArgs& a, int64_t n_tasks);
+hipError_t launch_sweep_pair(const KArgs& a, int pairs, hipStream_t s);
 void launch_coarse_large(const KArgs& a, hipStream_t s);
 // doubles of the eigenbasis tables of an nx x ny grid (KArgs::spec), and their construction
 size_t spectral_table_doubles(int nx, int ny);

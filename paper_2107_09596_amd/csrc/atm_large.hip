@@ -595,12 +595,17 @@ __global__ __launch_bounds__(256) void sum_partials_large_kernel(KArgs a, int64_
     if (threadIdx.x == 0) a.hdr->norm2 = acc;
 }
 
-void launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t s)
+hipError_t launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t s)
 {
+    if (mixed) {
+        const int pairs = a.large_scratch ? sweep_pair_pairs(a, n_tasks) : 0;
+        if (pairs > 0) return launch_sweep_pair(a, pairs, s);
+    }
     if (mixed)
         hipLaunchKernelGGL(sweep_large_mixed_kernel, dim3(n_tasks), dim3(kBlockL), 0, s, a, scratch_of(a));
     else
         hipLaunchKernelGGL(sweep_large_kernel, dim3(n_tasks), dim3(kBlockL), 0, s, a, scratch_of(a));
+    return hipGetLastError();
 }
 
 void launch_coarse_large(const KArgs& a, hipStream_t s)

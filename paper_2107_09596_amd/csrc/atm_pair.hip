@@ -1,0 +1,611 @@
+// FP32-fine / FP64-residual relaxation sweeps (precision 1) on 2D grids beyond the on-chip strip
+// layout, with two CUs per coarse interval.
+//
+// The CG state of one fine step of a 256 x 256 grid (x, r, p and M p in FP32: 1 MB) does not fit
+// on one CU (512 KB of registers, 160 KB of LDS), so each interval is taken by a pair of 512-thread
+// workgroups, each owning half of the rows: x, r and M p of its half in registers (a thread holds
+// R consecutive rows of one column), the search direction p of its half in LDS with one ghost row
+// above and below.  128 intervals then use all 256 CUs.
+//
+// The two halves meet once per CG iteration.  After the stencil pass each half publishes, through
+// a mailbox in global memory, three partial sums -- (p, M p), (r, M p), (M p, M p) -- and the true
+// (r, r) of its current residual, plus its first and last rows of r and its first two and last two
+// rows of p.  From these, both halves form the same step lengths (the sums are added in the order
+// half 0, half 1), the new residual norm by (r - a q, r - a q) = (r, r) - 2 a (r, q) + a^2 (q, q),
+// and each half recomputes its partner's boundary rows of the new p with the same expressions the
+// partner evaluates: the ghost rows of the next iteration need no second exchange.  The mathematics
+// is plain CG (the iterates of Jacobi-PCG with the constant diagonal); only the grouping of the
+// sums and the residual-norm recurrence differ from the one-workgroup solver.
+//
+// Handshake: the mailbox rows and sums are written with device-coherent stores (they bypass the
+// non-coherent caches), every thread waits for its stores to complete, the workgroup synchronises,
+// and one thread raises the half's epoch counter; the partner polls that counter with coherent
+// loads and then reads the mailbox the same way.  Every wait is bounded: a half that waits longer
+// than the spin cap sets the header's pair-timeout flag and leaves, and its partner then times out
+// too, so the kernel always ends.  The grid is launched cooperatively (every workgroup resident),
+// pairs sit on one XCD (blocks b and b ^ 8), and each pair takes intervals pair, pair + pairs, ...
+#include "atm_device.hpp"
+#include "atm_kernels.hpp"
+
+namespace atm {
+namespace pair {
+
+constexpr int kThreads = 512;
+constexpr int kWaves = kThreads / 64;
+constexpr int kParts = 4;  // (p, q), (r, q), (q, q), (r, r)
+constexpr int kTimeoutFlag = kFailPairTimeout;
+
+// floats of the boundary packs of one half: first rows (r, p, p of the next row) and last rows (r, p,
+// p of the row before), NX each, plus a spare row for the row groups between them, padded to a
+// multiple of the workgroup so that every thread copies the same number
+constexpr int pack_floats(int nx) { return (7 * nx + kThreads - 1) / kThreads * kThreads; }
+
+struct PairArgs {
+    unsigned* epoch;  // [pairs][2] handshake counters, zero before the launch
+    float* mail;      // [2 parities][pairs][2 halves][slot] mailbox
+    int pairs;        // workgroup pairs in the grid (a multiple of 8)
+    int slot;         // floats per mailbox slot: pack_floats(NX), then kParts doubles
+    int spin_cap;     // polls of the partner's counter before giving up
+};
+
+__device__ __forceinline__ void put(float* p, float v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float get(const float* p)
+{
+    return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void put(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double get(const double* p)
+{
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A 32-bit offset hidden from the optimiser, so that the row offsets of the unrolled strip loops are
+// recomputed where they are used instead of being hoisted out of the time loop (one register each);
+// a load is then a uniform base plus one offset register.
+__device__ __forceinline__ uint32_t opq(uint32_t v)
+{
+    __asm__ volatile("" : "+v"(v));
+    return v;
+}
+
+// No instruction; memory accesses are not moved across it by the compiler.  Placed every few rows
+// of the unrolled strip passes so that the loads of all rows are not issued at once (they would
+// hold one register each).
+__device__ __forceinline__ void row_fence() { __asm__ volatile("" ::: "memory"); }
+
+// a value every lane of the wave holds alike, kept in scalar registers
+__device__ __forceinline__ float uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uniform(double v)
+{
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// this thread's stores (and loads) have completed
+__device__ __forceinline__ void drain()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+}
+
+// The FP32 step operator at one point: M v = d v - cx (w + e) - cy (up + dn).  Both halves
+// evaluate every boundary point through this one expression.
+__device__ __forceinline__ float stencil32(float d, float cx, float cy, float up, float cen, float dn, float w, float e)
+{
+    return d * cen - cx * (w + e) - cy * (up + dn);
+}
+
+// one CG update at a point: r' = r - a q, p' = r' + b p
+__device__ __forceinline__ void cg_update(float a, float b, float q, float p, float& r, float& pn)
+{
+    r = r - a * q;
+    pn = r + b * p;
+}
+
+// Sum kParts doubles over the workgroup (wave sums, then the 16 wave totals in a fixed order).
+// Every thread returns the totals.
+__device__ __forceinline__ void block_sum4(double (&v)[kParts], double* red, int& slot)
+{
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int q = 0; q < kParts; ++q) v[q] = wave_sum(v[q]);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double* base = red + slot * kParts * kWaves;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < kParts; ++q) base[q * kWaves + wave] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kParts; ++q) {
+        double s = 0.0;
+        for (int w = 0; w < kWaves; ++w) s += base[q * kWaves + w];
+        v[q] = s;
+    }
+    slot ^= 1;
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// The per-launch constants of one half.
+template <int NX, int R>
+struct Half {
+    static constexpr int G = kThreads / NX;  // row groups of a half
+    static constexpr int H = G * R;          // rows of a half
+    int x, g, half, pair;
+    int xw, xe;         // west / east columns (-1: zero boundary)
+    int row0;           // first global row of this thread
+    bool top_ghost, bot_ghost;  // the ghost row above / below the half comes from the partner
+    bool periodic;
+};
+
+// v at global row Y (wrapped on the periodic grid, zero beyond a Dirichlet edge), column x
+template <int NX, int R>
+__device__ __forceinline__ double row_val(const double* v, const Half<NX, R>& h, int Y, int x)
+{
+    constexpr int ny = 2 * Half<NX, R>::H;
+    if (Y < 0 || Y >= ny) {
+        if (!h.periodic) return 0.0;
+        Y = Y < 0 ? Y + ny : Y - ny;
+    }
+    return v[opq((uint32_t)Y * NX + x)];
+}
+
+// Offsets into one slice of the rows of a thread (column x, rows row0 .. row0+R-1) and of their
+// neighbours.  The base is hidden from the optimiser where a pass starts, so the row offsets are
+// recomputed there (one add each) rather than held in registers across the time loop.
+template <int NX, int R>
+struct StripOff {
+    uint32_t c;        // row0 * NX + x
+    int dw, de;        // west / east neighbour relative to c (0 for a Dirichlet edge, masked)
+    uint32_t up, dn;   // the rows above the first and below the last row (wrapped; masked if absent)
+    bool wm, em, um, dm;
+    __device__ __forceinline__ StripOff(const Half<NX, R>& h)
+    {
+        constexpr int ny = 2 * Half<NX, R>::H;
+        c = opq((uint32_t)h.row0 * NX + (uint32_t)h.x);
+        wm = h.xw >= 0;
+        em = h.xe >= 0;
+        dw = wm ? h.xw - h.x : 0;
+        de = em ? h.xe - h.x : 0;
+        const int yu = h.row0 - 1, yd = h.row0 + R;
+        um = yu >= 0 || h.periodic;
+        dm = yd < ny || h.periodic;
+        up = (uint32_t)((yu < 0 ? yu + ny : yu) * NX + h.x);
+        dn = (uint32_t)((yd >= ny ? yd - ny : yd) * NX + h.x);
+        if (!um) up = c;
+        if (!dm) dn = c;
+    }
+};
+
+// the partner's mailbox slot of handshake k and the packs in it: first rows (r, p, p of the next
+// row), last rows (r, p, p of the row before)
+__device__ __forceinline__ const float* partner_slot(const PairArgs& pa, int pair, int half, unsigned k)
+{
+    return pa.mail + ((size_t)((k & 1) * pa.pairs + pair) * 2 + (half ^ 1)) * pa.slot;
+}
+__device__ __forceinline__ float* own_slot(const PairArgs& pa, int pair, int half, unsigned k)
+{
+    return pa.mail + ((size_t)((k & 1) * pa.pairs + pair) * 2 + half) * pa.slot;
+}
+
+// Exchange the partial sums and wait for the partner.  The caller has written its mailbox rows.
+// Returns false (all threads) if the partner did not arrive within the spin cap.
+template <int NX, int R>
+__device__ __forceinline__ bool handshake(const PairArgs& pa, const Half<NX, R>& h, unsigned k, double (&tot)[kParts],
+                                          double* red, int& slot, double (*parts)[kParts], int* flag, float* Pk)
+{
+    constexpr int PK = pack_floats(NX);
+    // the packs staged in Pk go to the mailbox (every thread copies its share; its stores are drained)
+    __syncthreads();
+    {
+        float* ms = own_slot(pa, h.pair, h.half, k);
+#pragma unroll
+        for (int q = 0; q < PK / kThreads; ++q) put(ms + q * kThreads + threadIdx.x, Pk[q * kThreads + threadIdx.x]);
+    }
+    drain();
+    block_sum4(tot, red, slot);  // its barrier follows every thread's drain
+    // wave 0 publishes and waits, all its lanes alike (same addresses, same values): a branch taken by
+    // whole waves, so the rest of the kernel sees no divergent control flow here
+    if (__builtin_amdgcn_readfirstlane(threadIdx.x) < 64) {
+        const int par = k & 1;
+        double* mine = reinterpret_cast<double*>(pa.mail + ((size_t)(par * pa.pairs + h.pair) * 2 + h.half) * pa.slot + PK);
+        const double* theirs = reinterpret_cast<const double*>(
+            pa.mail + ((size_t)(par * pa.pairs + h.pair) * 2 + (h.half ^ 1)) * pa.slot + PK);
+#pragma unroll
+        for (int q = 0; q < kParts; ++q) put(mine + q, tot[q]);
+        drain();
+        __hip_atomic_store(pa.epoch + 2 * h.pair + h.half, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the decision and the values are taken from one lane, so the wave agrees on them
+        int ok = 0;
+        for (int spin = 0; spin < pa.spin_cap; ++spin) {
+            const unsigned seen = (unsigned)__builtin_amdgcn_readfirstlane(
+                (int)__hip_atomic_load(pa.epoch + 2 * h.pair + (h.half ^ 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (seen >= k) {
+                ok = 1;
+                break;
+            }
+        }
+        if (ok) {
+#pragma unroll
+            for (int q = 0; q < kParts; ++q) {
+                parts[h.half][q] = tot[q];
+                parts[h.half ^ 1][q] = uniform(get(theirs + q));
+            }
+        }
+        *flag = ok;
+    }
+    __syncthreads();
+    if (!*flag) return false;
+#pragma unroll
+    for (int q = 0; q < kParts; ++q) tot[q] = parts[0][q] + parts[1][q];
+    // the partner's packs replace this half's in Pk
+    {
+        const float* ps = partner_slot(pa, h.pair, h.half, k);
+#pragma unroll
+        for (int q = 0; q < PK / kThreads; ++q) Pk[q * kThreads + threadIdx.x] = get(ps + q * kThreads + threadIdx.x);
+    }
+    __syncthreads();
+    return true;
+}
+
+template <int NX, int R>
+__global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, PairArgs pa)
+{
+    using HF = Half<NX, R>;
+    constexpr int G = HF::G, H = HF::H;
+    // p of the half in LDS: local rows 0 .. H+1 (0 and H+1 are the ghost rows from the partner), each
+    // of NX + 2 columns (columns 0 and NX+1: zero for Dirichlet, copies of the opposite edge when
+    // periodic), so that a thread's stencil reads are constant offsets from one base address
+    constexpr int PW = NX + 2;
+    constexpr int PK = pack_floats(NX);  // staged boundary packs: 6 rows of NX, padded to whole passes
+    __shared__ float P[(H + 3) * PW];    // row H+2: writes of the row groups without a ghost row
+    __shared__ float Pk[PK];             // this half's packs, then the partner's
+    __shared__ double red[2 * kParts * kWaves];
+    __shared__ double parts[2][kParts];
+    __shared__ int flag;
+    int slot = 0;
+
+    HF h;
+    h.x = threadIdx.x % NX;
+    h.g = threadIdx.x / NX;
+    h.half = (blockIdx.x >> 3) & 1;
+    h.pair = ((blockIdx.x >> 4) << 3) | (blockIdx.x & 7);
+    h.periodic = a.g.periodic != 0;
+    h.xw = h.x > 0 ? h.x - 1 : (h.periodic ? NX - 1 : -1);
+    h.xe = h.x < NX - 1 ? h.x + 1 : (h.periodic ? 0 : -1);
+    h.row0 = h.half * H + h.g * R;
+    h.top_ghost = h.periodic || h.half == 1;
+    h.bot_ghost = h.periodic || h.half == 0;
+    const int64_t n = a.n;
+    const StepCoef& c = a.fine;
+    const float d32 = (float)c.d, cx32 = (float)c.cx, cy32 = (float)c.cy;
+    const bool first_group = h.g == 0, last_group = h.g == G - 1;
+    float* const Pr = P + (h.g * R + 1) * PW + h.x + 1;  // this thread's first row
+    // its west and east neighbours through bases of their own, pointing at the wrapped column on the
+    // periodic grid and at the zero column 0 at a Dirichlet edge (opaque, so that the two reads of a
+    // row are not merged into one paired read, whose short offsets would need a base register per row)
+    const float* const Pw = P + opq((uint32_t)((h.g * R + 1) * PW + h.xw + 1));
+    const float* const Pe = P + opq((uint32_t)((h.g * R + 1) * PW + (h.xe >= 0 ? h.xe + 1 : 0)));
+    // where this thread's ghost-row value goes: above its first row (first group), below its last row
+    // (last group), else the spare row H+2; and its pack rows (first group: r, p, p of rows 0 and 1;
+    // last group: r, p, p of rows R-1 and R-2; other groups: the spare pack row 6)
+    float* const Pg = first_group ? Pr - PW : (last_group ? Pr + R * PW : P + (H + 2) * PW + h.x + 1);
+    const int pk0 = first_group ? h.x : (last_group ? 3 * NX + h.x : 6 * NX + h.x);
+    const int pk_step = (first_group || last_group) ? NX : 0;
+    const int prow_a = last_group ? (R - 1) * PW : 0, prow_b = last_group ? (R - 2) * PW : PW;
+    unsigned k = 0;  // handshakes so far
+    long long its_total = 0;
+    bool alive = true;
+
+    for (int q = threadIdx.x; q < (H + 2) * PW; q += kThreads) P[q] = 0.0f;
+    __syncthreads();
+
+    float xv[R], rv[R];
+
+    for (int64_t j = h.pair; j <= a.NT && alive; j += pa.pairs) {
+        const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
+        // the starting value c_j (written to u_{jm} in modes 1 and 2) and the defect of the first step
+        // rho_1 = psi(c_j) - M s_1, s_1 the value stored at the first point of the interval
+        const double* xo = a.u + (j * a.m + 1) * n;  // s_t of the next step (valid while total >= 1)
+        {
+            double* uc = a.u + (j * a.m) * n;
+            const double* ax = (a.mode != 0 && a.aux) ? a.aux + j * n : nullptr;
+            const bool use_aux = a.mode == 1 || (a.mode == 2 && j > 0);
+            if (total >= 1) {
+                const StripOff<NX, R> so(h);
+                const double s_up0 = xo[so.up], s_dn_last = xo[so.dn];  // both addresses valid
+                double s_up = so.um ? s_up0 : 0.0, s_cen = xo[so.c];
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const uint32_t o = so.c + (uint32_t)(i * NX);
+                    const double cu = uc[o];
+                    const double c0 = !use_aux ? cu : (a.mode == 1 ? cu + ax[o] : ax[o]);
+                    if (a.mode != 0) uc[o] = c0;
+                    const double s_dn = i < R - 1 ? xo[o + NX] : (so.dm ? s_dn_last : 0.0);
+                    const double wr = xo[o + so.dw], er = xo[o + so.de];
+                    const double w = so.wm ? wr : 0.0, e = so.em ? er : 0.0;
+                    rv[i] = (float)(explicit_part(c, c0) - stencil_value(c, s_up, s_cen, s_dn, w, e));
+                    s_up = s_cen;
+                    s_cen = s_dn;
+                    if ((i & 1) == 1) row_fence();
+                }
+            } else if (a.mode != 0) {
+                const uint32_t c0off = opq((uint32_t)h.row0 * NX + (uint32_t)h.x);
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const uint32_t o = c0off + (uint32_t)(i * NX);
+                    const double cu = uc[o];
+                    uc[o] = !use_aux ? cu : (a.mode == 1 ? cu + ax[o] : ax[o]);
+                }
+            }
+        }
+        for (int64_t t = 1; t <= total && alive; ++t) {
+            // ---- FP32 CG for M d = rho from d = 0: x = 0, p = r ----
+            double rr_part = 0.0;  // this thread's share of (r, r) of the current residual
+            {
+                float chunk = 0.0f;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    xv[i] = 0.0f;
+                    Pr[i * PW] = rv[i];
+                    chunk += rv[i] * rv[i];
+                    if ((i & 7) == 7 || i == R - 1) {
+                        rr_part += (double)chunk;
+                        chunk = 0.0f;
+                    }
+                }
+            }
+            ++k;
+            {
+                const float ra = last_group ? rv[R - 1] : rv[0], rb = last_group ? rv[R - 2] : rv[1];
+                Pk[pk0] = ra;
+                Pk[pk0 + pk_step] = ra;
+                Pk[pk0 + 2 * pk_step] = rb;
+            }
+            double tot[kParts] = {0.0, 0.0, 0.0, rr_part};
+            if (!handshake<NX, R>(pa, h, k, tot, red, slot, parts, &flag, Pk)) {
+                alive = false;
+                break;
+            }
+            {
+                // ghost rows of p = r: the partner's last row above, its first row below
+                const bool from_partner = first_group ? h.top_ghost : h.bot_ghost;
+                const float v = Pk[first_group ? 4 * NX + h.x : NX + h.x];
+                *Pg = from_partner ? v : 0.0f;
+            }
+            __syncthreads();
+            const double bb = tot[3];
+            const double thresh = a.rtol2_mixed * bb;
+            int it = 0;
+            bool converged = !(bb > thresh);  // b = 0 (d = 0 is exact), or a tolerance that b meets
+            while (!converged && it < a.maxit) {
+                // pass 1: the partial sums of q = M p (q is formed again in pass 2)
+                double sums[kParts] = {0.0, 0.0, 0.0, rr_part};
+                {
+                    float cpq = 0.0f, crq = 0.0f, cqq = 0.0f;
+                    float up = Pr[-PW], cen = Pr[0];
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        const float dn = Pr[(i + 1) * PW];
+                        const float q = stencil32(d32, cx32, cy32, up, cen, dn, Pw[i * PW], Pe[i * PW]);
+                        cpq += cen * q;
+                        crq += rv[i] * q;
+                        cqq += q * q;
+                        if ((i & 7) == 7 || i == R - 1) {
+                            sums[0] += (double)cpq;
+                            sums[1] += (double)crq;
+                            sums[2] += (double)cqq;
+                            cpq = crq = cqq = 0.0f;
+                        }
+                        up = cen;
+                        cen = dn;
+                        if ((i & 3) == 3) row_fence();
+                    }
+                }
+                // the boundary packs: r and p before the update
+                Pk[pk0] = last_group ? rv[R - 1] : rv[0];
+                Pk[pk0 + pk_step] = Pr[prow_a];
+                Pk[pk0 + 2 * pk_step] = Pr[prow_b];
+                ++k;
+                if (!handshake<NX, R>(pa, h, k, sums, red, slot, parts, &flag, Pk)) {
+                    alive = false;
+                    break;
+                }
+                const double rr = uniform(sums[3]);
+                const double alpha = uniform(rr / sums[0]);
+                const double rr_new = uniform(rr - 2.0 * alpha * sums[1] + alpha * alpha * sums[2]);
+                const double beta = rr_new / rr;
+                const float a32 = uniform((float)alpha), b32 = uniform((float)beta);
+                // the partner's boundary rows of the new p, as the partner computes them (written to the
+                // ghost rows after every thread has formed its q from the old ones)
+                // the partner's boundary row next to this thread's group, as the partner computes it:
+                // above the first group the partner's last row (its r and p, the row before it, and this
+                // half's first row below it), below the last group its first row (this half's last row
+                // above it, the row after it below)
+                float ghost;
+                {
+                    const bool top = first_group;
+                    const int o = top ? 3 * NX : 0;
+                    const float r0 = Pk[o + h.x], p0 = Pk[o + NX + h.x], p1 = Pk[o + 2 * NX + h.x];
+                    const float wr = Pk[o + NX + (h.xw >= 0 ? h.xw : h.x)];
+                    const float er = Pk[o + NX + (h.xe >= 0 ? h.xe : h.x)];
+                    const float w = h.xw >= 0 ? wr : 0.0f, e = h.xe >= 0 ? er : 0.0f;
+                    const float own = top ? Pr[0] : Pr[(R - 1) * PW];
+                    const float q = top ? stencil32(d32, cx32, cy32, p1, p0, own, w, e)
+                                        : stencil32(d32, cx32, cy32, own, p0, p1, w, e);
+                    float r = r0;
+                    cg_update(a32, b32, q, p0, r, ghost);
+                    if (!(top ? h.top_ghost : h.bot_ghost)) ghost = 0.0f;
+                }
+                // pass 2: q = M p again; x += a p, r -= a q, and this thread's share of the new (r, r)
+                {
+                    float crr = 0.0f;
+                    rr_part = 0.0;
+                    float up = Pr[-PW], cen = Pr[0];
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        const float dn = Pr[(i + 1) * PW];
+                        const float q = stencil32(d32, cx32, cy32, up, cen, dn, Pw[i * PW], Pe[i * PW]);
+                        xv[i] = xv[i] + a32 * cen;
+                        float unused;
+                        cg_update(a32, b32, q, cen, rv[i], unused);
+                        crr += rv[i] * rv[i];
+                        if ((i & 7) == 7 || i == R - 1) {
+                            rr_part += (double)crr;
+                            crr = 0.0f;
+                        }
+                        up = cen;
+                        cen = dn;
+                        if ((i & 3) == 3) row_fence();
+                    }
+                }
+                __syncthreads();
+                // pass 3: p = r + b p, the periodic copies and the ghost rows
+                {
+#pragma unroll
+                    for (int i = 0; i < R; ++i) {
+                        Pr[i * PW] = rv[i] + b32 * Pr[i * PW];
+                        if ((i & 7) == 7) row_fence();
+                    }
+                    *Pg = ghost;
+                }
+                __syncthreads();
+                ++it;
+                converged = !(rr_new > thresh);
+            }
+            if (!alive) break;
+            its_total += it;
+            if (!converged) atomicOr(a.fail, 1);
+            // ---- v_t = s_t + d in FP64; the defect of the next step ----
+            const bool ystep = (t == a.m);
+            const double* so = xo;
+            double* dst = ystep ? a.y + (j + 1) * n : a.u + (j * a.m + t) * n;
+            const double* xn = nullptr;
+            if (t < total) {
+                xn = (t + 1 < a.m) ? a.u + (j * a.m + t + 1) * n
+                                   : (a.mode == 0 ? a.u + ((j + 1) * a.m) * n : (a.mode == 1 ? a.y : a.aux) + (j + 1) * n);
+                const StripOff<NX, R> so_(h);
+                const double s_up0 = xn[so_.up], s_dn_last = xn[so_.dn];  // both addresses valid
+                double s_up = so_.um ? s_up0 : 0.0, s_cen = xn[so_.c];
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const uint32_t o = so_.c + (uint32_t)(i * NX);
+                    const double v = so[o] + (double)xv[i];
+                    dst[o] = v;
+                    const double s_dn = i < R - 1 ? xn[o + NX] : (so_.dm ? s_dn_last : 0.0);
+                    const double wr = xn[o + so_.dw], er = xn[o + so_.de];
+                    const double w = so_.wm ? wr : 0.0, e = so_.em ? er : 0.0;
+                    rv[i] = (float)(explicit_part(c, v) - stencil_value(c, s_up, s_cen, s_dn, w, e));
+                    s_up = s_cen;
+                    s_cen = s_dn;
+                    if ((i & 1) == 1) row_fence();
+                }
+            } else {
+                const uint32_t c0off = opq((uint32_t)h.row0 * NX + (uint32_t)h.x);
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const uint32_t o = c0off + (uint32_t)(i * NX);
+                    dst[o] = so[o] + (double)xv[i];
+                }
+            }
+            xo = xn;
+        }
+    }
+    if (!alive && threadIdx.x == 0) atomicOr(a.fail, kTimeoutFlag);
+    if (h.half == 0) count_cg(a, its_total);
+}
+
+__global__ void clear_epochs_kernel(unsigned* epoch, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) epoch[i] = 0u;
+}
+
+}  // namespace pair
+}  // namespace atm
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+namespace atm {
+
+namespace {
+
+constexpr int kSpinCap = 1 << 21;  // polls of the partner's counter (about a second) before giving up
+
+struct PairShape {
+    void* fn;  // the kernel instantiation, null when the grid has none
+};
+
+// the instantiation for an nx x ny grid: two halves of ny/2 rows, 512 / nx row groups of R rows
+PairShape pair_shape(int nx, int ny)
+{
+    PairShape p{nullptr};
+    if (ny % 2) return p;
+    const int half = ny / 2;
+    if (nx == 256 && half == 128) p.fn = (void*)pair::sweep_pair_mixed_kernel<256, 64>;
+    if (nx == 256 && half == 64) p.fn = (void*)pair::sweep_pair_mixed_kernel<256, 32>;
+    if (nx == 128 && half == 128) p.fn = (void*)pair::sweep_pair_mixed_kernel<128, 32>;
+    return p;
+}
+
+// resident workgroups of an instantiation on the current device (0 if it cannot run)
+int resident_blocks(void* fn)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), pair::kThreads, 0) !=
+        hipSuccess)
+        return 0;
+    return per_cu * cus;
+}
+
+}  // namespace
+
+int sweep_pair_pairs(const KArgs& a, int64_t n_tasks)
+{
+    const PairShape ps = pair_shape(a.g.nx, a.g.ny);
+    if (!ps.fn || !a.large || a.is1d) return 0;
+    const int resident = resident_blocks(ps.fn);
+    int pairs = (resident / 2) / 8 * 8;
+    const int64_t want = (n_tasks + 7) / 8 * 8;
+    if (pairs > want) pairs = (int)want;
+    if (pairs < 8) return 0;
+    // epochs and the mailbox in the large-grid scratch (free while the sweep runs)
+    const size_t slot = ((size_t)pair::pack_floats(a.g.nx) + 2 * pair::kParts + 63) / 64 * 64;
+    const size_t need = 256 + (size_t)pairs * 2 * sizeof(unsigned) + 2 * (size_t)pairs * 2 * slot * sizeof(float);
+    const size_t have = (size_t)(a.NT + 1) * 5 * (size_t)a.n * sizeof(double);
+    return need <= have ? pairs : 0;
+}
+
+hipError_t launch_sweep_pair(const KArgs& a, int pairs, hipStream_t s)
+{
+    const PairShape ps = pair_shape(a.g.nx, a.g.ny);
+    pair::PairArgs pa;
+    pa.pairs = pairs;
+    pa.slot = (int)(((size_t)pair::pack_floats(a.g.nx) + 2 * pair::kParts + 63) / 64 * 64);
+    pa.spin_cap = kSpinCap;
+    pa.epoch = reinterpret_cast<unsigned*>(a.large_scratch);
+    pa.mail = reinterpret_cast<float*>(reinterpret_cast<char*>(a.large_scratch) +
+                                       ((size_t)pairs * 2 * sizeof(unsigned) + 255) / 256 * 256);
+    hipLaunchKernelGGL(pair::clear_epochs_kernel, dim3(1), dim3(256), 0, s, pa.epoch, 2 * pairs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    KArgs ka = a;
+    void* args[] = {&ka, &pa};
+    return hipLaunchCooperativeKernel(ps.fn, dim3(2 * pairs), dim3(pair::kThreads), args, 0, s);
+}
+
+}  // namespace atm
