@@ -203,17 +203,10 @@ __device__ __forceinline__ float* own_slot(const PairArgs& pa, int pair, int hal
 // Returns false (all threads) if the partner did not arrive within the spin cap.
 template <int NX, int R>
 __device__ __forceinline__ bool handshake(const PairArgs& pa, const Half<NX, R>& h, unsigned k, double (&tot)[kParts],
-                                          double* red, int& slot, double (*parts)[kParts], int* flag, float* Pk)
+                                          double* red, int& slot, double (*parts)[kParts], int* flag)
 {
     constexpr int PK = pack_floats(NX);
-    // the packs staged in Pk go to the mailbox (every thread copies its share; its stores are drained)
-    __syncthreads();
-    {
-        float* ms = own_slot(pa, h.pair, h.half, k);
-#pragma unroll
-        for (int q = 0; q < PK / kThreads; ++q) put(ms + q * kThreads + threadIdx.x, Pk[q * kThreads + threadIdx.x]);
-    }
-    drain();
+    drain();  // this thread's pack stores
     block_sum4(tot, red, slot);  // its barrier follows every thread's drain
     // wave 0 publishes and waits, all its lanes alike (same addresses, same values): a branch taken by
     // whole waves, so the rest of the kernel sees no divergent control flow here
@@ -249,13 +242,6 @@ __device__ __forceinline__ bool handshake(const PairArgs& pa, const Half<NX, R>&
     if (!*flag) return false;
 #pragma unroll
     for (int q = 0; q < kParts; ++q) tot[q] = parts[0][q] + parts[1][q];
-    // the partner's packs replace this half's in Pk
-    {
-        const float* ps = partner_slot(pa, h.pair, h.half, k);
-#pragma unroll
-        for (int q = 0; q < PK / kThreads; ++q) Pk[q * kThreads + threadIdx.x] = get(ps + q * kThreads + threadIdx.x);
-    }
-    __syncthreads();
     return true;
 }
 
@@ -268,9 +254,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
     // of NX + 2 columns (columns 0 and NX+1: zero for Dirichlet, copies of the opposite edge when
     // periodic), so that a thread's stencil reads are constant offsets from one base address
     constexpr int PW = NX + 2;
-    constexpr int PK = pack_floats(NX);  // staged boundary packs: 6 rows of NX, padded to whole passes
-    __shared__ float P[(H + 3) * PW];    // row H+2: writes of the row groups without a ghost row
-    __shared__ float Pk[PK];             // this half's packs, then the partner's
+    __shared__ float P[(H + 3) * PW];  // row H+2: writes of the row groups without a ghost row
     __shared__ double red[2 * kParts * kWaves];
     __shared__ double parts[2][kParts];
     __shared__ int flag;
@@ -299,7 +283,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
     const float* const Pe = P + opq((uint32_t)((h.g * R + 1) * PW + (h.xe >= 0 ? h.xe + 1 : 0)));
     // where this thread's ghost-row value goes: above its first row (first group), below its last row
     // (last group), else the spare row H+2; and its pack rows (first group: r, p, p of rows 0 and 1;
-    // last group: r, p, p of rows R-1 and R-2; other groups: the spare pack row 6)
+    // last group: r, p, p of rows R-1 and R-2; other groups: the spare pack row 6 of the mailbox slot)
     float* const Pg = first_group ? Pr - PW : (last_group ? Pr + R * PW : P + (H + 2) * PW + h.x + 1);
     const int pk0 = first_group ? h.x : (last_group ? 3 * NX + h.x : 6 * NX + h.x);
     const int pk_step = (first_group || last_group) ? NX : 0;
@@ -311,7 +295,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
     for (int q = threadIdx.x; q < (H + 2) * PW; q += kThreads) P[q] = 0.0f;
     __syncthreads();
 
-    float xv[R], rv[R];
+    float xv[R], rv[R], qv[R];
 
     for (int64_t j = h.pair; j <= a.NT && alive; j += pa.pairs) {
         const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
@@ -368,20 +352,22 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
             }
             ++k;
             {
+                float* ms = own_slot(pa, h.pair, h.half, k) + pk0;
                 const float ra = last_group ? rv[R - 1] : rv[0], rb = last_group ? rv[R - 2] : rv[1];
-                Pk[pk0] = ra;
-                Pk[pk0 + pk_step] = ra;
-                Pk[pk0 + 2 * pk_step] = rb;
+                put(ms, ra);
+                put(ms + pk_step, ra);
+                put(ms + 2 * pk_step, rb);
             }
             double tot[kParts] = {0.0, 0.0, 0.0, rr_part};
-            if (!handshake<NX, R>(pa, h, k, tot, red, slot, parts, &flag, Pk)) {
+            if (!handshake<NX, R>(pa, h, k, tot, red, slot, parts, &flag)) {
                 alive = false;
                 break;
             }
             {
                 // ghost rows of p = r: the partner's last row above, its first row below
+                const float* ps = partner_slot(pa, h.pair, h.half, k);
                 const bool from_partner = first_group ? h.top_ghost : h.bot_ghost;
-                const float v = Pk[first_group ? 4 * NX + h.x : NX + h.x];
+                const float v = get(ps + (first_group ? 4 * NX : NX) + h.x);
                 *Pg = from_partner ? v : 0.0f;
             }
             __syncthreads();
@@ -390,7 +376,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
             int it = 0;
             bool converged = !(bb > thresh);  // b = 0 (d = 0 is exact), or a tolerance that b meets
             while (!converged && it < a.maxit) {
-                // pass 1: the partial sums of q = M p (q is formed again in pass 2)
+                // pass 1: q = M p and the partial sums
                 double sums[kParts] = {0.0, 0.0, 0.0, rr_part};
                 {
                     float cpq = 0.0f, crq = 0.0f, cqq = 0.0f;
@@ -399,6 +385,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                     for (int i = 0; i < R; ++i) {
                         const float dn = Pr[(i + 1) * PW];
                         const float q = stencil32(d32, cx32, cy32, up, cen, dn, Pw[i * PW], Pe[i * PW]);
+                        qv[i] = q;
                         cpq += cen * q;
                         crq += rv[i] * q;
                         cqq += q * q;
@@ -414,11 +401,14 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                     }
                 }
                 // the boundary packs: r and p before the update
-                Pk[pk0] = last_group ? rv[R - 1] : rv[0];
-                Pk[pk0 + pk_step] = Pr[prow_a];
-                Pk[pk0 + 2 * pk_step] = Pr[prow_b];
+                {
+                    float* ms = own_slot(pa, h.pair, h.half, k + 1) + pk0;
+                    put(ms, last_group ? rv[R - 1] : rv[0]);
+                    put(ms + pk_step, Pr[prow_a]);
+                    put(ms + 2 * pk_step, Pr[prow_b]);
+                }
                 ++k;
-                if (!handshake<NX, R>(pa, h, k, sums, red, slot, parts, &flag, Pk)) {
+                if (!handshake<NX, R>(pa, h, k, sums, red, slot, parts, &flag)) {
                     alive = false;
                     break;
                 }
@@ -436,10 +426,10 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                 float ghost;
                 {
                     const bool top = first_group;
-                    const int o = top ? 3 * NX : 0;
-                    const float r0 = Pk[o + h.x], p0 = Pk[o + NX + h.x], p1 = Pk[o + 2 * NX + h.x];
-                    const float wr = Pk[o + NX + (h.xw >= 0 ? h.xw : h.x)];
-                    const float er = Pk[o + NX + (h.xe >= 0 ? h.xe : h.x)];
+                    const float* ps = partner_slot(pa, h.pair, h.half, k) + (top ? 3 * NX : 0);
+                    const float r0 = get(ps + h.x), p0 = get(ps + NX + h.x), p1 = get(ps + 2 * NX + h.x);
+                    const float wr = get(ps + NX + (h.xw >= 0 ? h.xw : h.x));
+                    const float er = get(ps + NX + (h.xe >= 0 ? h.xe : h.x));
                     const float w = h.xw >= 0 ? wr : 0.0f, e = h.xe >= 0 ? er : 0.0f;
                     const float own = top ? Pr[0] : Pr[(R - 1) * PW];
                     const float q = top ? stencil32(d32, cx32, cy32, p1, p0, own, w, e)
@@ -448,34 +438,23 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                     cg_update(a32, b32, q, p0, r, ghost);
                     if (!(top ? h.top_ghost : h.bot_ghost)) ghost = 0.0f;
                 }
-                // pass 2: q = M p again; x += a p, r -= a q, and this thread's share of the new (r, r)
+                // pass 2: x += a p, r -= a q, p = r + b p (each thread reads and writes only its own points
+                // of p), this thread's share of the new (r, r), and the ghost rows
                 {
                     float crr = 0.0f;
                     rr_part = 0.0;
-                    float up = Pr[-PW], cen = Pr[0];
 #pragma unroll
                     for (int i = 0; i < R; ++i) {
-                        const float dn = Pr[(i + 1) * PW];
-                        const float q = stencil32(d32, cx32, cy32, up, cen, dn, Pw[i * PW], Pe[i * PW]);
-                        xv[i] = xv[i] + a32 * cen;
-                        float unused;
-                        cg_update(a32, b32, q, cen, rv[i], unused);
+                        const float pc = Pr[i * PW];
+                        xv[i] = xv[i] + a32 * pc;
+                        float pn;
+                        cg_update(a32, b32, qv[i], pc, rv[i], pn);
+                        Pr[i * PW] = pn;
                         crr += rv[i] * rv[i];
                         if ((i & 7) == 7 || i == R - 1) {
                             rr_part += (double)crr;
                             crr = 0.0f;
                         }
-                        up = cen;
-                        cen = dn;
-                        if ((i & 3) == 3) row_fence();
-                    }
-                }
-                __syncthreads();
-                // pass 3: p = r + b p, the periodic copies and the ghost rows
-                {
-#pragma unroll
-                    for (int i = 0; i < R; ++i) {
-                        Pr[i * PW] = rv[i] + b32 * Pr[i * PW];
                         if ((i & 7) == 7) row_fence();
                     }
                     *Pg = ghost;
