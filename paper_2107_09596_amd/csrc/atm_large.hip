@@ -397,9 +397,106 @@ __device__ __forceinline__ void gemm_f64(const double* __restrict__ A, int lda, 
     }
 }
 
-// one Psi substep w <- M^-1 psi(w) (coarse coefficients) by the eigenbasis solve; t0, t1 scratch
+// The same product for M and K multiples of 64 and N = 64 NT (NT <= 4), MFMA-bound: 64-row blocks of
+// C, each computed by 16 waves (wave w: the 16 rows 16 (w / 4) .. of the block and the N / 4 columns
+// (w % 4) N / 4 .., NT tiles of 16 x 16), over k-chunks of 16 whose A block ([k][row], pitch kAP) and B
+// rows ([k][col], pitch kBP) are staged in LDS, two buffers: the next chunk's loads are in flight
+// while the current chunk's MFMAs run.  The k order of every output's sum is that of gemm_f64.
+constexpr int kKC = 16;
+constexpr int kAP = 64 + 2;
+constexpr int kBP = 256 + 2;
+constexpr int kGemmBuf = kKC * kAP + kKC * kBP;  // doubles of one buffer
+constexpr int kGemmLds = 2 * kGemmBuf;
+template <int NT, bool AT = false, typename F>
+__device__ __forceinline__ void gemm_f64_tiled(const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                               int ldb, double* __restrict__ C, int ldc, int M, int K, double* lds,
+                                               F&& epi)
+{
+    constexpr int N = 64 * NT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int rt = wave >> 2, cg = wave & 3;
+    const int nkc = K / kKC;
+    for (int i0 = 0; i0 < M; i0 += 64) {
+        f64x4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+        double ra, rb[NT];
+        // element of the A block and of the B rows this thread moves: A (k, row), B (k, col)
+        const int ak = AT ? (tid >> 6) : (tid & 15), ar = AT ? (tid & 63) : (tid >> 4);
+        auto load = [&](int k0) {
+            ra = AT ? A[(int64_t)(k0 + ak) * lda + i0 + ar] : A[(int64_t)(i0 + ar) * lda + k0 + ak];
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                const int e = tid + q * kBlockL;
+                rb[q] = B[(int64_t)(k0 + e / N) * ldb + e % N];
+            }
+        };
+        auto stage = [&](int buf) {
+            double* As = lds + buf * kGemmBuf;
+            double* Bs = As + kKC * kAP;
+            As[ak * kAP + ar] = ra;
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                const int e = tid + q * kBlockL;
+                Bs[(e / N) * kBP + e % N] = rb[q];
+            }
+        };
+        load(0);
+        stage(0);
+        __syncthreads();
+        for (int kc = 0; kc < nkc; ++kc) {
+            const int buf = kc & 1;
+            if (kc + 1 < nkc) load((kc + 1) * kKC);
+            const double* As = lds + buf * kGemmBuf;
+            const double* Bs = As + kKC * kAP;
+#pragma unroll
+            for (int q = 0; q < kKC / 4; ++q) {
+                const int k = 4 * q + lk;
+                const double fa = As[k * kAP + rt * 16 + li];
+#pragma unroll
+                for (int t = 0; t < NT; ++t) {
+                    const double fb = Bs[k * kBP + cg * (N / 4) + t * 16 + li];
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb, acc[t], 0, 0, 0);
+                }
+            }
+            if (kc + 1 < nkc) stage(buf ^ 1);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + rt * 16 + 4 * u + lk, j = cg * (N / 4) + t * 16 + li;
+                C[(int64_t)i * ldc + j] = epi(i, j, acc[t][u]);
+            }
+    }
+}
+
+// C = A B: the tiled product with NT column tiles per wave (N = 64 NT), or gemm_f64 for NT = 0
+template <int NT, bool AT = false, typename F>
+__device__ __forceinline__ void gemm_f64_any(const double* __restrict__ A, int lda, const double* __restrict__ B,
+                                             int ldb, double* __restrict__ C, int ldc, int M, int N, int K, double* lds,
+                                             F&& epi)
+{
+    if constexpr (NT > 0)
+        gemm_f64_tiled<NT, AT>(A, lda, B, ldb, C, ldc, M, K, lds, epi);
+    else
+        gemm_f64<AT>(A, lda, B, ldb, C, ldc, M, N, K, epi);
+}
+
+// the tiled products' column tiles per wave for an nx x ny grid (0: they do not apply)
+inline int spectral_nt(int nx, int ny)
+{
+    if (ny % 64 || nx % 64 || nx > 256) return 0;
+    return nx / 64 >= 2 ? nx / 64 : 0;
+}
+
+// one Psi substep w <- M^-1 psi(w) (coarse coefficients) by the eigenbasis solve; t0, t1 scratch; lds
+// (kGemmLds doubles) for the tiled products (NT > 0)
+template <int NT>
 __device__ __forceinline__ void spectral_step(const KArgs& a, const LCol& col, double* __restrict__ w,
-                                              double* __restrict__ t0, double* __restrict__ t1)
+                                              double* __restrict__ t0, double* __restrict__ t1, double* lds)
 {
     const Grid2D& g = a.g;
     const SpecTables T = spec_tables(a);
@@ -411,36 +508,39 @@ __device__ __forceinline__ void spectral_step(const KArgs& a, const LCol& col, d
         t0[i] = explicit_part(a.coarse, w[i]);
     }
     __syncthreads();
-    gemm_f64<true>(T.qy, ny, t0, nx, t1, nx, ny, nx, ny, same);  // Qy^T b (read through Qy)
+    gemm_f64_any<NT, true>(T.qy, ny, t0, nx, t1, nx, ny, nx, ny, lds, same);  // Qy^T b (read through Qy)
     __syncthreads();
     const double cx2 = 2.0 * a.coarse.cx, cy2 = 2.0 * a.coarse.cy;
-    gemm_f64(t1, nx, T.qx, nx, t0, nx, ny, nx, nx,           // (.. Qx) ./ mu
-             [&](int i, int j, double v) { return v / (1.0 + (cx2 * T.ex[j] + cy2 * T.ey[i])); });
+    gemm_f64_any<NT>(t1, nx, T.qx, nx, t0, nx, ny, nx, nx, lds,           // (.. Qx) ./ mu
+                 [&](int i, int j, double v) { return v / (1.0 + (cx2 * T.ex[j] + cy2 * T.ey[i])); });
     __syncthreads();
-    gemm_f64<true>(T.qyt, ny, t0, nx, t1, nx, ny, nx, ny, same); // Qy .. (read through Qy^T)
+    gemm_f64_any<NT, true>(T.qyt, ny, t0, nx, t1, nx, ny, nx, ny, lds, same); // Qy .. (read through Qy^T)
     __syncthreads();
-    gemm_f64(t1, nx, T.qxt, nx, w, nx, ny, nx, nx, same);    // .. Qx^T
+    gemm_f64_any<NT>(t1, nx, T.qxt, nx, w, nx, ny, nx, nx, lds, same);    // .. Qx^T
     __syncthreads();
 }
 
+template <int NT>
 __device__ __forceinline__ long long psi_large(const KArgs& a, const LCol& col, double* w, const LScratch& sc,
-                                               int64_t task, double* red, int& slot)
+                                               int64_t task, double* red, int& slot, double* lds)
 {
     long long its = 0;
     for (int q = 0; q < a.substeps; ++q) {
-        if (a.spectral)
-            spectral_step(a, col, w, sc.vec(task, 0), sc.vec(task, 1));
-        else
+        if (NT > 0 || a.spectral)
+            spectral_step<NT>(a, col, w, sc.vec(task, 0), sc.vec(task, 1), lds);
+        else if constexpr (NT == 0)
             its += step_large64(a, a.coarse, a.rtol2_coarse, col, w, sc.vec(task, 0), sc.vec(task, 1),
                                 sc.vec(task, 2), sc.vec(task, 3), red, slot);
     }
     return its;
 }
 
-// window p (linear or FAS form), FP64
+// window p (linear or FAS form), FP64; NT > 0: Psi in the eigenbasis by the tiled products
+template <int NT>
 __global__ __launch_bounds__(kBlockL) void coarse_large_kernel(KArgs a, LScratch sc)
 {
     __shared__ double red[4 * kWavesL];
+    __shared__ double gl[NT > 0 ? kGemmLds : 1];
     int slot = 0;
     const int64_t p = blockIdx.x;
     const int64_t s0 = p - a.k + 1 > 0 ? p - a.k + 1 : 0;
@@ -457,7 +557,7 @@ __global__ __launch_bounds__(kBlockL) void coarse_large_kernel(KArgs a, LScratch
     __syncthreads();
     long long its = 0;
     for (int64_t jj = s0 + 1; jj <= p; ++jj) {
-        its += psi_large(a, col, w, sc, p, red, slot);
+        its += psi_large<NT>(a, col, w, sc, p, red, slot, gl);
         FOR_ROWS(col, g, y)
         {
             const int64_t i = (int64_t)y * g.nx + col.x;
@@ -474,9 +574,11 @@ __global__ __launch_bounds__(kBlockL) void coarse_large_kernel(KArgs a, LScratch
 }
 
 // tau_j = (v_j - Psi(v_{j-1})) + r_j, one workgroup per j = 1..N_T
+template <int NT>
 __global__ __launch_bounds__(kBlockL) void tau_large_kernel(KArgs a, LScratch sc)
 {
     __shared__ double red[4 * kWavesL];
+    __shared__ double gl[NT > 0 ? kGemmLds : 1];
     int slot = 0;
     const int64_t j = blockIdx.x + 1;
     const Grid2D& g = a.g;
@@ -489,7 +591,7 @@ __global__ __launch_bounds__(kBlockL) void tau_large_kernel(KArgs a, LScratch sc
         w[i] = a.u[((j - 1) * a.m) * n + i];
     }
     __syncthreads();
-    const long long its = psi_large(a, col, w, sc, j, red, slot);
+    const long long its = psi_large<NT>(a, col, w, sc, j, red, slot, gl);
     FOR_ROWS(col, g, y)
     {
         const int64_t i = (int64_t)y * g.nx + col.x;
@@ -611,8 +713,24 @@ hipError_t launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipSt
 void launch_coarse_large(const KArgs& a, hipStream_t s)
 {
     if (a.spectral) launch_spectral_tables(a, s);
-    if (a.fas && a.NT >= 1) hipLaunchKernelGGL(tau_large_kernel, dim3(a.NT), dim3(kBlockL), 0, s, a, scratch_of(a));
-    hipLaunchKernelGGL(coarse_large_kernel, dim3(a.NT + 1), dim3(kBlockL), 0, s, a, scratch_of(a));
+    const int nt = a.spectral ? spectral_nt(a.g.nx, a.g.ny) : 0;
+    switch (nt) {
+        case 4:
+            if (a.fas && a.NT >= 1) hipLaunchKernelGGL(tau_large_kernel<4>, dim3(a.NT), dim3(kBlockL), 0, s, a, scratch_of(a));
+            hipLaunchKernelGGL(coarse_large_kernel<4>, dim3(a.NT + 1), dim3(kBlockL), 0, s, a, scratch_of(a));
+            break;
+        case 3:
+            if (a.fas && a.NT >= 1) hipLaunchKernelGGL(tau_large_kernel<3>, dim3(a.NT), dim3(kBlockL), 0, s, a, scratch_of(a));
+            hipLaunchKernelGGL(coarse_large_kernel<3>, dim3(a.NT + 1), dim3(kBlockL), 0, s, a, scratch_of(a));
+            break;
+        case 2:
+            if (a.fas && a.NT >= 1) hipLaunchKernelGGL(tau_large_kernel<2>, dim3(a.NT), dim3(kBlockL), 0, s, a, scratch_of(a));
+            hipLaunchKernelGGL(coarse_large_kernel<2>, dim3(a.NT + 1), dim3(kBlockL), 0, s, a, scratch_of(a));
+            break;
+        default:
+            if (a.fas && a.NT >= 1) hipLaunchKernelGGL(tau_large_kernel<0>, dim3(a.NT), dim3(kBlockL), 0, s, a, scratch_of(a));
+            hipLaunchKernelGGL(coarse_large_kernel<0>, dim3(a.NT + 1), dim3(kBlockL), 0, s, a, scratch_of(a));
+    }
 }
 
 void launch_sequential_large(const KArgs& a, hipStream_t s)
