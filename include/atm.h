@@ -256,6 +256,16 @@ size_t atm_static_scratch_bytes(void);
    cooperatively, when the device holds them all at once). */
 const char* atm_sweep_kernel(const atm_problem* prob, const atm_options* opts);
 
+/* Name of the kernel that runs the local solves (the windows of the truncated coarse
+   problem, section 2.1) of atm_coarse_solve and of the two-level atm_solve on the
+   current device (static string; "" if the arguments are invalid, for coarse_form 3
+   and for levels 3): coarse1d_kernel, coarse2d_kernel, coarse2d_spec_kernel,
+   coarse2d_bf_kernel, coarse2d_bf_fas_kernel, coarse_large_kernel, or
+   coarse_pair_kernel (the eigenbasis Psi on large grids of 128, 192 or 256 columns and
+   a multiple of 128 rows: two workgroups per window, launched cooperatively, when the
+   device holds them all at once). */
+const char* atm_coarse_kernel(const atm_problem* prob, const atm_options* opts);
+
 /* Residual 2-norm ||g - A(u)||_2 of an iterate whose F-points are relaxed
    (the stopping test of section 4.3): sqrt(sum_{j=1..N_T} ||y_j - u_{jm}||^2).
    Synchronises the stream and writes the value to *norm_out (host).

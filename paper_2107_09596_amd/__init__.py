@@ -16,7 +16,7 @@ from ._abi import (ATM_AC2D, ATM_ERR_DEVICE, ATM_ERR_DIVERGED, ATM_ERR_INNER_SOL
 
 __all__ = [
     "atm_num_intervals", "atm_window_start", "atm_workspace_bytes", "atm_sweep", "atm_coarse_solve",
-    "atm_coarse_solve_static", "atm_static_scratch_bytes", "atm_sweep_kernel",
+    "atm_coarse_solve_static", "atm_static_scratch_bytes", "atm_sweep_kernel", "atm_coarse_kernel",
     "atm_residual_norm", "atm_implicit_residual_norm", "atm_step_residual_norm", "atm_sequential", "atm_sequential_workspace_bytes", "atm_solve", "atm_status_string",
     "atm_last_error", "workspace", "atm_cnn_param_count", "atm_cnn_workspace_bytes", "atm_cnn_forward",
     "atm_cnn_jvp", "atm_cnn_gradients", "atm_cnn_train_step", "Batch", "AtmError", "ATM_OK", "ATM_NOT_CONVERGED", "ATM_ERR_INVALID_ARG",
@@ -103,6 +103,11 @@ def atm_coarse_solve_static(prob, opts, u, y, e, stream=None) -> None:
 def atm_sweep_kernel(prob, opts) -> str:
     """The kernel that runs the relaxation sweeps for these arguments on the current device."""
     return _abi.lib().atm_sweep_kernel(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts))).decode()
+
+
+def atm_coarse_kernel(prob, opts) -> str:
+    """The kernel that runs the local solves (the windows) for these arguments on the current device."""
+    return _abi.lib().atm_coarse_kernel(ctypes.byref(_abi.problem(prob)), ctypes.byref(_abi.options(opts))).decode()
 
 
 def atm_static_scratch_bytes() -> int:

@@ -74,6 +74,7 @@ SIGNATURES = {
     "atm_coarse_solve": (ctypes.c_int32, [_P, _O, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "atm_coarse_solve_static": (ctypes.c_int32, [_P, _O, _vp, _vp, _vp, _vp]),
     "atm_sweep_kernel": (ctypes.c_char_p, [_P, _O]),
+    "atm_coarse_kernel": (ctypes.c_char_p, [_P, _O]),
     "atm_static_scratch_bytes": (ctypes.c_size_t, []),
     "atm_residual_norm": (ctypes.c_int32, [_P, _O, _vp, _vp, _dp, _vp, ctypes.c_size_t, _vp]),
     "atm_implicit_residual_norm": (ctypes.c_int32, [_P, _O, _vp, _dp, _vp, ctypes.c_size_t, _vp]),

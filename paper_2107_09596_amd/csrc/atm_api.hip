@@ -429,7 +429,8 @@ atm_status do_coarse(atm::KArgs a, double* u, double* y, double* e, hipStream_t 
     a.y = y;
     a.e = e;
     if (a.large) {
-        atm::launch_coarse_large(a, s);
+        const hipError_t err = atm::launch_coarse_large(a, s);
+        if (err != hipSuccess) return fail(ATM_ERR_DEVICE, "window launch: %s", hipGetErrorString(err));
         return check_launch();
     }
     if (a.spectral && !tables_ready) atm::launch_spectral_tables(a, s);
@@ -1400,6 +1401,26 @@ const char* atm_sweep_kernel(const atm_problem* prob, const atm_options* opts)
     a.n = n_space(prob);
     a.NT = n_intervals(prob, opts);
     return atm::sweep_pair_pairs(a, sweep_tasks(prob, opts)) > 0 ? "sweep_pair_mixed_kernel" : "sweep_large_mixed_kernel";
+}
+
+const char* atm_coarse_kernel(const atm_problem* prob, const atm_options* opts)
+{
+    if (validate(prob, opts) != ATM_OK || opts->coarse_form == 3 || three_level(opts)) return "";
+    if (prob->kind == ATM_HEAT1D) return "coarse1d_kernel";
+    const int spec = spectral(prob, opts) ? (opts->coarse_solver == 2 ? 2 : 1) : 0;
+    if (!large_grid(prob)) {
+        if (spec == 2) return use_fas(prob, opts) ? "coarse2d_bf_fas_kernel" : "coarse2d_bf_kernel";
+        return spec ? "coarse2d_spec_kernel" : "coarse2d_kernel";
+    }
+    atm::KArgs a;
+    memset(&a, 0, sizeof(a));
+    a.large = 1;
+    a.spectral = spec;
+    a.g.nx = prob->nx;
+    a.g.ny = prob->ny;
+    a.n = n_space(prob);
+    a.NT = n_intervals(prob, opts);
+    return atm::coarse_pair_pairs(a) > 0 ? "coarse_pair_kernel" : "coarse_large_kernel";
 }
 
 atm_status atm_residual_norm(const atm_problem* prob, const atm_options* opts, const double* u, const double* y,

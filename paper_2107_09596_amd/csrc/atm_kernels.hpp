@@ -163,8 +163,13 @@ hipError_t launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipSt
 // cooperative launch.  Header::fail bit 2 marks a pair whose partner did not arrive.
 constexpr int kFailPairTimeout = 2;
 int sweep_pair_pairs(const KArgs& a, int64_t n_tasks);
+// workgroups of threads threads of kernel fn resident at once on the current device (0 if unknown)
+int resident_blocks(const void* fn, int threads);
 hipError_t launch_sweep_pair(const KArgs& a, int pairs, hipStream_t s);
-void launch_coarse_large(const KArgs& a, hipStream_t s);
+// the windows (and FAS right-hand sides) of the large grids; with the eigenbasis Psi on grids of
+// 128 .. 256 columns they run on two CUs per window (cooperative launch)
+hipError_t launch_coarse_large(const KArgs& a, hipStream_t s);
+int coarse_pair_pairs(const KArgs& a);  // workgroup pairs of the paired window kernels (0: not taken)
 // doubles of the eigenbasis tables of an nx x ny grid (KArgs::spec), and their construction
 size_t spectral_table_doubles(int nx, int ny);
 size_t spectral_bf16_doubles(int nx, int ny);

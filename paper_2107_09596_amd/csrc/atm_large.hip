@@ -11,6 +11,7 @@
 // steps with FP64 update (precision 1), FP64 coarse steps.
 #include "atm_device.hpp"
 #include "atm_kernels.hpp"
+#include "atm_pairsync.hpp"
 #include "atm_spectral.hpp"
 
 namespace atm {
@@ -402,12 +403,13 @@ __device__ __forceinline__ void gemm_f64(const double* __restrict__ A, int lda, 
 // (w % 4) N / 4 .., NT tiles of 16 x 16), over k-chunks of 16 whose A block ([k][row], pitch kAP) and B
 // rows ([k][col], pitch kBP) are staged in LDS, two buffers: the next chunk's loads are in flight
 // while the current chunk's MFMAs run.  The k order of every output's sum is that of gemm_f64.
+// CB / CC: B is read, C written, through device-coherent accesses (data shared by a pair).
 constexpr int kKC = 16;
 constexpr int kAP = 64 + 2;
 constexpr int kBP = 256 + 2;
 constexpr int kGemmBuf = kKC * kAP + kKC * kBP;  // doubles of one buffer
 constexpr int kGemmLds = 2 * kGemmBuf;
-template <int NT, bool AT = false, typename F>
+template <int NT, bool AT = false, bool CB = false, bool CC = false, typename F>
 __device__ __forceinline__ void gemm_f64_tiled(const double* __restrict__ A, int lda, const double* __restrict__ B,
                                                int ldb, double* __restrict__ C, int ldc, int M, int K, double* lds,
                                                F&& epi)
@@ -429,7 +431,8 @@ __device__ __forceinline__ void gemm_f64_tiled(const double* __restrict__ A, int
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
                 const int e = tid + q * kBlockL;
-                rb[q] = B[(int64_t)(k0 + e / N) * ldb + e % N];
+                const int64_t o = (int64_t)(k0 + e / N) * ldb + e % N;
+                rb[q] = CB ? pair::get(B + o) : B[o];
             }
         };
         auto stage = [&](int buf) {
@@ -468,7 +471,11 @@ __device__ __forceinline__ void gemm_f64_tiled(const double* __restrict__ A, int
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + rt * 16 + 4 * u + lk, j = cg * (N / 4) + t * 16 + li;
-                C[(int64_t)i * ldc + j] = epi(i, j, acc[t][u]);
+                const double v = epi(i, j, acc[t][u]);
+                if constexpr (CC)
+                    pair::put(C + (int64_t)i * ldc + j, v);
+                else
+                    C[(int64_t)i * ldc + j] = v;
             }
     }
 }
@@ -601,6 +608,125 @@ __global__ __launch_bounds__(kBlockL) void tau_large_kernel(KArgs a, LScratch sc
     count_cg(a, its);
 }
 
+// ---------------------------------------------------------------------------
+// Windows and FAS right-hand sides on two CUs each (eigenbasis Psi, tiled products)
+// ---------------------------------------------------------------------------
+// One window's state (256 x 256 FP64, 512 KB) lives in global memory anyway, so splitting a window
+// over two workgroups costs only their meetings: each half computes the rows r0 .. r0 + ny/2 of
+// every product of the eigenbasis solve.  Of the four products, the two that apply Qy^T or Qy need
+// every row of their right operand, the other two only the half's own rows, so a Psi substep has
+// two meetings: after the explicit part is formed and after the scaled forward transform.  The
+// operands written by one half and read by the other go through device-coherent stores and loads;
+// a half raises its counter after its stores have completed and waits (bounded) for its partner's.
+// The k order of every sum is that of the one-workgroup kernels, so the results are identical.
+
+struct WinPair {
+    unsigned* epoch;  // [pairs][2] meeting counters, zero before the launch
+    int pairs;        // workgroup pairs in the grid (a multiple of 8)
+    int spin_cap;     // polls of the partner's counter before giving up
+};
+
+// meeting k of the two halves; false (every thread) if the partner did not arrive within the cap
+__device__ __forceinline__ bool pair_meet(const WinPair& wp, int pr, int half, unsigned k, int* ok)
+{
+    pair::drain();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(wp.epoch + 2 * pr + half, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int seen = 0;
+        for (int spin = 0; spin < wp.spin_cap && !seen; ++spin)
+            seen = __hip_atomic_load(wp.epoch + 2 * pr + (half ^ 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= k;
+        *ok = seen;
+    }
+    __syncthreads();
+    return *ok != 0;
+}
+
+// one Psi substep w <- M^-1 psi(w) on the rows r0 .. r0 + rows of w; t0, t2 shared by the pair, t1
+// private rows; false if a meeting failed
+template <int NT>
+__device__ __forceinline__ bool spectral_step_pair(const KArgs& a, const SpecTables& T, double* __restrict__ w,
+                                                   double* __restrict__ t0, double* __restrict__ t1,
+                                                   double* __restrict__ t2, double* lds, int r0, int rows,
+                                                   const WinPair& wp, int pr, int half, unsigned& k, int* ok)
+{
+    const int nx = a.g.nx, ny = a.g.ny;
+    const int64_t o = (int64_t)r0 * nx;
+    auto same = [](int, int, double v) { return v; };
+    for (int e = threadIdx.x; e < rows * nx; e += kBlockL) pair::put(t0 + o + e, explicit_part(a.coarse, w[o + e]));
+    if (!pair_meet(wp, pr, half, ++k, ok)) return false;
+    gemm_f64_tiled<NT, true, true>(T.qy + r0, ny, t0, nx, t1 + o, nx, rows, ny, lds, same);  // Qy^T b
+    __syncthreads();
+    const double cx2 = 2.0 * a.coarse.cx, cy2 = 2.0 * a.coarse.cy;
+    gemm_f64_tiled<NT, false, false, true>(t1 + o, nx, T.qx, nx, t2 + o, nx, rows, nx, lds,  // (.. Qx) ./ mu
+                                           [&](int i, int j, double v) {
+                                               return v / (1.0 + (cx2 * T.ex[j] + cy2 * T.ey[r0 + i]));
+                                           });
+    if (!pair_meet(wp, pr, half, ++k, ok)) return false;
+    gemm_f64_tiled<NT, true, true>(T.qyt + r0, ny, t2, nx, t1 + o, nx, rows, ny, lds, same);  // Qy ..
+    __syncthreads();
+    gemm_f64_tiled<NT>(t1 + o, nx, T.qxt, nx, w + o, nx, rows, nx, lds, same);  // .. Qx^T
+    __syncthreads();
+    return true;
+}
+
+// TAU: tau_j = (v_j - Psi(v_{j-1})) + r_j for the tasks j = 1 .. N_T; else window p for the tasks
+// p = 0 .. N_T (linear or FAS form).  Pair q takes the tasks q, q + pairs, ...
+template <int NT, bool TAU>
+__global__ __launch_bounds__(kBlockL) void coarse_pair_kernel(KArgs a, LScratch sc, WinPair wp)
+{
+    __shared__ double gl[kGemmLds];
+    __shared__ int ok;
+    const int pr = pair::pair_of(blockIdx.x), half = pair::half_of(blockIdx.x);
+    const int nx = a.g.nx, rows = a.g.ny / 2, r0 = half * rows;
+    const int64_t n = a.n, o = (int64_t)r0 * nx, cnt = (int64_t)rows * nx;
+    const SpecTables T = spec_tables(a);
+    unsigned k = 0;
+    bool alive = true;
+    for (int64_t task = (TAU ? 1 : 0) + pr; alive && task <= a.NT; task += wp.pairs) {
+        double* __restrict__ w = sc.vec(task, 4);
+        double* t0 = sc.vec(task, 0);
+        double* t1 = sc.vec(task, 1);
+        double* t2 = sc.vec(task, 2);
+        const int64_t s0 = TAU ? task - 1 : (task - a.k + 1 > 0 ? task - a.k + 1 : 0);
+        for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) {
+            const int64_t i = o + e;
+            if (TAU)
+                w[i] = a.u[(s0 * a.m) * n + i];
+            else {
+                const double r = cpoint_residual(a, s0, i);
+                w[i] = a.fas ? a.u[(s0 * a.m) * n + i] + r : r;
+            }
+        }
+        __syncthreads();
+        for (int64_t jj = s0 + 1; alive && jj <= task; ++jj) {
+            for (int q = 0; alive && q < a.substeps; ++q)
+                alive = spectral_step_pair<NT>(a, T, w, t0, t1, t2, gl, r0, rows, wp, pr, half, k, &ok);
+            if (!alive || TAU) break;
+            for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) {
+                const int64_t i = o + e;
+                w[i] = w[i] + (a.fas ? a.tau[jj * n + i] : cpoint_residual(a, jj, i));
+            }
+            __syncthreads();
+        }
+        if (!alive) break;
+        for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) {
+            const int64_t i = o + e;
+            if (TAU)
+                a.tau[task * n + i] = (a.u[(task * a.m) * n + i] - w[i]) + cpoint_residual(a, task, i);
+            else
+                a.e[task * n + i] = a.fas ? w[i] - a.u[(task * a.m) * n + i] : w[i];
+        }
+        __syncthreads();
+    }
+    if (!alive && threadIdx.x == 0) atomicOr(a.fail, kFailPairTimeout);
+}
+
+__global__ void clear_counters_kernel(unsigned* c, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) c[i] = 0u;
+}
+
 // sequential stepping in one workgroup
 __global__ __launch_bounds__(kBlockL) void seq_large_kernel(KArgs a, LScratch sc)
 {
@@ -710,9 +836,53 @@ hipError_t launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipSt
     return hipGetLastError();
 }
 
-void launch_coarse_large(const KArgs& a, hipStream_t s)
+// the paired window kernels of an nx x ny grid with NT-tile products, and the pairs to launch (0: the
+// one-workgroup kernels take the grid)
+struct CoarsePair {
+    const void* tau;
+    const void* win;
+    int pairs;
+};
+
+static CoarsePair coarse_pair(const KArgs& a)
+{
+    CoarsePair cp{nullptr, nullptr, 0};
+    const int nt = a.spectral ? spectral_nt(a.g.nx, a.g.ny) : 0;
+    if (a.g.ny % 128) return cp;  // halves of whole 64-row blocks
+    if (nt == 4) cp = {(const void*)coarse_pair_kernel<4, true>, (const void*)coarse_pair_kernel<4, false>, 0};
+    if (nt == 3) cp = {(const void*)coarse_pair_kernel<3, true>, (const void*)coarse_pair_kernel<3, false>, 0};
+    if (nt == 2) cp = {(const void*)coarse_pair_kernel<2, true>, (const void*)coarse_pair_kernel<2, false>, 0};
+    if (!cp.win) return cp;
+    int pairs = (resident_blocks(cp.win, kBlockL) / 2) / 8 * 8;
+    const int64_t want = (a.NT + 1 + 7) / 8 * 8;
+    if (pairs > want) pairs = (int)want;
+    cp.pairs = pairs >= 8 ? pairs : 0;
+    return cp;
+}
+
+int coarse_pair_pairs(const KArgs& a) { return coarse_pair(a).pairs; }
+
+hipError_t launch_coarse_large(const KArgs& a, hipStream_t s)
 {
     if (a.spectral) launch_spectral_tables(a, s);
+    const CoarsePair cp = coarse_pair(a);
+    if (cp.pairs > 0) {
+        // the meeting counters in the fourth vector of task 0, which no paired task uses
+        WinPair wp;
+        wp.epoch = reinterpret_cast<unsigned*>(a.large_scratch + 3 * a.n);
+        wp.pairs = cp.pairs;
+        wp.spin_cap = 1 << 21;
+        KArgs ka = a;
+        LScratch sc = scratch_of(a);
+        void* args[] = {&ka, &sc, &wp};
+        if (a.fas && a.NT >= 1) {
+            hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(256), 0, s, wp.epoch, 2 * cp.pairs);
+            hipError_t e = hipLaunchCooperativeKernel(cp.tau, dim3(2 * cp.pairs), dim3(kBlockL), args, 0, s);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(256), 0, s, wp.epoch, 2 * cp.pairs);
+        return hipLaunchCooperativeKernel(cp.win, dim3(2 * cp.pairs), dim3(kBlockL), args, 0, s);
+    }
     const int nt = a.spectral ? spectral_nt(a.g.nx, a.g.ny) : 0;
     switch (nt) {
         case 4:
@@ -731,6 +901,7 @@ void launch_coarse_large(const KArgs& a, hipStream_t s)
             if (a.fas && a.NT >= 1) hipLaunchKernelGGL(tau_large_kernel<0>, dim3(a.NT), dim3(kBlockL), 0, s, a, scratch_of(a));
             hipLaunchKernelGGL(coarse_large_kernel<0>, dim3(a.NT + 1), dim3(kBlockL), 0, s, a, scratch_of(a));
     }
+    return hipGetLastError();
 }
 
 void launch_sequential_large(const KArgs& a, hipStream_t s)

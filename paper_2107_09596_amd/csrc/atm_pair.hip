@@ -18,14 +18,17 @@
 // sums and the residual-norm recurrence differ from the one-workgroup solver.
 //
 // Handshake: the mailbox rows and sums are written with device-coherent stores (they bypass the
-// non-coherent caches), every thread waits for its stores to complete, the workgroup synchronises,
-// and one thread raises the half's epoch counter; the partner polls that counter with coherent
-// loads and then reads the mailbox the same way.  Every wait is bounded: a half that waits longer
-// than the spin cap sets the header's pair-timeout flag and leaves, and its partner then times out
-// too, so the kernel always ends.  The grid is launched cooperatively (every workgroup resident),
+// non-coherent caches).  The rows are stored where a pass starts (their values are known then), and
+// every thread waits for its stores to complete before the workgroup sums its partials; one wave
+// then stores the four sums, which are themselves the signal: the partner polls them with coherent
+// loads until none holds the empty mark (a NaN pattern no arithmetic produces), and after taking
+// them writes the mark back, freeing the slot for the handshake after next.  Every wait is bounded:
+// a half that waits longer than the spin cap sets the header's pair-timeout flag and leaves, and its
+// partner then times out too, so the kernel always ends.  The grid is launched cooperatively (every workgroup resident),
 // pairs sit on one XCD (blocks b and b ^ 8), and each pair takes intervals pair, pair + pairs, ...
 #include "atm_device.hpp"
 #include "atm_kernels.hpp"
+#include "atm_pairsync.hpp"
 
 namespace atm {
 namespace pair {
@@ -41,29 +44,12 @@ constexpr int kTimeoutFlag = kFailPairTimeout;
 constexpr int pack_floats(int nx) { return (7 * nx + kThreads - 1) / kThreads * kThreads; }
 
 struct PairArgs {
-    unsigned* epoch;  // [pairs][2] handshake counters, zero before the launch
-    float* mail;      // [2 parities][pairs][2 halves][slot] mailbox
+    float* mail;      // [2 parities][pairs][2 halves][slot] mailbox, sums marked empty before the launch
     int pairs;        // workgroup pairs in the grid (a multiple of 8)
     int slot;         // floats per mailbox slot: pack_floats(NX), then kParts doubles
+    int pack;         // pack_floats(NX): where the sums of a slot start
     int spin_cap;     // polls of the partner's counter before giving up
 };
-
-__device__ __forceinline__ void put(float* p, float v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ float get(const float* p)
-{
-    return __hip_atomic_load(const_cast<float*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void put(double* p, double v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double get(const double* p)
-{
-    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // A 32-bit offset hidden from the optimiser, so that the row offsets of the unrolled strip loops are
 // recomputed where they are used instead of being hoisted out of the time loop (one register each);
@@ -90,13 +76,6 @@ __device__ __forceinline__ double uniform(double v)
     const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
     const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// this thread's stores (and loads) have completed
-__device__ __forceinline__ void drain()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_waitcnt(0);
 }
 
 // The FP32 step operator at one point: M v = d v - cx (w + e) - cy (up + dn).  Both halves
@@ -161,32 +140,66 @@ __device__ __forceinline__ double row_val(const double* v, const Half<NX, R>& h,
     return v[opq((uint32_t)Y * NX + x)];
 }
 
-// Offsets into one slice of the rows of a thread (column x, rows row0 .. row0+R-1) and of their
-// neighbours.  The base is hidden from the optimiser where a pass starts, so the row offsets are
-// recomputed there (one add each) rather than held in registers across the time loop.
-template <int NX, int R>
-struct StripOff {
-    uint32_t c;        // row0 * NX + x
-    int dw, de;        // west / east neighbour relative to c (0 for a Dirichlet edge, masked)
-    uint32_t up, dn;   // the rows above the first and below the last row (wrapped; masked if absent)
-    bool wm, em, um, dm;
-    __device__ __forceinline__ StripOff(const Half<NX, R>& h)
-    {
-        constexpr int ny = 2 * Half<NX, R>::H;
-        c = opq((uint32_t)h.row0 * NX + (uint32_t)h.x);
-        wm = h.xw >= 0;
-        em = h.xe >= 0;
-        dw = wm ? h.xw - h.x : 0;
-        de = em ? h.xe - h.x : 0;
-        const int yu = h.row0 - 1, yd = h.row0 + R;
-        um = yu >= 0 || h.periodic;
-        dm = yd < ny || h.periodic;
-        up = (uint32_t)((yu < 0 ? yu + ny : yu) * NX + h.x);
-        dn = (uint32_t)((yd >= ny ? yd - ny : yd) * NX + h.x);
-        if (!um) up = c;
-        if (!dm) dn = c;
-    }
+// The FP64 part of a step boundary, over the half's points in row order (coalesced, and free of the
+// per-thread CG arrays): for each point the value v the next step starts from and the defect of that
+// step, rho = psi(v) - M s with s the stored iterate of the step, written as FP32 into the p rows of
+// LDS, where the next step's CG takes it as r = p.  v comes from two loads (vin: global index o, LDS
+// index li) and a combination that may store (vout).  A thread takes kBatch points at a time and
+// issues every load of the batch before the first store, so that a batch costs one memory latency
+// (a store may alias the loads of the next batch: v is written over its own input in place).  The
+// arithmetic of every point is that of the defect in the one-workgroup solver.
+constexpr int kBatch = 8;
+// element i of one slice, addressed as a uniform base plus a 32-bit byte offset (one register)
+__device__ __forceinline__ const double& at(const double* base, uint32_t i)
+{
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + i * 8u);
+}
+__device__ __forceinline__ double& at(double* base, uint32_t i)
+{
+    return *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + i * 8u);
+}
+struct V2 {
+    double a, b;
 };
+template <int NX, int R, typename VIN, typename VOUT>
+__device__ __forceinline__ void defect_pass(const StepCoef& c, const Half<NX, R>& h, float* P, const double* __restrict__ s,
+                                            VIN&& vin, VOUT&& vout)
+{
+    constexpr int H = Half<NX, R>::H, PW = NX + 2, NY = 2 * H;
+    constexpr int RS = kThreads / NX;  // rows between a thread's points
+    static_assert(H % (kBatch * RS) == 0, "whole batches per half");
+    const int col = threadIdx.x % NX;
+    // the neighbour columns at wrapped (always valid) addresses, zero beyond a Dirichlet edge
+    const int cw = col > 0 ? col - 1 : NX - 1, ce = col < NX - 1 ? col + 1 : 0;
+    const bool wm = col > 0 || h.periodic, em = col < NX - 1 || h.periodic;
+    for (int rb = threadIdx.x / NX; rb < H; rb += kBatch * RS) {
+        const int r0 = (int)opq((uint32_t)rb);  // the offsets are formed here, not held across the CG
+        V2 in[kBatch];
+        double cen[kBatch], up[kBatch], dn[kBatch], w[kBatch], ea[kBatch];
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int row = r0 + b * RS, Y = h.half * H + row;
+            const uint32_t o = (uint32_t)Y * NX + col;
+            const int yu = Y > 0 ? Y - 1 : NY - 1, yd = Y < NY - 1 ? Y + 1 : 0;
+            in[b] = vin(o, (row + 1) * PW + col + 1);
+            cen[b] = at(s, o);
+            up[b] = at(s, (uint32_t)yu * NX + col);
+            dn[b] = at(s, (uint32_t)yd * NX + col);
+            w[b] = at(s, (uint32_t)Y * NX + cw);
+            ea[b] = at(s, (uint32_t)Y * NX + ce);
+        }
+#pragma unroll
+        for (int b = 0; b < kBatch; ++b) {
+            const int row = r0 + b * RS, Y = h.half * H + row;
+            const uint32_t o = (uint32_t)Y * NX + col;
+            const int li = (row + 1) * PW + col + 1;
+            const double v = vout(in[b], o, li);
+            const double u_ = (Y > 0 || h.periodic) ? up[b] : 0.0, d_ = (Y < NY - 1 || h.periodic) ? dn[b] : 0.0;
+            const double w_ = wm ? w[b] : 0.0, e_ = em ? ea[b] : 0.0;
+            P[li] = (float)(explicit_part(c, v) - stencil_value(c, u_, cen[b], d_, w_, e_));
+        }
+    }
+}
 
 // the partner's mailbox slot of handshake k and the packs in it: first rows (r, p, p of the next
 // row), last rows (r, p, p of the row before)
@@ -198,6 +211,10 @@ __device__ __forceinline__ float* own_slot(const PairArgs& pa, int pair, int hal
 {
     return pa.mail + ((size_t)((k & 1) * pa.pairs + pair) * 2 + half) * pa.slot;
 }
+
+// the mark of a sum not yet written: a signalling-NaN pattern, which no arithmetic produces
+constexpr unsigned long long kEmpty = 0x7FF4DEADBEEF0001ull;
+__device__ __forceinline__ bool is_empty(double v) { return __builtin_bit_cast(unsigned long long, v) == kEmpty; }
 
 // Exchange the partial sums and wait for the partner.  The caller has written its mailbox rows.
 // Returns false (all threads) if the partner did not arrive within the spin cap.
@@ -211,29 +228,27 @@ __device__ __forceinline__ bool handshake(const PairArgs& pa, const Half<NX, R>&
     // wave 0 publishes and waits, all its lanes alike (same addresses, same values): a branch taken by
     // whole waves, so the rest of the kernel sees no divergent control flow here
     if (__builtin_amdgcn_readfirstlane(threadIdx.x) < 64) {
-        const int par = k & 1;
-        double* mine = reinterpret_cast<double*>(pa.mail + ((size_t)(par * pa.pairs + h.pair) * 2 + h.half) * pa.slot + PK);
-        const double* theirs = reinterpret_cast<const double*>(
-            pa.mail + ((size_t)(par * pa.pairs + h.pair) * 2 + (h.half ^ 1)) * pa.slot + PK);
+        double* mine = reinterpret_cast<double*>(own_slot(pa, h.pair, h.half, k) + PK);
+        double* theirs = reinterpret_cast<double*>(const_cast<float*>(partner_slot(pa, h.pair, h.half, k)) + PK);
 #pragma unroll
         for (int q = 0; q < kParts; ++q) put(mine + q, tot[q]);
-        drain();
-        __hip_atomic_store(pa.epoch + 2 * h.pair + h.half, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // the decision and the values are taken from one lane, so the wave agrees on them
         int ok = 0;
-        for (int spin = 0; spin < pa.spin_cap; ++spin) {
-            const unsigned seen = (unsigned)__builtin_amdgcn_readfirstlane(
-                (int)__hip_atomic_load(pa.epoch + 2 * h.pair + (h.half ^ 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            if (seen >= k) {
-                ok = 1;
-                break;
+        double v[kParts];
+        for (int spin = 0; spin < pa.spin_cap && !ok; ++spin) {
+            ok = 1;
+#pragma unroll
+            for (int q = 0; q < kParts; ++q) {
+                v[q] = uniform(get(theirs + q));
+                ok = is_empty(v[q]) ? 0 : ok;
             }
         }
         if (ok) {
 #pragma unroll
             for (int q = 0; q < kParts; ++q) {
                 parts[h.half][q] = tot[q];
-                parts[h.half ^ 1][q] = uniform(get(theirs + q));
+                parts[h.half ^ 1][q] = v[q];
+                put(theirs + q, __builtin_bit_cast(double, kEmpty));
             }
         }
         *flag = ok;
@@ -263,8 +278,8 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
     HF h;
     h.x = threadIdx.x % NX;
     h.g = threadIdx.x / NX;
-    h.half = (blockIdx.x >> 3) & 1;
-    h.pair = ((blockIdx.x >> 4) << 3) | (blockIdx.x & 7);
+    h.half = half_of(blockIdx.x);
+    h.pair = pair_of(blockIdx.x);
     h.periodic = a.g.periodic != 0;
     h.xw = h.x > 0 ? h.x - 1 : (h.periodic ? NX - 1 : -1);
     h.xe = h.x < NX - 1 ? h.x + 1 : (h.periodic ? 0 : -1);
@@ -300,49 +315,36 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
     for (int64_t j = h.pair; j <= a.NT && alive; j += pa.pairs) {
         const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
         // the starting value c_j (written to u_{jm} in modes 1 and 2) and the defect of the first step
-        // rho_1 = psi(c_j) - M s_1, s_1 the value stored at the first point of the interval
+        // rho_1 = psi(c_j) - M s_1, s_1 the value stored at the first point of the interval (into LDS)
         const double* xo = a.u + (j * a.m + 1) * n;  // s_t of the next step (valid while total >= 1)
         {
             double* uc = a.u + (j * a.m) * n;
             const double* ax = (a.mode != 0 && a.aux) ? a.aux + j * n : nullptr;
             const bool use_aux = a.mode == 1 || (a.mode == 2 && j > 0);
-            if (total >= 1) {
-                const StripOff<NX, R> so(h);
-                const double s_up0 = xo[so.up], s_dn_last = xo[so.dn];  // both addresses valid
-                double s_up = so.um ? s_up0 : 0.0, s_cen = xo[so.c];
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t o = so.c + (uint32_t)(i * NX);
-                    const double cu = uc[o];
-                    const double c0 = !use_aux ? cu : (a.mode == 1 ? cu + ax[o] : ax[o]);
-                    if (a.mode != 0) uc[o] = c0;
-                    const double s_dn = i < R - 1 ? xo[o + NX] : (so.dm ? s_dn_last : 0.0);
-                    const double wr = xo[o + so.dw], er = xo[o + so.de];
-                    const double w = so.wm ? wr : 0.0, e = so.em ? er : 0.0;
-                    rv[i] = (float)(explicit_part(c, c0) - stencil_value(c, s_up, s_cen, s_dn, w, e));
-                    s_up = s_cen;
-                    s_cen = s_dn;
-                    if ((i & 1) == 1) row_fence();
+            auto start_in = [&](uint32_t o, int) { return V2{at(uc, o), use_aux ? at(ax, o) : 0.0}; };
+            auto start_out = [&](const V2& in, uint32_t o, int) {
+                const double c0 = !use_aux ? in.a : (a.mode == 1 ? in.a + in.b : in.b);
+                if (a.mode != 0) at(uc, o) = c0;
+                return c0;
+            };
+            if (total >= 1)
+                defect_pass<NX, R>(c, h, P, xo, start_in, start_out);
+            else if (a.mode != 0)
+                for (int e = threadIdx.x; e < H * NX; e += kThreads) {
+                    const uint32_t o = (uint32_t)(h.half * H) * NX + e;
+                    start_out(start_in(o, 0), o, 0);
                 }
-            } else if (a.mode != 0) {
-                const uint32_t c0off = opq((uint32_t)h.row0 * NX + (uint32_t)h.x);
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t o = c0off + (uint32_t)(i * NX);
-                    const double cu = uc[o];
-                    uc[o] = !use_aux ? cu : (a.mode == 1 ? cu + ax[o] : ax[o]);
-                }
-            }
         }
+        __syncthreads();
         for (int64_t t = 1; t <= total && alive; ++t) {
-            // ---- FP32 CG for M d = rho from d = 0: x = 0, p = r ----
+            // ---- FP32 CG for M d = rho from d = 0: x = 0, p = r (rho in the p rows of LDS) ----
             double rr_part = 0.0;  // this thread's share of (r, r) of the current residual
             {
                 float chunk = 0.0f;
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
                     xv[i] = 0.0f;
-                    Pr[i * PW] = rv[i];
+                    rv[i] = Pr[i * PW];
                     chunk += rv[i] * rv[i];
                     if ((i & 7) == 7 || i == R - 1) {
                         rr_part += (double)chunk;
@@ -376,6 +378,14 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
             int it = 0;
             bool converged = !(bb > thresh);  // b = 0 (d = 0 is exact), or a tolerance that b meets
             while (!converged && it < a.maxit) {
+                // the boundary packs, r and p before the update, stored first (their latency is hidden
+                // by the pass)
+                {
+                    float* ms = own_slot(pa, h.pair, h.half, k + 1) + pk0;
+                    put(ms, last_group ? rv[R - 1] : rv[0]);
+                    put(ms + pk_step, Pr[prow_a]);
+                    put(ms + 2 * pk_step, Pr[prow_b]);
+                }
                 // pass 1: q = M p and the partial sums
                 double sums[kParts] = {0.0, 0.0, 0.0, rr_part};
                 {
@@ -400,13 +410,6 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                         if ((i & 3) == 3) row_fence();
                     }
                 }
-                // the boundary packs: r and p before the update
-                {
-                    float* ms = own_slot(pa, h.pair, h.half, k + 1) + pk0;
-                    put(ms, last_group ? rv[R - 1] : rv[0]);
-                    put(ms + pk_step, Pr[prow_a]);
-                    put(ms + 2 * pk_step, Pr[prow_b]);
-                }
                 ++k;
                 if (!handshake<NX, R>(pa, h, k, sums, red, slot, parts, &flag)) {
                     alive = false;
@@ -417,27 +420,19 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                 const double rr_new = uniform(rr - 2.0 * alpha * sums[1] + alpha * alpha * sums[2]);
                 const double beta = rr_new / rr;
                 const float a32 = uniform((float)alpha), b32 = uniform((float)beta);
-                // the partner's boundary rows of the new p, as the partner computes them (written to the
-                // ghost rows after every thread has formed its q from the old ones)
                 // the partner's boundary row next to this thread's group, as the partner computes it:
                 // above the first group the partner's last row (its r and p, the row before it, and this
                 // half's first row below it), below the last group its first row (this half's last row
-                // above it, the row after it below)
-                float ghost;
-                {
-                    const bool top = first_group;
-                    const float* ps = partner_slot(pa, h.pair, h.half, k) + (top ? 3 * NX : 0);
-                    const float r0 = get(ps + h.x), p0 = get(ps + NX + h.x), p1 = get(ps + 2 * NX + h.x);
-                    const float wr = get(ps + NX + (h.xw >= 0 ? h.xw : h.x));
-                    const float er = get(ps + NX + (h.xe >= 0 ? h.xe : h.x));
-                    const float w = h.xw >= 0 ? wr : 0.0f, e = h.xe >= 0 ? er : 0.0f;
-                    const float own = top ? Pr[0] : Pr[(R - 1) * PW];
-                    const float q = top ? stencil32(d32, cx32, cy32, p1, p0, own, w, e)
-                                        : stencil32(d32, cx32, cy32, own, p0, p1, w, e);
-                    float r = r0;
-                    cg_update(a32, b32, q, p0, r, ghost);
-                    if (!(top ? h.top_ghost : h.bot_ghost)) ghost = 0.0f;
-                }
+                // above it, the row after it below); written to the ghost rows after every thread has
+                // formed its q from the old ones.  Its inputs are loaded here, before the update pass, and
+                // used after it, which hides their latency; this thread's own boundary value of p is
+                // taken before the pass overwrites it.
+                const bool top = first_group;
+                const float* ps = partner_slot(pa, h.pair, h.half, k) + (top ? 3 * NX : 0);
+                const float g_r = get(ps + h.x), g_p0 = get(ps + NX + h.x), g_p1 = get(ps + 2 * NX + h.x);
+                const float g_wr = get(ps + NX + (h.xw >= 0 ? h.xw : h.x));
+                const float g_er = get(ps + NX + (h.xe >= 0 ? h.xe : h.x));
+                const float g_own = top ? Pr[0] : Pr[(R - 1) * PW];
                 // pass 2: x += a p, r -= a q, p = r + b p (each thread reads and writes only its own points
                 // of p), this thread's share of the new (r, r), and the ghost rows
                 {
@@ -457,7 +452,12 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                         }
                         if ((i & 7) == 7) row_fence();
                     }
-                    *Pg = ghost;
+                    const float w = h.xw >= 0 ? g_wr : 0.0f, e = h.xe >= 0 ? g_er : 0.0f;
+                    const float q = top ? stencil32(d32, cx32, cy32, g_p1, g_p0, g_own, w, e)
+                                        : stencil32(d32, cx32, cy32, g_own, g_p0, g_p1, w, e);
+                    float r = g_r, ghost;
+                    cg_update(a32, b32, q, g_p0, r, ghost);
+                    *Pg = (top ? h.top_ghost : h.bot_ghost) ? ghost : 0.0f;
                 }
                 __syncthreads();
                 ++it;
@@ -467,37 +467,33 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
             its_total += it;
             if (!converged) atomicOr(a.fail, 1);
             // ---- v_t = s_t + d in FP64; the defect of the next step ----
+            // d goes to the p rows of LDS (p is no longer needed), then a row-order pass forms v_t and
+            // the next defect in its place
+#pragma unroll
+            for (int i = 0; i < R; ++i) Pr[i * PW] = xv[i];
+            __syncthreads();
             const bool ystep = (t == a.m);
             const double* so = xo;
             double* dst = ystep ? a.y + (j + 1) * n : a.u + (j * a.m + t) * n;
             const double* xn = nullptr;
+            auto upd_in = [&](uint32_t o, int li) { return V2{at(so, o), (double)P[li]}; };
+            auto upd_out = [&](const V2& in, uint32_t o, int) {
+                const double v = in.a + in.b;
+                at(dst, o) = v;
+                return v;
+            };
             if (t < total) {
                 xn = (t + 1 < a.m) ? a.u + (j * a.m + t + 1) * n
                                    : (a.mode == 0 ? a.u + ((j + 1) * a.m) * n : (a.mode == 1 ? a.y : a.aux) + (j + 1) * n);
-                const StripOff<NX, R> so_(h);
-                const double s_up0 = xn[so_.up], s_dn_last = xn[so_.dn];  // both addresses valid
-                double s_up = so_.um ? s_up0 : 0.0, s_cen = xn[so_.c];
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t o = so_.c + (uint32_t)(i * NX);
-                    const double v = so[o] + (double)xv[i];
-                    dst[o] = v;
-                    const double s_dn = i < R - 1 ? xn[o + NX] : (so_.dm ? s_dn_last : 0.0);
-                    const double wr = xn[o + so_.dw], er = xn[o + so_.de];
-                    const double w = so_.wm ? wr : 0.0, e = so_.em ? er : 0.0;
-                    rv[i] = (float)(explicit_part(c, v) - stencil_value(c, s_up, s_cen, s_dn, w, e));
-                    s_up = s_cen;
-                    s_cen = s_dn;
-                    if ((i & 1) == 1) row_fence();
-                }
+                defect_pass<NX, R>(c, h, P, xn, upd_in, upd_out);
             } else {
-                const uint32_t c0off = opq((uint32_t)h.row0 * NX + (uint32_t)h.x);
-#pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const uint32_t o = c0off + (uint32_t)(i * NX);
-                    dst[o] = so[o] + (double)xv[i];
+                for (int e = threadIdx.x; e < H * NX; e += kThreads) {
+                    const uint32_t o = (uint32_t)(h.half * H) * NX + e;
+                    const int li = (e / NX + 1) * PW + e % NX + 1;
+                    upd_out(upd_in(o, li), o, li);
                 }
             }
+            __syncthreads();
             xo = xn;
         }
     }
@@ -505,9 +501,14 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
     if (h.half == 0) count_cg(a, its_total);
 }
 
-__global__ void clear_epochs_kernel(unsigned* epoch, int n)
+// mark every sum of the mailbox empty (the slots of both parities, pairs and halves)
+__global__ void reset_mailbox_kernel(PairArgs pa)
 {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) epoch[i] = 0u;
+    const int slots = 2 * pa.pairs * 2;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < slots * kParts; i += gridDim.x * blockDim.x) {
+        double* sums = reinterpret_cast<double*>(pa.mail + (size_t)(i / kParts) * pa.slot + pa.pack);
+        sums[i % kParts] = __builtin_bit_cast(double, kEmpty);
+    }
 }
 
 }  // namespace pair
@@ -539,32 +540,29 @@ PairShape pair_shape(int nx, int ny)
     return p;
 }
 
-// resident workgroups of an instantiation on the current device (0 if it cannot run)
-int resident_blocks(void* fn)
+}  // namespace
+
+int resident_blocks(const void* fn, int threads)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn), pair::kThreads, 0) !=
-        hipSuccess)
-        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess) return 0;
     return per_cu * cus;
 }
-
-}  // namespace
 
 int sweep_pair_pairs(const KArgs& a, int64_t n_tasks)
 {
     const PairShape ps = pair_shape(a.g.nx, a.g.ny);
     if (!ps.fn || !a.large || a.is1d) return 0;
-    const int resident = resident_blocks(ps.fn);
+    const int resident = resident_blocks(ps.fn, pair::kThreads);
     int pairs = (resident / 2) / 8 * 8;
     const int64_t want = (n_tasks + 7) / 8 * 8;
     if (pairs > want) pairs = (int)want;
     if (pairs < 8) return 0;
-    // epochs and the mailbox in the large-grid scratch (free while the sweep runs)
+    // the mailbox in the large-grid scratch (free while the sweep runs)
     const size_t slot = ((size_t)pair::pack_floats(a.g.nx) + 2 * pair::kParts + 63) / 64 * 64;
-    const size_t need = 256 + (size_t)pairs * 2 * sizeof(unsigned) + 2 * (size_t)pairs * 2 * slot * sizeof(float);
+    const size_t need = 2 * (size_t)pairs * 2 * slot * sizeof(float);
     const size_t have = (size_t)(a.NT + 1) * 5 * (size_t)a.n * sizeof(double);
     return need <= have ? pairs : 0;
 }
@@ -575,11 +573,10 @@ hipError_t launch_sweep_pair(const KArgs& a, int pairs, hipStream_t s)
     pair::PairArgs pa;
     pa.pairs = pairs;
     pa.slot = (int)(((size_t)pair::pack_floats(a.g.nx) + 2 * pair::kParts + 63) / 64 * 64);
+    pa.pack = pair::pack_floats(a.g.nx);
     pa.spin_cap = kSpinCap;
-    pa.epoch = reinterpret_cast<unsigned*>(a.large_scratch);
-    pa.mail = reinterpret_cast<float*>(reinterpret_cast<char*>(a.large_scratch) +
-                                       ((size_t)pairs * 2 * sizeof(unsigned) + 255) / 256 * 256);
-    hipLaunchKernelGGL(pair::clear_epochs_kernel, dim3(1), dim3(256), 0, s, pa.epoch, 2 * pairs);
+    pa.mail = reinterpret_cast<float*>(a.large_scratch);
+    hipLaunchKernelGGL(pair::reset_mailbox_kernel, dim3(8), dim3(256), 0, s, pa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     KArgs ka = a;
