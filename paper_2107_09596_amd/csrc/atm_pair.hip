@@ -260,6 +260,10 @@ __device__ __forceinline__ bool handshake(const PairArgs& pa, const Half<NX, R>&
     return true;
 }
 
+// Rows of x a thread keeps in LDS rather than registers: the 256 x 256 grid's R = 64 rows of x, r and
+// M p fill the registers of a thread; LDS beyond p and the sums holds 14 of them.
+constexpr int x_lds_rows(int nx, int r) { return (nx == 256 && r == 64) ? 14 : 0; }
+
 template <int NX, int R>
 __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, PairArgs pa)
 {
@@ -269,7 +273,12 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
     // of NX + 2 columns (columns 0 and NX+1: zero for Dirichlet, copies of the opposite edge when
     // periodic), so that a thread's stencil reads are constant offsets from one base address
     constexpr int PW = NX + 2;
-    __shared__ float P[(H + 3) * PW];  // row H+2: writes of the row groups without a ghost row
+    // row H+2: writes of the row groups without a ghost row (none when a half has two row groups)
+    constexpr int PROWS = G > 2 ? H + 3 : H + 2;
+    __shared__ float P[PROWS * PW];
+    // the last XL rows of x of every thread, in the LDS that p leaves free (fewer registers to spill)
+    constexpr int XL = x_lds_rows(NX, R);
+    __shared__ float XS[XL > 0 ? XL * kThreads : 1];
     __shared__ double red[2 * kParts * kWaves];
     __shared__ double parts[2][kParts];
     __shared__ int flag;
@@ -343,7 +352,10 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                 float chunk = 0.0f;
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    xv[i] = 0.0f;
+                    if (i < R - XL)
+                        xv[i] = 0.0f;
+                    else
+                        XS[(i - (R - XL)) * kThreads + threadIdx.x] = 0.0f;
                     rv[i] = Pr[i * PW];
                     chunk += rv[i] * rv[i];
                     if ((i & 7) == 7 || i == R - 1) {
@@ -373,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                 *Pg = from_partner ? v : 0.0f;
             }
             __syncthreads();
-            const double bb = tot[3];
+            const double bb = uniform(tot[3]);
             const double thresh = a.rtol2_mixed * bb;
             int it = 0;
             bool converged = !(bb > thresh);  // b = 0 (d = 0 is exact), or a tolerance that b meets
@@ -441,7 +453,12 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
 #pragma unroll
                     for (int i = 0; i < R; ++i) {
                         const float pc = Pr[i * PW];
-                        xv[i] = xv[i] + a32 * pc;
+                        if (i < R - XL)
+                            xv[i] = xv[i] + a32 * pc;
+                        else {
+                            float& xl = XS[(i - (R - XL)) * kThreads + threadIdx.x];
+                            xl = xl + a32 * pc;
+                        }
                         float pn;
                         cg_update(a32, b32, qv[i], pc, rv[i], pn);
                         Pr[i * PW] = pn;
@@ -470,7 +487,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
             // d goes to the p rows of LDS (p is no longer needed), then a row-order pass forms v_t and
             // the next defect in its place
 #pragma unroll
-            for (int i = 0; i < R; ++i) Pr[i * PW] = xv[i];
+            for (int i = 0; i < R; ++i) Pr[i * PW] = i < R - XL ? xv[i] : XS[(i - (R - XL)) * kThreads + threadIdx.x];
             __syncthreads();
             const bool ystep = (t == a.m);
             const double* so = xo;
