@@ -95,12 +95,23 @@ __global__ __launch_bounds__(kBlock2D) void sweep2d_xg_kernel(KArgs a)
     sweep2d_xg<S, EX, PER>(a, blockIdx.x, lp, red);
 }
 
+// The window a workgroup takes.  Workgroups are dealt to the eight XCDs in turn (block b to XCD
+// b mod 8), and window p reads the C-point residuals of its k slices s..p: windows p, p+1, ... share
+// k - 1 of them.  Block b takes window (b mod 8) * per + b / 8 (per = count / 8), so that every XCD
+// runs a run of consecutive windows and serves their shared slices from its own L2; the blocks past
+// 8 * per take the remaining windows in order.
+__device__ __forceinline__ int64_t xcd_window(int64_t b, int64_t count)
+{
+    const int64_t per = count / 8;
+    return b < 8 * per ? (b % 8) * per + b / 8 : b;
+}
+
 template <int S, bool EX, bool PER>
 __global__ __launch_bounds__(kBlock2D) void coarse2d_kernel(KArgs a)
 {
     __shared__ __align__(16) double lp[Lds2D<double>::size];
     __shared__ double red[4 * kWaves2D];
-    coarse2d_body<S, EX, PER>(a, blockIdx.x, lp, red);
+    coarse2d_body<S, EX, PER>(a, xcd_window(blockIdx.x, gridDim.x), lp, red);
 }
 
 template <int S, bool EX, bool PER>
@@ -117,7 +128,7 @@ __global__ __launch_bounds__(kBlock2D) void coarse2d_spec_kernel(KArgs a)
 {
     __shared__ __align__(16) double lp[Lds2D<double>::size];
     __shared__ double red[4 * kWaves2D];
-    coarse2d_body<S, EX, PER, kMaxSide2D + 2, true>(a, blockIdx.x, lp, red);
+    coarse2d_body<S, EX, PER, kMaxSide2D + 2, true>(a, xcd_window(blockIdx.x, gridDim.x), lp, red);
 }
 
 // Psi in the eigenbasis on the BF16 matrix cores: linear form, and FAS in terms of e = w - v
@@ -126,7 +137,7 @@ __global__ __launch_bounds__(kBlock2D) void coarse2d_bf_kernel(KArgs a)
 {
     __shared__ __align__(16) double lp[Lds2D<double>::size];
     __shared__ double red[4 * kWaves2D];
-    coarse2d_body<S, EX, PER, kMaxSide2D + 2, false, true, true, false>(a, blockIdx.x, lp, red);
+    coarse2d_body<S, EX, PER, kMaxSide2D + 2, false, true, true, false>(a, xcd_window(blockIdx.x, gridDim.x), lp, red);
 }
 
 template <int S, bool EX, bool PER>
@@ -134,7 +145,7 @@ __global__ __launch_bounds__(kBlock2D) void coarse2d_bf_fas_kernel(KArgs a)
 {
     __shared__ __align__(16) double lp[Lds2D<double>::size];
     __shared__ double red[4 * kWaves2D];
-    coarse2d_body<S, EX, PER, kMaxSide2D + 2, false, true, true, true>(a, blockIdx.x, lp, red);
+    coarse2d_body<S, EX, PER, kMaxSide2D + 2, false, true, true, true>(a, xcd_window(blockIdx.x, gridDim.x), lp, red);
 }
 
 template <int S, bool EX, bool PER>
