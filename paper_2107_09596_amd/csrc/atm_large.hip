@@ -220,6 +220,7 @@ struct LScratch {
     double* base;
     int64_t n;
     __device__ double* vec(int64_t task, int k) const { return base + (task * 5 + k) * n; }
+    __device__ double* flat(int64_t i) const { return base + i * n; }  // vector i of the whole scratch
 };
 
 // one FP64 step v <- Phi_c(v) in place (v global), using CG vectors x, r, p, q
@@ -403,13 +404,14 @@ __device__ __forceinline__ void gemm_f64(const double* __restrict__ A, int lda, 
 // (w % 4) N / 4 .., NT tiles of 16 x 16), over k-chunks of 16 whose A block ([k][row], pitch kAP) and B
 // rows ([k][col], pitch kBP) are staged in LDS, two buffers: the next chunk's loads are in flight
 // while the current chunk's MFMAs run.  The k order of every output's sum is that of gemm_f64.
-// CB / CC: B is read, C written, through device-coherent accesses (data shared by a pair).
+// CB / CC: B is read, C written, through device-coherent accesses (data shared by a pair).  STORE
+// false: C is not written (the epilogue consumes the products).
 constexpr int kKC = 16;
 constexpr int kAP = 64 + 2;
 constexpr int kBP = 256 + 2;
 constexpr int kGemmBuf = kKC * kAP + kKC * kBP;  // doubles of one buffer
 constexpr int kGemmLds = 2 * kGemmBuf;
-template <int NT, bool AT = false, bool CB = false, bool CC = false, typename F>
+template <int NT, bool AT = false, bool CB = false, bool CC = false, bool STORE = true, typename F>
 __device__ __forceinline__ void gemm_f64_tiled(const double* __restrict__ A, int lda, const double* __restrict__ B,
                                                int ldb, double* __restrict__ C, int ldc, int M, int K, double* lds,
                                                F&& epi)
@@ -472,7 +474,9 @@ __device__ __forceinline__ void gemm_f64_tiled(const double* __restrict__ A, int
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + rt * 16 + 4 * u + lk, j = cg * (N / 4) + t * 16 + li;
                 const double v = epi(i, j, acc[t][u]);
-                if constexpr (CC)
+                if constexpr (!STORE)
+                    (void)v;
+                else if constexpr (CC)
                     pair::put(C + (int64_t)i * ldc + j, v);
                 else
                     C[(int64_t)i * ldc + j] = v;
@@ -813,6 +817,58 @@ __global__ __launch_bounds__(kBlockL) void step_residual_large_kernel(KArgs a, L
 
 static LScratch scratch_of(const KArgs& a) { return LScratch{a.large_scratch, a.n}; }
 
+// ||M^-1 rho_i||^2 in the eigenbasis with the tiled products, the fine steps i = 1 .. nt split into
+// gridDim.x contiguous runs (one workgroup each, all CUs busy): rho_i = psi(u_{i-1}) - M u_i, then
+// |(Qy^T rho Qx) ./ mu|^2 (fine coefficients), each thread summing its entries in a fixed order.
+// Two scratch vectors per workgroup.  The square grid's products are taken transposed, X^T = rho^T Qy
+// and (X^T)^T Qx, so that the workgroup's own vectors are the left operands, read once per product
+// (the right operands, Qy and Qx, are shared by all workgroups and stay in L2); the second product's
+// entries are summed, not stored.
+template <int NT>
+__global__ __launch_bounds__(kBlockL) void step_residual_spec_kernel(KArgs a, LScratch sc)
+{
+    __shared__ double red[4 * kWavesL];
+    __shared__ double gl[kGemmLds];
+    int slot = 0;
+    const int64_t b = blockIdx.x, nb = gridDim.x;
+    const int64_t i_lo = 1 + (a.nt * b) / nb, i_hi = (a.nt * (b + 1)) / nb;  // steps i_lo .. i_hi
+    const Grid2D& g = a.g;
+    const LCol col = make_col(g);
+    const int64_t n = a.n;
+    double* __restrict__ r = sc.flat(2 * b);
+    double* __restrict__ x = sc.flat(2 * b + 1);
+    const SpecTables T = spec_tables(a);
+    const double cx2 = 2.0 * a.fine.cx, cy2 = 2.0 * a.fine.cy;
+    auto same = [](int, int, double v) { return v; };
+    double acc = 0.0;
+    for (int64_t i0 = i_lo; i0 <= i_hi; ++i0) {
+        FOR_ROWS(col, g, y)
+        {
+            const int64_t i = (int64_t)y * g.nx + col.x;
+            r[i] = explicit_part(a.fine, a.u[(i0 - 1) * n + i]) - stencil_g(g, a.fine, col, a.u + i0 * n, y);
+        }
+        __syncthreads();
+        auto scaled = [&](int i, int jj, double v) {
+            const double c = v / (1.0 + (cx2 * T.ex[jj] + cy2 * T.ey[i]));
+            acc += c * c;
+            return c;
+        };
+        if (g.nx == g.ny) {
+            gemm_f64_tiled<NT, true>(r, g.nx, T.qy, g.ny, x, g.ny, g.nx, g.ny, gl, same);      // x = (Qy^T rho)^T
+            __syncthreads();
+            gemm_f64_tiled<NT, true, false, false, false>(x, g.ny, T.qx, g.nx, r, g.nx, g.ny, g.nx, gl, scaled);
+        } else {
+            gemm_f64_tiled<NT, true>(T.qy, g.ny, r, g.nx, x, g.nx, g.ny, g.ny, gl, same);
+            __syncthreads();
+            gemm_f64_tiled<NT>(x, g.nx, T.qx, g.nx, r, g.nx, g.ny, g.nx, gl, scaled);
+        }
+        __syncthreads();
+    }
+    double unused = 0.0;
+    block_sum2(acc, unused, red, slot, kWavesL);
+    if (threadIdx.x == 0) a.partials[b] = acc;
+}
+
 __global__ __launch_bounds__(256) void sum_partials_large_kernel(KArgs a, int64_t count)
 {
     __shared__ double red[2 * 2 * 4];
@@ -909,11 +965,35 @@ void launch_sequential_large(const KArgs& a, hipStream_t s)
     hipLaunchKernelGGL(seq_large_kernel, dim3(1), dim3(kBlockL), 0, s, a, scratch_of(a));
 }
 
+static int64_t step_residual_large_blocks(const KArgs& a, int64_t n_tasks, const void* fn)
+{
+    // the eigenbasis form over the whole chip: one round of resident workgroups (a second, partial
+    // round would double the time), two scratch vectors and one partial each
+    if (!fn) return n_tasks;
+    int64_t blocks = 2 * (a.NT + 1) < kResidBlocks ? 2 * (a.NT + 1) : kResidBlocks;  // (N_T + 1) * 5 vectors
+    const int64_t resident = resident_blocks(fn, kBlockL);
+    if (resident > 0 && blocks > resident) blocks = resident;
+    if (blocks > a.nt) blocks = a.nt;
+    return blocks > 0 ? blocks : n_tasks;
+}
+
 void launch_step_residual_large(const KArgs& a, int64_t n_tasks, hipStream_t s)
 {
     if (a.spectral) launch_spectral_tables(a, s);
-    hipLaunchKernelGGL(step_residual_large_kernel, dim3(n_tasks), dim3(kBlockL), 0, s, a, scratch_of(a));
-    hipLaunchKernelGGL(sum_partials_large_kernel, dim3(1), dim3(256), 0, s, a, n_tasks);
+    const int nt = a.spectral ? spectral_nt(a.g.nx, a.g.ny) : 0;
+    const void* fn = nt == 4 ? (const void*)step_residual_spec_kernel<4>
+                   : nt == 3 ? (const void*)step_residual_spec_kernel<3>
+                   : nt == 2 ? (const void*)step_residual_spec_kernel<2> : nullptr;
+    const int64_t blocks = step_residual_large_blocks(a, n_tasks, fn);
+    if (nt == 4)
+        hipLaunchKernelGGL(step_residual_spec_kernel<4>, dim3(blocks), dim3(kBlockL), 0, s, a, scratch_of(a));
+    else if (nt == 3)
+        hipLaunchKernelGGL(step_residual_spec_kernel<3>, dim3(blocks), dim3(kBlockL), 0, s, a, scratch_of(a));
+    else if (nt == 2)
+        hipLaunchKernelGGL(step_residual_spec_kernel<2>, dim3(blocks), dim3(kBlockL), 0, s, a, scratch_of(a));
+    else
+        hipLaunchKernelGGL(step_residual_large_kernel, dim3(blocks), dim3(kBlockL), 0, s, a, scratch_of(a));
+    hipLaunchKernelGGL(sum_partials_large_kernel, dim3(1), dim3(256), 0, s, a, blocks);
 }
 
 }  // namespace atm

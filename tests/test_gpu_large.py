@@ -163,3 +163,25 @@ def test_max_1d_grid(atm, orc):
     status, hist, st = atm.atm_solve(p, o, ud)
     assert status == atm.ATM_OK and hist[-1] <= o.tol
     assert_close(host(ud), orc.sequential(p, u0), rtol=1e-10, what="1D solve vs sequential stepping")
+
+
+@pytest.mark.parametrize("case", [(W.HEAT2D, 256, 256, 12, 4, 2), (W.AC2D, 192, 128, 262, 2, 3),
+                                  (W.HEAT2D, 128, 256, 10, 2, 3)], ids=ids)
+def test_large_step_residual_norm_in_eigenbasis(atm, orc, case):
+    """|M^-1 rho| summed over all fine steps by the whole-chip eigenbasis kernel (the steps split into
+    contiguous runs, one workgroup each) equals the oracle's, on a rough iterate and on a converged one."""
+    from tests.test_gpu_mixed import rounding_floor
+    kind, nx, ny, nt, m, k = case
+    p, u0 = small(kind, nx, ny, nt)
+    o = W.Options(m=m, k=k)
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o))
+    u = W.initial_guess(p, u0, "random", seed=9) * 0.5
+    u[0] = u0
+    got = atm.atm_step_residual_norm(p, o, dev(u), ws)
+    ref = float(np.linalg.norm(orc.step_residual(p, u)))
+    assert abs(got - ref) <= 1e-12 * ref
+    seq = orc.sequential(p, u0)
+    seq[1:] += 1e-9 * np.random.default_rng(3).standard_normal(seq[1:].shape)
+    got = atm.atm_step_residual_norm(p, o, dev(seq), ws)
+    ref = float(np.linalg.norm(orc.step_residual(p, seq)))
+    assert abs(got - ref) <= 1e-11 * ref + rounding_floor(p, seq)
