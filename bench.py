@@ -35,6 +35,7 @@ if ROOT not in sys.path:
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VECTOR_TFLOPS = 157.3
+PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
 # Algorithmic HBM bytes per fine point-update of the FP32-fine / FP64-residual sweep: the stored
@@ -46,7 +47,7 @@ FLOPS_PER_CG_ITER_POINT = 18
 # HBM traffic per launch of the headline's sweep kernel (bytes read, bytes written), from rocprofv3
 # FETCH_SIZE and WRITE_SIZE on the headline workload, scaled by the same counters of a plain device
 # copy; keyed by the kernel they were taken on (a kernel without counters reports null)
-SWEEP_TRAFFIC_BYTES = {"sweep_large_mixed_kernel": (133.4e9, 87.2e9)}
+SWEEP_TRAFFIC_BYTES = {"sweep_pair_mixed_kernel": (12.009e9, 7.391e9)}
 
 
 def parse():
@@ -476,7 +477,7 @@ def main():
         step()
         log(f"warmup {i + 1}/{args.warmup}")
     torch.cuda.synchronize()
-    keys = ("ms_sweep", "ms_coarse", "ms_norm", "cg_fine", "cg_coarse", "fine_steps", "n_sweeps")
+    keys = ("ms_sweep", "ms_coarse", "ms_norm", "cg_fine", "cg_coarse", "fine_steps", "n_sweeps", "coarse_steps")
     agg = dict.fromkeys(keys, 0.0)
     last = None
     t0 = time.perf_counter()
@@ -502,12 +503,19 @@ def main():
     kernel = atm.atm_sweep_kernel(p, o)
     traffic = SWEEP_TRAFFIC_BYTES.get(kernel)
     cg_tflops = FLOPS_PER_CG_ITER_POINT * p.n * agg["cg_fine"] / (agg["ms_sweep"] / 1e3) / 1e12 if agg["ms_sweep"] else 0
+    # the windows and FAS right-hand sides: every Psi application is coarse_substeps eigenbasis solves
+    # of four FP64 products, 4 n (nx + ny) flops each, on the FP64 matrix cores
+    coarse_flops = agg["coarse_steps"] * o.coarse_substeps * 4.0 * p.n * (p.nx + p.ny)
+    coarse_tflops = coarse_flops / (agg["ms_coarse"] / 1e3) / 1e12 if agg["ms_coarse"] else 0.0
     roofline = {
         "kernel": kernel, "bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
         "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
         "traffic": None if traffic is None else sum(traffic),
         "bytes_per_launch": bytes_launch, "avg_launch_ms": round(avg_ms, 4), "launches_per_step": launches / args.steps,
         "fp32_cg": {"achieved": round(cg_tflops, 2), "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s"},
+        "coarse_mfma": {"kernel": atm.atm_coarse_kernel(p, o), "bound": "mfma", "achieved": round(coarse_tflops, 2),
+                        "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(coarse_tflops / PEAK_FP64_MFMA_TFLOPS, 4)},
     }
     record = {"headline": {"phase_ms": {k: agg[k] / args.steps for k in ("ms_sweep", "ms_coarse", "ms_norm")},
                            "cg_iters": {"fine": agg["cg_fine"] / args.steps, "coarse": agg["cg_coarse"] / args.steps},
