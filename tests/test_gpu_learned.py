@@ -132,8 +132,8 @@ def test_learned_fallback_to_plain(atm, orc):
 def test_trained_network_learns_the_coarse_map(atm, orc):
     """Train on the GPU on pairs of the fine propagator (32 x 32 periodic Allen-Cahn, lag m = 8).  On
     held-out pairs the learned Psi must be far closer to Phi^m than the identity; its error against the
-    plain coarse step's is printed.  The learned solve reaches the plain solve's fixed point, and the
-    cycle counts of both are printed (what the trained network gains or costs)."""
+    plain coarse step's is printed.  The learned solve reaches the plain solve's fixed point and takes
+    no fewer cycles than the plain one (the measured loss; both counts are printed)."""
     import torch
     from paper_2107_09596_amd import learned
     p = W.Problem(W.AC2D, nx=32, ny=32, nu=1.0, eps=0.06, tf=256 * 1e-4, nt=256, cg_rtol=1e-12)
@@ -170,4 +170,9 @@ def test_trained_network_learns_the_coarse_map(atm, orc):
     _, hp, sp = atm.atm_solve(p, o, up)
     print(f"cycles: learned {sl['iterations']} ({sl['learned_cycles']} learned), plain {sp['iterations']}")
     assert hl[-1] <= o.tol and hp[-1] <= o.tol
+    # the measured outcome: a network far better than the identity on held-out pairs still does not
+    # take fewer cycles than the plain coarse step (the two-level rate depends on how Psi treats the
+    # slowly varying error, where the one-step fit is weakest), so with one application costing tens
+    # of plain steps it cannot pay in wall time
+    assert sl["iterations"] >= sp["iterations"]
     assert np.max(np.abs(host(ul) - host(up))) <= 1e-7
