@@ -401,15 +401,21 @@ __device__ __forceinline__ void gemm_f64(const double* __restrict__ A, int lda, 
 
 // The same product for M and K multiples of 64 and N = 64 NT (NT <= 4), MFMA-bound: 64-row blocks of
 // C, each computed by 16 waves (wave w: the 16 rows 16 (w / 4) .. of the block and the N / 4 columns
-// (w % 4) N / 4 .., NT tiles of 16 x 16), over k-chunks of 16 whose A block ([k][row], pitch kAP) and B
-// rows ([k][col], pitch kBP) are staged in LDS, two buffers: the next chunk's loads are in flight
-// while the current chunk's MFMAs run.  The k order of every output's sum is that of gemm_f64.
+// (w % 4) N / 4 .., NT tiles of 16 x 16), over k-chunks of 16 whose A block and B rows ([k][col], pitch
+// kBP) are staged in LDS, two buffers: the next chunk's loads are in flight while the current chunk's
+// MFMAs run.  The A block is kept as the global A is read -- [k][row] (pitch kAPT) when A is given
+// transposed, [row][k] (pitch kAPN) otherwise -- so that its stores take consecutive addresses.  The
+// pitches put the 32 lanes of a fragment read (16 consecutive entries at k and 16 at k + 1) on distinct
+// banks of the 64-bank LDS: 16 mod 32 doubles for the [k][..] layouts, 2 mod 32 for [row][k].  The k
+// order of every output's sum is that of gemm_f64.
 // CB / CC: B is read, C written, through device-coherent accesses (data shared by a pair).  STORE
 // false: C is not written (the epilogue consumes the products).
 constexpr int kKC = 16;
-constexpr int kAP = 64 + 2;
-constexpr int kBP = 256 + 2;
-constexpr int kGemmBuf = kKC * kAP + kKC * kBP;  // doubles of one buffer
+constexpr int kAPT = 64 + 16;
+constexpr int kAPN = kKC + 2;
+constexpr int kBP = 256 + 16;
+constexpr int kABuf = kKC * kAPT > 64 * kAPN ? kKC * kAPT : 64 * kAPN;  // doubles of the A block
+constexpr int kGemmBuf = kABuf + kKC * kBP;                             // doubles of one buffer
 constexpr int kGemmLds = 2 * kGemmBuf;
 template <int NT, bool AT = false, bool CB = false, bool CC = false, bool STORE = true, typename F>
 __device__ __forceinline__ void gemm_f64_tiled(const double* __restrict__ A, int lda, const double* __restrict__ B,
@@ -439,8 +445,8 @@ __device__ __forceinline__ void gemm_f64_tiled(const double* __restrict__ A, int
         };
         auto stage = [&](int buf) {
             double* As = lds + buf * kGemmBuf;
-            double* Bs = As + kKC * kAP;
-            As[ak * kAP + ar] = ra;
+            double* Bs = As + kABuf;
+            As[AT ? ak * kAPT + ar : ar * kAPN + ak] = ra;
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
                 const int e = tid + q * kBlockL;
@@ -454,11 +460,11 @@ __device__ __forceinline__ void gemm_f64_tiled(const double* __restrict__ A, int
             const int buf = kc & 1;
             if (kc + 1 < nkc) load((kc + 1) * kKC);
             const double* As = lds + buf * kGemmBuf;
-            const double* Bs = As + kKC * kAP;
+            const double* Bs = As + kABuf;
 #pragma unroll
             for (int q = 0; q < kKC / 4; ++q) {
                 const int k = 4 * q + lk;
-                const double fa = As[k * kAP + rt * 16 + li];
+                const double fa = AT ? As[k * kAPT + rt * 16 + li] : As[(rt * 16 + li) * kAPN + k];
 #pragma unroll
                 for (int t = 0; t < NT; ++t) {
                     const double fb = Bs[k * kBP + cg * (N / 4) + t * 16 + li];
