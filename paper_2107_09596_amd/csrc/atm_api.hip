@@ -1106,11 +1106,22 @@ atm_status upload_tables(atm_batch* B)
     return ATM_OK;
 }
 
-// launches of the given phases, one branch stream per class, joined on the main stream
+// launches of the given phases, one branch stream per class present, joined on the main stream; with a
+// single class present they go to the main stream itself (no fork or join to record or replay)
 atm_status enqueue_phases(atm_batch* B, const int* phases, int nphases)
 {
-    ATM_HIP(hipEventRecord(B->fork, B->main));
-    for (int c = 0; c < NCLS; ++c) ATM_HIP(hipStreamWaitEvent(B->br[c], B->fork, 0));
+    bool used[NCLS] = {false, false, false};
+    for (int q = 0; q < nphases; ++q)
+        for (const Group& g : B->groups)
+            if (g.phase == phases[q]) used[g.cls] = true;
+    int nused = 0;
+    for (int c = 0; c < NCLS; ++c) nused += used[c] ? 1 : 0;
+    const bool fork = nused > 1;
+    if (fork) {
+        ATM_HIP(hipEventRecord(B->fork, B->main));
+        for (int c = 0; c < NCLS; ++c)
+            if (used[c]) ATM_HIP(hipStreamWaitEvent(B->br[c], B->fork, 0));
+    }
     for (int q = 0; q < nphases; ++q)
         for (const Group& g : B->groups) {
             if (g.phase != phases[q]) continue;
@@ -1121,12 +1132,14 @@ atm_status enqueue_phases(atm_batch* B, const int* phases, int nphases)
             l.ctl = B->ctl_dev;
             l.nchunk = B->nchunk_dev;
             const bool per = g.cls == CLS_2DP;
-            atm::batch::launch_tasks(g.body, g.S, per, g.small, l, B->br[g.cls]);
+            atm::batch::launch_tasks(g.body, g.S, per, g.small, l, fork ? B->br[g.cls] : B->main);
         }
-    for (int c = 0; c < NCLS; ++c) {
-        ATM_HIP(hipEventRecord(B->join[c], B->br[c]));
-        ATM_HIP(hipStreamWaitEvent(B->main, B->join[c], 0));
-    }
+    if (fork)
+        for (int c = 0; c < NCLS; ++c)
+            if (used[c]) {
+                ATM_HIP(hipEventRecord(B->join[c], B->br[c]));
+                ATM_HIP(hipStreamWaitEvent(B->main, B->join[c], 0));
+            }
     return check_launch();
 }
 
