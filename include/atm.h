@@ -143,14 +143,6 @@ typedef struct atm_options {
                               F-relaxes them, a level between getting one V-cycle of its own system.
                               Precision 0, grids up to 128 per side, no source, not the learned
                               propagator; its time is atm_stats.ms_setup */
-    int32_t cg_guess;      /* where the CG of a fine step starts (2D kinds, precision 0, two levels,
-                              grids up to 128 per side; the 1D step is a direct solve).  0: from the
-                              previous time point's value.  1: the F-points of a sweep that moves C-point
-                              j start from the stored iterate moved by the change the sweep has made at
-                              the previous point, u_t + (x_{t-1} - u_{t-1}), x the new values; the step
-                              that forms Phi of the last F-point (the residual) starts from x_{m-1}.  Both
-                              solve to the problem's cg_rtol; 1 needs fewer iterations once the
-                              corrections are small against the iterate.  Not with the batch API */
 } atm_options;
 
 typedef struct atm_stats {

@@ -38,7 +38,6 @@ class OrOptions(ctypes.Structure):
         ("tol", ctypes.c_double), ("coarse_cg_rtol", ctypes.c_double),
         ("m", ctypes.c_int32), ("k", ctypes.c_int32), ("relax", ctypes.c_int32),
         ("max_iter", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32), ("coarse_form", ctypes.c_int32),
-        ("cg_guess", ctypes.c_int32),
     ]
 
 
@@ -108,7 +107,6 @@ def lib():
             "or_coarse_step": (ctypes.c_int, [P, O, dp, dp, i64p]),
             "or_sequential": (ctypes.c_int, [P, dp, i64p]),
             "or_f_relax": (ctypes.c_int, [P, O, dp, i64p]),
-            "or_f_relax_from": (ctypes.c_int, [P, O, dp, dp, ctypes.c_int, i64p]),
             "or_c_relax": (ctypes.c_int, [P, O, dp, i64p]),
             "or_residual": (ctypes.c_int, [P, dp, dp, dp, i64p]),
             "or_norm2": (ctypes.c_double, [ctypes.c_int64, dp]),
@@ -153,8 +151,7 @@ def _src(source):
 def _opts(o) -> OrOptions:
     return OrOptions(tol=o.tol, coarse_cg_rtol=getattr(o, "coarse_cg_rtol", 0.0), m=o.m, k=o.k, relax=o.relax,
                      max_iter=o.max_iter,
-                     coarse_substeps=o.coarse_substeps, coarse_form=o.coarse_form,
-                     cg_guess=int(getattr(o, "cg_guess", 0)))
+                     coarse_substeps=o.coarse_substeps, coarse_form=o.coarse_form)
 
 
 def _ml_opts(o) -> OrMlOptions:
@@ -220,18 +217,11 @@ def sequential(p, u0, source=None):
     return u
 
 
-def f_relax(p, o, u, source=None, c_old=None, skip=False):
-    """F-relaxation of every interval.  c_old: the C-point values [N_T+1, n] before the caller changed
-    them (their changes start the extrapolated CG guess of o.cg_guess = 1); skip: u's F-points are the
-    relaxation from c_old, and intervals whose C-point equals it keep them."""
+def f_relax(p, o, u, source=None):
+    """F-relaxation of every interval: each F-point is Phi of the point before it."""
     src = _src(source)
     u = np.array(u, dtype=np.float64, order="C")
-    if c_old is None:
-        _check(lib().or_f_relax(ctypes.byref(_prob(p, src)), ctypes.byref(_opts(o)), _ptr(u), None), "f_relax")
-    else:
-        c_old = np.ascontiguousarray(c_old, dtype=np.float64)
-        _check(lib().or_f_relax_from(ctypes.byref(_prob(p, src)), ctypes.byref(_opts(o)), _ptr(u), _ptr(c_old),
-                                     int(bool(skip)), None), "f_relax")
+    _check(lib().or_f_relax(ctypes.byref(_prob(p, src)), ctypes.byref(_opts(o)), _ptr(u), None), "f_relax")
     return u
 
 

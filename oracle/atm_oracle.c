@@ -40,14 +40,9 @@
  *   - Phi for the 2D problems is one backward-Euler (heat) or IMEX
  *     (Allen-Cahn) step whose linear system (I - dt nu L_h) is solved by
  *     Jacobi-preconditioned CG started from the input state, stopped when the
- *     recursively updated residual satisfies ||r|| <= rtol ||b||.  With
- *     cg_guess = 1 an F-relaxation pass starts the solve of F-point t from the
- *     iterate's previous value there moved by the change the pass made at t-1.
- *   - Inside a solve the iterate is F-relaxed after the initial F-relaxation
- *     and after every correction, and F-relaxation of an F-relaxed iterate
- *     leaves it as it is: the leading F-relaxation of later cycles is not
- *     repeated, and a pass keeps the F-points of every interval whose C-point
- *     it has not changed.
+ *     recursively updated residual satisfies ||r|| <= rtol ||b||.
+ *   - Every cycle runs its whole F(CF)^nu relaxation, the leading F-relaxation
+ *     included, and every F-relaxation steps every interval from its C-point.
  *   - Psi is coarse_substeps steps of size m dt / coarse_substeps of the same
  *     integrator (a re-discretisation with step dT, section 2.1 end); its CG
  *     tolerance is coarse_cg_rtol when set (Psi only approximates Phi^m, so its
@@ -78,7 +73,6 @@ typedef struct {
     double tol;
     double coarse_cg_rtol; /* CG tolerance inside Psi; 0 means the fine cg_rtol */
     int32_t m, k, relax, max_iter, coarse_substeps, coarse_form;
-    int32_t cg_guess; /* 1: F-point solves start from the extrapolated iterate (see f_relax_interval) */
 } or_options;
 
 typedef struct {
@@ -244,17 +238,16 @@ static void apply_M_fine(const or_problem* P, const double* x, double* y)
    (NULL: no source), the linear systems of the 2D kinds solved to relative
    tolerance rtol.  work must hold 6n doubles.  out may not alias in. */
 static int step_dt_tol(const or_problem* P, double dt, double rtol, const double* in, const double* f,
-                       const double* x0, double* out, double* work, int64_t* cg_its);
+                       double* out, double* work, int64_t* cg_its);
 
 static int step_dt(const or_problem* P, double dt, const double* in, const double* f, double* out,
                    double* work, int64_t* cg_its)
 {
-    return step_dt_tol(P, dt, P->cg_rtol, in, f, NULL, out, work, cg_its);
+    return step_dt_tol(P, dt, P->cg_rtol, in, f, out, work, cg_its);
 }
 
-/* x0: where the CG of a 2D step starts (NULL: from in) */
 static int step_dt_tol(const or_problem* P, double dt, double rtol, const double* in, const double* f,
-                       const double* x0, double* out, double* work, int64_t* cg_its)
+                       double* out, double* work, int64_t* cg_its)
 {
     const int64_t n = nspace(P);
     double* b = work + 4 * n;
@@ -268,7 +261,7 @@ static int step_dt_tol(const or_problem* P, double dt, double rtol, const double
     }
     const double hx = spacing(P, P->nx), hy = spacing(P, P->ny);
     const double cx = P->nu * dt / (hx * hx), cy = P->nu * dt / (hy * hy);
-    for (int64_t i = 0; i < n; ++i) out[i] = x0 ? x0[i] : in[i];
+    for (int64_t i = 0; i < n; ++i) out[i] = in[i];
     return pcg2d(P, cx, cy, rtol, b, out, work, cg_its);
 }
 
@@ -280,14 +273,6 @@ static int fine_step(const or_problem* P, int64_t i, const double* in, double* o
                      int64_t* cg)
 {
     return step_dt(P, step_size(P), in, P->src ? P->src + i * nspace(P) : NULL, out, work, cg);
-}
-
-/* the same step with its linear solve started from x0 */
-static int fine_step_from(const or_problem* P, int64_t i, const double* in, const double* x0, double* out,
-                          double* work, int64_t* cg)
-{
-    return step_dt_tol(P, step_size(P), P->cg_rtol, in, P->src ? P->src + i * nspace(P) : NULL, x0, out, work,
-                       cg);
 }
 
 /* Psi: the coarse propagator, a re-discretisation with dT = m dt taken in s substeps. */
@@ -302,7 +287,7 @@ static int coarse_step(const or_problem* P, const or_options* O, const double* i
     const double* src = in;
     for (int i = 0; i < s; ++i) {
         double* dst = (i == s - 1) ? out : tmp + (i & 1) * n;
-        int st = step_dt_tol(P, dts, rtol, src, NULL, NULL, dst, work, cg);
+        int st = step_dt_tol(P, dts, rtol, src, NULL, dst, work, cg);
         if (st) return st;
         src = dst;
     }
@@ -365,43 +350,17 @@ static int64_t interval_end(const or_problem* P, const or_options* O, int64_t j)
 /* relaxation (section 2.1; F(CF)^nu, section 2.2)                           */
 /* ------------------------------------------------------------------------ */
 
-/* F-relaxation of one interval: u_{jm+i} = Phi(u_{jm+i-1}) for its F-points.
-   c_old (nullable, [N_T+1][n]) holds the C-point values before the pass changed
-   them (NULL: unchanged).  skip: the F-points already hold the relaxation from
-   c_old, so an interval whose C-point still equals c_old (bit for bit) keeps
-   them.  Where the paper leaves the inner solve open: with cg_guess = 1 the
-   linear solve of F-point t (2D kinds) starts from u_t + (u'_{t-1} - u_{t-1}),
-   the value the iterate held at t moved by the change the pass has made at t-1
-   (u' the new values); otherwise from u'_{t-1}.  work: relax_work_len doubles. */
-static int f_relax_interval(const or_problem* P, const or_options* O, double* u, int64_t j,
-                            const double* c_old, int skip, double* work, int64_t* cg)
+/* F-relaxation of one interval: u_{jm+i} = Phi(u_{jm+i-1}) for its F-points, in
+   order.  work: work_len doubles. */
+static int f_relax_interval(const or_problem* P, const or_options* O, double* u, int64_t j, double* work,
+                            int64_t* cg)
 {
     const int64_t n = nspace(P);
-    const double* uc = u + j * O->m * n;
-    const double* co = c_old ? c_old + j * n : uc;
-    if (skip) {
-        int same = 1;
-        for (int64_t x = 0; x < n && same; ++x) same = !(uc[x] != co[x]);
-        if (same) return OR_OK;
-    }
-    const int extrap = O->cg_guess == 1 && P->kind != OR_HEAT1D;
-    double* prev_old = work + work_len(P); /* u_{t-1} before the pass */
-    double* x0 = prev_old + n;
-    if (extrap) memcpy(prev_old, co, sizeof(double) * n);
     int st = OR_OK;
-    for (int64_t i = j * O->m + 1; i <= interval_end(P, O, j) && st == OR_OK; ++i) {
-        if (!extrap) {
-            st = fine_step(P, i, u + (i - 1) * n, u + i * n, work, cg);
-            continue;
-        }
-        for (int64_t x = 0; x < n; ++x) x0[x] = u[i * n + x] + (u[(i - 1) * n + x] - prev_old[x]);
-        memcpy(prev_old, u + i * n, sizeof(double) * n);
-        st = fine_step_from(P, i, u + (i - 1) * n, x0, u + i * n, work, cg);
-    }
+    for (int64_t i = j * O->m + 1; i <= interval_end(P, O, j) && st == OR_OK; ++i)
+        st = fine_step(P, i, u + (i - 1) * n, u + i * n, work, cg);
     return st;
 }
-
-static int64_t relax_work_len(const or_problem* P) { return work_len(P) + 2 * nspace(P); }
 
 static int64_t n_relax_intervals(const or_problem* P, const or_options* O)
 {
@@ -410,20 +369,19 @@ static int64_t n_relax_intervals(const or_problem* P, const or_options* O)
     return (NT * O->m < P->nt) ? NT + 1 : NT;
 }
 
-/* F-relaxation of every interval (c_old and skip as for f_relax_interval) */
-int or_f_relax_from(const or_problem* P, const or_options* O, double* u, const double* c_old, int skip,
-                    int64_t* cg)
+/* F-relaxation of every interval (the intervals are independent) */
+int or_f_relax(const or_problem* P, const or_options* O, double* u, int64_t* cg)
 {
     const int64_t NI = n_relax_intervals(P, O);
     int status = OR_OK;
     int64_t cg_total = 0;
 #pragma omp parallel num_threads(g_threads) reduction(+ : cg_total)
     {
-        double* work = malloc(sizeof(double) * relax_work_len(P));
+        double* work = malloc(sizeof(double) * work_len(P));
 #pragma omp for schedule(dynamic, 1)
         for (int64_t j = 0; j < NI; ++j) {
             int64_t c = 0;
-            int st = f_relax_interval(P, O, u, j, c_old, skip, work, &c);
+            int st = f_relax_interval(P, O, u, j, work, &c);
             cg_total += c;
             if (st) {
 #pragma omp critical
@@ -434,11 +392,6 @@ int or_f_relax_from(const or_problem* P, const or_options* O, double* u, const d
     }
     if (cg) *cg += cg_total;
     return status;
-}
-
-int or_f_relax(const or_problem* P, const or_options* O, double* u, int64_t* cg)
-{
-    return or_f_relax_from(P, O, u, NULL, 0, cg);
 }
 
 /* C-relaxation: u_{jm} = Phi(u_{jm-1}) for every C-point j >= 1. */
@@ -668,27 +621,13 @@ int or_local_solves(const or_problem* P, const or_options* O, const double* rc, 
 
 /* Correction u = u + P_S^(p) e_p for every p: add e_p to C-point p, then
    F-relax the interval that follows it (selective ideal interpolation). */
-static void inject(const or_problem* P, const or_options* O, const double* v, double* out);
-
-/* skip: u is F-relaxed, and intervals whose C-point e leaves unchanged keep their F-points */
-static int correct_pass(const or_problem* P, const or_options* O, double* u, const double* e, int skip,
-                        int64_t* cg)
+int or_correct(const or_problem* P, const or_options* O, double* u, const double* e, int64_t* cg)
 {
     const int64_t n = nspace(P);
     const int64_t NT = or_num_intervals(P, O);
-    double* c_old = malloc(sizeof(double) * (NT + 1) * n);
-    if (!c_old) return OR_INVALID;
-    inject(P, O, u, c_old);
     for (int64_t p = 0; p <= NT; ++p)
         for (int64_t x = 0; x < n; ++x) u[p * O->m * n + x] += e[p * n + x];
-    int st = or_f_relax_from(P, O, u, c_old, skip, cg);
-    free(c_old);
-    return st;
-}
-
-int or_correct(const or_problem* P, const or_options* O, double* u, const double* e, int64_t* cg)
-{
-    return correct_pass(P, O, u, e, 0, cg);
+    return or_f_relax(P, O, u, cg);
 }
 
 /* C-point injection R_I of a space-time vector: out_j = v_{jm}. */
@@ -704,7 +643,7 @@ static void inject(const or_problem* P, const or_options* O, const double* v, do
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-    double *r, *rc, *vc, *e, *cold;
+    double *r, *rc, *vc, *e;
 } buffers;
 
 static int alloc_buffers(const or_problem* P, const or_options* O, buffers* B)
@@ -715,8 +654,7 @@ static int alloc_buffers(const or_problem* P, const or_options* O, buffers* B)
     B->rc = malloc(sizeof(double) * (NT + 1) * n);
     B->vc = malloc(sizeof(double) * (NT + 1) * n);
     B->e = malloc(sizeof(double) * (NT + 1) * n);
-    B->cold = malloc(sizeof(double) * (NT + 1) * n);
-    return (B->r && B->rc && B->vc && B->e && B->cold) ? OR_OK : OR_INVALID;
+    return (B->r && B->rc && B->vc && B->e) ? OR_OK : OR_INVALID;
 }
 
 static void free_buffers(buffers* B)
@@ -725,27 +663,19 @@ static void free_buffers(buffers* B)
     free(B->rc);
     free(B->vc);
     free(B->e);
-    free(B->cold);
 }
 
-/* F(CF)^nu relaxation.  relaxed: u is F-relaxed already (inside a solve, after
-   the initial F-relaxation or a correction), so the leading F-relaxation would
-   leave it as it is and is not repeated, and the F-relaxation after the
-   C-relaxation keeps the intervals whose C-point it left unchanged. */
-static int relax(const or_problem* P, const or_options* O, double* u, or_stats* S, int relaxed, double* c_old)
+/* F(CF)^nu relaxation (nu = relax: 0 or 1) */
+static int relax(const or_problem* P, const or_options* O, double* u, or_stats* S)
 {
     const int64_t NT = or_num_intervals(P, O);
-    int st = OR_OK;
-    if (!relaxed) {
-        st = or_f_relax(P, O, u, &S->cg_iters);
-        S->fine_steps += P->nt - NT;
-    }
+    int st = or_f_relax(P, O, u, &S->cg_iters);
+    S->fine_steps += P->nt - NT;
     if (st || O->relax == 0) return st;
-    inject(P, O, u, c_old);
     st = or_c_relax(P, O, u, &S->cg_iters);
     S->fine_steps += NT;
     if (st) return st;
-    st = or_f_relax_from(P, O, u, c_old, relaxed, &S->cg_iters);
+    st = or_f_relax(P, O, u, &S->cg_iters);
     S->fine_steps += P->nt - NT;
     return st;
 }
@@ -757,9 +687,9 @@ static int global_coarse_solve(const or_problem* P, const or_options* O, const d
                                const double* vc, double* e, or_stats* S);
 
 static int cycle(const or_problem* P, const or_options* O, double* u, const double* g0, buffers* B,
-                 or_stats* S, int global, int relaxed)
+                 or_stats* S, int global)
 {
-    int st = relax(P, O, u, S, relaxed, B->cold);
+    int st = relax(P, O, u, S);
     if (st) return st;
     if ((st = or_residual(P, u, g0, B->r, &S->cg_iters))) return st;
     S->fine_steps += P->nt;
@@ -770,7 +700,7 @@ static int cycle(const or_problem* P, const or_options* O, double* u, const doub
     else
         st = or_local_solves(P, O, B->rc, B->vc, B->e, &S->cg_iters, &S->coarse_steps);
     if (st) return st;
-    st = correct_pass(P, O, u, B->e, relaxed, &S->cg_iters);
+    st = or_correct(P, O, u, B->e, &S->cg_iters);
     S->fine_steps += P->nt - or_num_intervals(P, O);
     return st;
 }
@@ -779,7 +709,7 @@ int or_cycle(const or_problem* P, const or_options* O, double* u, const double* 
 {
     buffers B;
     if (alloc_buffers(P, O, &B)) return OR_INVALID;
-    int st = cycle(P, O, u, g0, &B, S, 0, 0);
+    int st = cycle(P, O, u, g0, &B, S, 0);
     free_buffers(&B);
     return st;
 }
@@ -826,7 +756,7 @@ static int solve(const or_problem* P, const or_options* O, double* u, double* hi
             st = OR_NOT_CONVERGED;
             break;
         }
-        st = cycle(P, O, u, g0, &B, S, global, 1);
+        st = cycle(P, O, u, g0, &B, S, global);
         if (st) break;
         ++it;
         st = residual_norm(P, O, u, g0, &B, S, &res);
@@ -902,7 +832,7 @@ int or_parareal_cycle(const or_problem* P, const or_options* O, double* u, const
 {
     buffers B;
     if (alloc_buffers(P, O, &B)) return OR_INVALID;
-    int st = cycle(P, O, u, g0, &B, S, 1, 0);
+    int st = cycle(P, O, u, g0, &B, S, 1);
     free_buffers(&B);
     return st;
 }
@@ -966,7 +896,7 @@ static int ml_step(const or_problem* P, const ml_level* L, int64_t i, const doub
     const double* src = in;
     for (int q = 0; q < L->substeps; ++q) {
         double* dst = (q == L->substeps - 1) ? out : tmp + (q & 1) * n;
-        int st = step_dt_tol(P, L->dt / L->substeps, L->rtol, src, NULL, NULL, dst, work, cg);
+        int st = step_dt_tol(P, L->dt / L->substeps, L->rtol, src, NULL, dst, work, cg);
         if (st) return st;
         src = dst;
     }

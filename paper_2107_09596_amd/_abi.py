@@ -43,7 +43,6 @@ class AtmOptions(ctypes.Structure):
         ("max_iter", ctypes.c_int32), ("coarse_substeps", ctypes.c_int32), ("coarse_form", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("profile", ctypes.c_int32), ("coarse_solver", ctypes.c_int32),
         ("levels", ctypes.c_int32), ("m_coarse", ctypes.c_int32), ("nested", ctypes.c_int32),
-        ("cg_guess", ctypes.c_int32),
     ]
 
 
@@ -163,5 +162,4 @@ def options(o) -> AtmOptions:
                       max_iter=o.max_iter, coarse_substeps=o.coarse_substeps, coarse_form=o.coarse_form,
                       precision=getattr(o, "precision", 0), profile=int(getattr(o, "profile", 0)),
                       coarse_solver=int(getattr(o, "coarse_solver", 0)), levels=int(getattr(o, "levels", 2)),
-                      m_coarse=int(getattr(o, "m_coarse", 0)), nested=int(getattr(o, "nested", 0)),
-                      cg_guess=int(getattr(o, "cg_guess", 0)))
+                      m_coarse=int(getattr(o, "m_coarse", 0)), nested=int(getattr(o, "nested", 0)))

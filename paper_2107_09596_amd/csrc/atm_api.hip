@@ -229,13 +229,6 @@ atm_status validate(const atm_problem* p, const atm_options* o)
         if (o->coarse_form == 3) return fail(ATM_ERR_UNSUPPORTED, "nested iteration uses the plain coarse propagator");
         if (large_grid(p)) return fail(ATM_ERR_UNSUPPORTED, "nested iteration takes grids up to 128 x 128");
     }
-    if (o->cg_guess != 0 && o->cg_guess != 1) return fail(ATM_ERR_INVALID_ARG, "cg_guess must be 0 or 1");
-    if (o->cg_guess == 1) {
-        if (o->precision != 0) return fail(ATM_ERR_UNSUPPORTED, "cg_guess 1 applies to precision 0");
-        if (o->levels == 3 || o->nested == 1)
-            return fail(ATM_ERR_UNSUPPORTED, "cg_guess 1 applies to two levels without nested iteration");
-        if (large_grid(p)) return fail(ATM_ERR_UNSUPPORTED, "cg_guess 1 takes grids up to 128 x 128");
-    }
     if (!(o->tol >= 0.0)) return fail(ATM_ERR_INVALID_ARG, "tol must be >= 0");
     if (o->precision != 0 && o->precision != 1) return fail(ATM_ERR_INVALID_ARG, "precision must be 0 or 1");
     if (o->precision == 1 && p->kind == ATM_HEAT1D)
@@ -310,7 +303,6 @@ atm_status make_args_in(const atm_problem* p, const atm_options* o, void* ws, si
     a.gadd = nullptr;
     a.fine_substeps = 1;
     a.psi_only = 0;
-    a.cg_guess = (o->cg_guess == 1 && p->kind != ATM_HEAT1D) ? 1 : 0;
     a.fine = step_coef(p, dt);
     a.coarse = step_coef(p, dt * o->m / o->coarse_substeps);
     a.rtol2 = p->cg_rtol * p->cg_rtol;
@@ -698,7 +690,6 @@ atm::KArgs level1_args(const atm::KArgs& a0, const atm_problem* p, const atm_opt
     a1.cg_count = &a0.hdr->cg_coarse;
     a1.skip_unchanged = 0;
     a1.skip_y_src = nullptr;
-    a1.cg_guess = 0;
     a1.spectral = ml_bf(p, o) ? 2 : 0;
     a1.cres = ml_bf(p, o) ? (double*)(base + L.cres) : nullptr;
     return a1;
@@ -981,7 +972,6 @@ atm_status describe(int32_t n, const atm_problem* probs, const atm_options* opts
         if (large_grid(&in.p)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take grids up to 128 x 128", i);
         if (in.p.source) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take no PDE source", i);
         if (three_level(&in.o)) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches run two levels", i);
-        if (in.o.cg_guess != 0) return fail(ATM_ERR_UNSUPPORTED, "instance %d: batches take cg_guess 0", i);
         in.cls = in.p.kind == ATM_HEAT1D ? CLS_1D : (in.p.kind == ATM_AC2D ? CLS_2DP : CLS_2D);
         if (in.cls == CLS_1D && in.p.nx > 512)
             return fail(ATM_ERR_UNSUPPORTED, "instance %d: 1D batch instances take nx <= 512", i);

@@ -93,65 +93,6 @@ __device__ __forceinline__ int step2d(const KArgs& a, const StepCoef& c, double 
     return cg2d<double, S, EX, PER, true>(a.g, c, st, v.x, v.r, v.q, lp, red, slot, rtol2, a.maxit, a.fail);
 }
 
-// XG: the CG of F-point t starts from u_t + (x_{t-1} - u_{t-1}), u the stored iterate before the
-// sweep and x the sweep's new values; the y-step starts from x_{m-1}.  The store of x_{t-1} waits
-// until step t has read u_{t-1}, the C-point's (modes 1 and 2) included.
-template <int S, bool EX, bool PER>
-__device__ __forceinline__ void sweep2d_xg(const KArgs& a, int64_t j, double* lp, double* red)
-{
-    int slot = 0;
-    const Strip st = make_strip<double>(a.g);
-    lds_clear<kMaxSide2D + 2>(lp);
-    Strip2DState<S> v;
-    const int nx = a.g.nx;
-    bool same = true;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        v.x[s] = 0.0;
-        if (row_ok<EX, S>(st, s)) {
-            const int64_t idx = (int64_t)(st.gbase + s * nx);
-            v.x[s] = sweep_start(a, j, idx);
-            same = same && !(v.x[s] != a.u[(j * a.m) * a.n + idx]);
-        }
-    }
-    const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
-    if (a.skip_unchanged && __syncthreads_and(same)) {
-        skip_interval(a, j, total, st.gbase, nx, EX ? S : st.nr);
-        return;
-    }
-    long long its = 0;
-    for (int64_t t = 1; t <= total; ++t) {
-        const StepCoef& c = a.fine;
-#pragma unroll
-        for (int s = 0; s < S; ++s) v.r[s] = explicit_part(c, v.x[s]);
-        double* prev = a.u + (j * a.m + t - 1) * a.n;
-        const bool wr = t > 1 || a.mode != 0;
-        const int64_t off = opaque_off(st.gbase);
-        if (t < a.m) {
-            const double* cur = a.u + (j * a.m + t) * a.n;
-#pragma unroll
-            for (int s = 0; s < S; ++s)
-                if (row_ok<EX, S>(st, s)) {
-                    const int64_t o = off + (int64_t)s * nx;
-                    const double keep = v.x[s];
-                    v.x[s] = cur[o] + (keep - prev[o]);
-                    v.q[s] = keep;
-                }
-            if (wr) strip_store<S, EX>(prev, st, nx, v.q);
-        } else if (wr) {
-            strip_store<S, EX>(prev, st, nx, v.x);
-        }
-        its += cg2d<double, S, EX, PER, true>(a.g, c, st, v.x, v.r, v.q, lp, red, slot, a.rtol2, a.maxit, a.fail);
-    }
-    if (total > 0) {
-        double* dst = (total < a.m) ? a.u + (j * a.m + total) * a.n : a.y + (j + 1) * a.n;
-        strip_store<S, EX>(dst, st, nx, v.x);
-    } else if (a.mode != 0) {
-        strip_store<S, EX>(a.u + (j * a.m) * a.n, st, nx, v.x);
-    }
-    count_cg(a, its);
-}
-
 // LV: a level below the finest (substeps and the additive FAS right-hand side of the multilevel
 // cycle); a separate instantiation keeps the finest level's kernel as it is
 template <int S, bool EX, bool PER, int COLS = kMaxSide2D + 2, bool LV = false>

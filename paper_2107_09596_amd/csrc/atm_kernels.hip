@@ -86,15 +86,6 @@ __global__ __launch_bounds__(kBlock2D) void sweep2d_lv_kernel(KArgs a)
     sweep2d_body<S, EX, PER, kMaxSide2D + 2, true>(a, blockIdx.x, lp, red);
 }
 
-// the finest level with the CG of each F-point started from the extrapolated iterate
-template <int S, bool EX, bool PER>
-__global__ __launch_bounds__(kBlock2D) void sweep2d_xg_kernel(KArgs a)
-{
-    __shared__ __align__(16) double lp[Lds2D<double>::size];
-    __shared__ double red[4 * kWaves2D];
-    sweep2d_xg<S, EX, PER>(a, blockIdx.x, lp, red);
-}
-
 // The window a workgroup takes.  Workgroups are dealt to the eight XCDs in turn (block b to XCD
 // b mod 8), and window p reads the C-point residuals of its k slices s..p: windows p, p+1, ... share
 // k - 1 of them.  Block b takes window (b mod 8) * per + b / 8 (per = count / 8), so that every XCD
@@ -271,8 +262,6 @@ void launch_sweep(const KArgs& a, int64_t n_tasks, hipStream_t s)
         hipLaunchKernelGGL(sweep1d_kernel, dim3(n_tasks), dim3(block1d(a)), 0, s, a);
     else if (a.gadd || a.fine_substeps > 1)
         ATM_LAUNCH_2D(sweep2d_lv_kernel, n_tasks, s, a);
-    else if (a.cg_guess == 1)
-        ATM_LAUNCH_2D(sweep2d_xg_kernel, n_tasks, s, a);
     else
         ATM_LAUNCH_2D(sweep2d_kernel, n_tasks, s, a);
 }

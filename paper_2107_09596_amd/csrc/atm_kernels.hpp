@@ -46,9 +46,6 @@ struct KArgs {
     // FAS right-hand-side kernels: 1 writes y_j = Psi(u_{(j-1)m}) instead of tau_j, so that the
     // window kernels see the coarse residual y_j - u_{jm} of the injected iterate (nested iteration)
     int psi_only;
-    // 2D FP64 sweeps: 1 starts the CG of F-point t from u_t + (x_{t-1} - u_{t-1}), the stored
-    // iterate moved by the change the sweep has made at t-1 (0: from x_{t-1})
-    int cg_guess;
     Grid2D g;
     StepCoef fine, coarse;
     double rtol2;         // squared CG tolerance of Phi

@@ -173,20 +173,3 @@ def test_three_levels_bf16_coarsest_needs_one_substep(abi):
                                          ctypes.byref(abi.options(W.Options(**{**ok.__dict__, "coarse_solver": 1}))))
     assert n_ok > n_cg > 0  # the tables and the coarsest level's residual rows
     assert abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(bad))) == 0
-
-
-def test_cg_guess_restrictions(abi):
-    """cg_guess 1 is taken by two-level FP64 solves on grids up to 128 per side (a no-op in 1D)."""
-    ok = W.Problem(W.HEAT2D, nx=64, ny=96, nt=64)
-    for p, o, expect in [
-            (ok, W.Options(m=4, k=2, cg_guess=1), True),
-            (W.Problem(W.AC2D, nx=33, ny=21, nt=64), W.Options(m=4, k=2, cg_guess=1), True),
-            (W.Problem(W.HEAT1D, nx=64, nt=64), W.Options(m=4, k=2, cg_guess=1), True),
-            (ok, W.Options(m=4, k=2, cg_guess=1, coarse_solver=2), True),
-            (ok, W.Options(m=4, k=2, cg_guess=1, precision=1), False),
-            (ok, W.Options(m=4, k=2, cg_guess=1, levels=3, m_coarse=2), False),
-            (ok, W.Options(m=4, k=2, cg_guess=1, nested=1), False),
-            (W.Problem(W.AC2D, nx=256, ny=256, nt=64), W.Options(m=4, k=2, cg_guess=1), False),
-            (ok, W.Options(m=4, k=2, cg_guess=2), False)]:
-        n = abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(o)))
-        assert (n > 0) == expect, (p, o)

@@ -188,9 +188,8 @@ def test_c1_full_solve_matches_oracle(atm, orc):
     assert ghist[-1] <= o.tol
     assert_close(host(ud), ref, what="c1 converged iterate")
     np.testing.assert_allclose(ghist, hist, rtol=1e-10)
-    # intervals whose C-point no longer changes are not recomputed (neither are they in the oracle's
-    # solve loop: F-relaxation of an F-relaxed interval leaves it as it is), and the step accounting
-    # adds up
+    # intervals whose C-point no longer changes are not recomputed (the oracle recomputes them; the
+    # F-relaxation of an F-relaxed interval reproduces it bit for bit), and the step accounting adds up
     assert gst["fine_steps_skipped"] > 0
     assert gst["fine_steps"] + gst["fine_steps_skipped"] == gst["n_sweeps"] * p.nt
 

@@ -208,6 +208,31 @@ def test_ragged_tail_exactness(orc):
     assert np.max(np.abs(u - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("kind", [W.HEAT1D, W.HEAT2D, W.AC2D])
+def test_f_relaxation_of_relaxed_iterate_is_identity(orc, kind):
+    """F-relaxation recomputes every F-point from its C-point alone: a second pass reproduces the first
+    bit for bit, and an F-point's value never enters (the property a sweep that leaves unchanged intervals
+    alone rests on).  A pass that read a stored F-point (a wrong index) would differ on the scrambled
+    iterate."""
+    p, u0 = W.small_problem(kind, seed=8, nt=38, nx=9)
+    o = W.Options(m=4, k=2)
+    u = W.initial_guess(p, u0, "random", seed=2)
+    once = orc.f_relax(p, o, u)
+    assert np.array_equal(orc.f_relax(p, o, once), once)
+    scrambled = once.copy()
+    rng = np.random.default_rng(3)
+    for t in range(p.nt + 1):
+        if t % o.m:
+            scrambled[t] = rng.standard_normal(p.n)
+    assert np.array_equal(orc.f_relax(p, o, scrambled), once)
+    # the F-points are the sequential steps from each C-point
+    for j in range(0, p.nt, o.m):
+        seq = orc.sequential(W.Problem(**{**p.__dict__, "nt": min(o.m - 1, p.nt - j),
+                                          "t0": p.t0 + j * p.dt, "tf": p.t0 + (j + min(o.m - 1, p.nt - j)) * p.dt}),
+                             once[j])
+        np.testing.assert_allclose(once[j:j + len(seq)], seq, rtol=0, atol=1e-12 * np.max(np.abs(once)))
+
+
 @pytest.mark.parametrize("kind,form", [(W.HEAT1D, 1), (W.HEAT2D, 1), (W.AC2D, 2)])
 @pytest.mark.parametrize("relax", [0, 1])
 def test_k_full_equals_parareal_bitwise(orc, kind, form, relax):

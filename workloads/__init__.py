@@ -74,7 +74,6 @@ class Options:
     levels: int = 2         # 2: two-level AT-MGRIT (Alg. 1); 3: the FAS V-cycle of Alg. 2 over three levels
     m_coarse: int = 0       # levels 3: coarsening factor between level 1 and the coarsest level 2
     nested: int = 0         # 1: start from the nested-iteration guess built from the coarse levels
-    cg_guess: int = 0       # 1: a sweep's fine CG starts from the stored iterate plus the change at t-1
     coarse_cg_rtol: float = 0.0  # CG tolerance inside Psi; 0 = the problem's cg_rtol
     mixed_cg_rtol: float = 0.0   # precision 1: FP32 CG tolerance of the fine correction solves; 0 = 1e-6
     fallback_ratio: float = 0.0  # coarse_form 3: stagnation ratio that switches to the plain Psi; 0 = 0.95
