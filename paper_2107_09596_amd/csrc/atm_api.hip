@@ -50,7 +50,7 @@ constexpr double kLearnedGrowthLimit = 1e6;  // learned coarse solve: give up be
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
-    size_t header, partials, ya, yb, e, tau, pk, d1, d2, large, spec, cres, u1, y1a, y1b, tau2, e2, total;
+    size_t header, partials, ya, yb, e, tau, pk, d1, d2, large, spec, cres, traj, u1, y1a, y1b, tau2, e2, total;
 };
 
 int64_t n_intervals(const atm_problem* p, const atm_options* o) { return p->nt / o->m; }
@@ -60,6 +60,13 @@ int64_t n_space(const atm_problem* p) { return (int64_t)p->nx * p->ny; }
 bool large_grid(const atm_problem* p)
 {
     return p->kind != ATM_HEAT1D && (p->nx > atm::kMaxSide2D || p->ny > atm::kMaxSide2D);
+}
+
+// large grids whose windows the paired BF16 kernel takes: rows of 128, 192 or 256 points, 128 or 256
+// rows (two halves of 64 or 128)
+bool bf_pair_grid(const atm_problem* p)
+{
+    return p->nx % 64 == 0 && p->nx >= 128 && p->nx <= 256 && (p->ny == 128 || p->ny == 256);
 }
 
 // the multilevel FAS V-cycle over three levels (Alg. 2)
@@ -88,6 +95,14 @@ bool ml_bf(const atm_problem* p, const atm_options* o)
 bool spectral(const atm_problem* p, const atm_options* o)
 {
     return p->kind != ATM_HEAT1D && (o->coarse_solver == 0 || o->coarse_solver == 2) && !three_level(o);
+}
+
+// rows of n of the trajectory of v through Psi's substeps (the paired BF16 windows' FAS form)
+size_t traj_rows(const atm_problem* p, const atm_options* o)
+{
+    if (!(large_grid(p) && spectral(p, o) && o->coarse_solver == 2 && use_fas(p, o) && o->coarse_substeps > 1))
+        return 0;
+    return (size_t)n_intervals(p, o) * (size_t)(o->coarse_substeps - 1);
 }
 
 Layout layout(const atm_problem* p, const atm_options* o)
@@ -126,7 +141,10 @@ Layout layout(const atm_problem* p, const atm_options* o)
                           sizeof(double))
                : 0;
     L.cres = off;  // coarse_solver 2: the windows' C-point residuals (three levels: the coarsest level's)
-    off += ml_bf(p, o) ? align_up(slab2) : ((spectral(p, o) && o->coarse_solver == 2) ? align_up(slab) : 0);
+    off += ml_bf(p, o) ? align_up(slab2)
+                       : ((spectral(p, o) && o->coarse_solver == 2 && !large_grid(p)) ? align_up(slab) : 0);
+    L.traj = off;  // the paired BF16 windows, FAS form with s > 1 substeps: v through Psi's first s - 1
+    off += traj_rows(p, o) ? align_up((size_t)traj_rows(p, o) * (size_t)n_space(p) * sizeof(double)) : 0;
     // three levels: the level-1 iterate [N_T+1][n]; the level-1 sweeps' y (two), the level-2 FAS
     // right-hand side and corrections, [N_2+1][n] each
     L.u1 = off;
@@ -196,9 +214,14 @@ atm_status validate(const atm_problem* p, const atm_options* o)
     if (o->coarse_solver == 2 && o->levels != 3) {
         if (p->kind == ATM_HEAT1D || o->coarse_form == 3)
             return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 is built for the plain coarse propagator of the 2D kinds");
-        if (use_fas(p, o) && o->coarse_substeps != 1)
+        if (large_grid(p)) {
+            if (!bf_pair_grid(p))
+                return fail(ATM_ERR_UNSUPPORTED,
+                            "coarse_solver 2 beyond 128 points per side takes rows of 128, 192 or 256 points and "
+                            "128 or 256 rows");
+        } else if (use_fas(p, o) && o->coarse_substeps != 1) {
             return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 takes the FAS form with coarse_substeps 1");
-        if (large_grid(p)) return fail(ATM_ERR_UNSUPPORTED, "coarse_solver 2 takes grids up to 128 x 128");
+        }
     }
     if (o->coarse_form == 3) {
         if (p->kind != ATM_AC2D)
@@ -313,7 +336,8 @@ atm_status make_args_in(const atm_problem* p, const atm_options* o, void* ws, si
     a.maxit = p->cg_max_iter;
     a.spectral = spectral(p, o) ? (o->coarse_solver == 2 ? 2 : 1) : 0;
     a.spec = (a.spectral || ml_bf(p, o)) ? (double*)(base + L.spec) : nullptr;
-    a.cres = a.spectral == 2 ? (double*)(base + L.cres) : nullptr;
+    a.cres = (a.spectral == 2 && !large_grid(p)) ? (double*)(base + L.cres) : nullptr;
+    a.traj = traj_rows(p, o) ? (double*)(base + L.traj) : nullptr;
     if (large_grid(p)) {
         a.large = 1;
         a.large_scratch = (double*)(base + L.large);
@@ -1423,6 +1447,9 @@ const char* atm_coarse_kernel(const atm_problem* prob, const atm_options* opts)
     a.g.ny = prob->ny;
     a.n = n_space(prob);
     a.NT = n_intervals(prob, opts);
+    a.fas = use_fas(prob, opts) ? 1 : 0;
+    a.substeps = opts->coarse_substeps;
+    if (spec == 2) return atm::coarse_pair_pairs(a) > 0 ? "coarse_pair_bf_kernel" : "";
     return atm::coarse_pair_pairs(a) > 0 ? "coarse_pair_kernel" : "coarse_large_kernel";
 }
 

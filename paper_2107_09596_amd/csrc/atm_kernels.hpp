@@ -67,8 +67,12 @@ struct KArgs {
     int spectral;
     double* spec;
     // spectral 2: the C-point residuals r_j = y_j - u_{jm} (r_0 = 0), [N_T+1][n], formed once per
-    // coarse solve so that each window step reads one row
+    // coarse solve so that each window step reads one row (grids up to 128 per side)
     double* cres;
+    // spectral 2 on the paired large-grid windows, FAS form with s > 1 substeps: v_{j-1} carried
+    // through Psi's first s - 1 substeps, [N_T][s - 1][n] (entry (j - 1, q - 1): q substeps from
+    // the C-point u_{(j-1)m})
+    double* traj;
 };
 
 // ---------------------------------------------------------------------------

@@ -680,28 +680,33 @@ __device__ __forceinline__ bool spectral_step_pair(const KArgs& a, const SpecTab
     return true;
 }
 
-// TAU: tau_j = (v_j - Psi(v_{j-1})) + r_j for the tasks j = 1 .. N_T; else window p for the tasks
-// p = 0 .. N_T (linear or FAS form).  Pair q takes the tasks q, q + pairs, ...
-template <int NT, bool TAU>
+// The tasks of the paired kernels: windows p = 0 .. N_T (linear or FAS form); the FAS right-hand
+// sides tau_j = (v_j - Psi(v_{j-1})) + r_j, j = 1 .. N_T; or the trajectory of v_{j-1} through Psi's
+// first s - 1 substeps, j = 1 .. N_T (the BF16 windows' FAS form in terms of e).
+enum PairTask { kWinTask = 0, kTauTask = 1, kTrajTask = 2 };
+
+// Pair q takes the tasks q, q + pairs, ... of its kind.
+template <int NT, int MODE>
 __global__ __launch_bounds__(kBlockL) void coarse_pair_kernel(KArgs a, LScratch sc, WinPair wp)
 {
     __shared__ double gl[kGemmLds];
     __shared__ int ok;
+    constexpr bool WIN = MODE == kWinTask;
     const int pr = pair::pair_of(blockIdx.x), half = pair::half_of(blockIdx.x);
     const int nx = a.g.nx, rows = a.g.ny / 2, r0 = half * rows;
     const int64_t n = a.n, o = (int64_t)r0 * nx, cnt = (int64_t)rows * nx;
     const SpecTables T = spec_tables(a);
     unsigned k = 0;
     bool alive = true;
-    for (int64_t task = (TAU ? 1 : 0) + pr; alive && task <= a.NT; task += wp.pairs) {
+    for (int64_t task = (WIN ? 0 : 1) + pr; alive && task <= a.NT; task += wp.pairs) {
         double* __restrict__ w = sc.vec(task, 4);
         double* t0 = sc.vec(task, 0);
         double* t1 = sc.vec(task, 1);
         double* t2 = sc.vec(task, 2);
-        const int64_t s0 = TAU ? task - 1 : (task - a.k + 1 > 0 ? task - a.k + 1 : 0);
+        const int64_t s0 = !WIN ? task - 1 : (task - a.k + 1 > 0 ? task - a.k + 1 : 0);
         for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) {
             const int64_t i = o + e;
-            if (TAU)
+            if (!WIN)
                 w[i] = a.u[(s0 * a.m) * n + i];
             else {
                 const double r = cpoint_residual(a, s0, i);
@@ -709,10 +714,16 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_kernel(KArgs a, LScratch 
             }
         }
         __syncthreads();
+        const int steps = MODE == kTrajTask ? a.substeps - 1 : a.substeps;
         for (int64_t jj = s0 + 1; alive && jj <= task; ++jj) {
-            for (int q = 0; alive && q < a.substeps; ++q)
+            for (int q = 0; alive && q < steps; ++q) {
                 alive = spectral_step_pair<NT>(a, T, w, t0, t1, t2, gl, r0, rows, wp, pr, half, k, &ok);
-            if (!alive || TAU) break;
+                if (MODE == kTrajTask && alive) {
+                    double* dst = a.traj + ((task - 1) * (a.substeps - 1) + q) * n;
+                    for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) dst[o + e] = w[o + e];
+                }
+            }
+            if (!alive || !WIN) break;
             for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) {
                 const int64_t i = o + e;
                 w[i] = w[i] + (a.fas ? a.tau[jj * n + i] : cpoint_residual(a, jj, i));
@@ -720,16 +731,277 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_kernel(KArgs a, LScratch 
             __syncthreads();
         }
         if (!alive) break;
-        for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) {
-            const int64_t i = o + e;
-            if (TAU)
-                a.tau[task * n + i] = (a.u[(task * a.m) * n + i] - w[i]) + cpoint_residual(a, task, i);
-            else
-                a.e[task * n + i] = a.fas ? w[i] - a.u[(task * a.m) * n + i] : w[i];
+        if (MODE != kTrajTask) {
+            for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) {
+                const int64_t i = o + e;
+                if (MODE == kTauTask)
+                    a.tau[task * n + i] = (a.u[(task * a.m) * n + i] - w[i]) + cpoint_residual(a, task, i);
+                else
+                    a.e[task * n + i] = a.fas ? w[i] - a.u[(task * a.m) * n + i] : w[i];
+            }
         }
         __syncthreads();
     }
     if (!alive && threadIdx.x == 0) atomicOr(a.fail, kFailPairTimeout);
+}
+
+// ---------------------------------------------------------------------------
+// The paired windows with Psi's eigenbasis solve on the BF16 matrix cores (coarse_solver 2)
+// ---------------------------------------------------------------------------
+// A window carries e (the correction; FAS form: e = w - v) in FP64 in its global scratch.  Every
+// substep forms its explicit part in FP64 -- the FAS form the difference of the explicit parts at
+// v + e and at v, e + react (e - e (3 v^2 + 3 v e + e^2)), so that the products' error scales with e
+// and vanishes with it -- splits it into BF16 planes hi + lo and applies M^-1 by the four products
+// of the eigenbasis solve, each taken as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
+// sums (about 16 significant bits per operand: Psi to about 1e-5 relative, which changes the
+// two-level convergence rate and never the fixed point).  v passes through Psi's substeps as well:
+// v^(0) = v_{j-1} is the C-point, v^(1 .. s-1) are the FP64 trajectory (kTrajTask).
+//
+// Every product is OutT[j][i] = sum_k A[i][k] BT[j][k] with A [M][K] and BT [N][K] stored
+// k-contiguous (BF16 hi and lo planes), so that each lane reads 8 consecutive k of a fragment and
+// writes 4 consecutive entries of an OutT row, which is the layout the next product reads:
+//   t1[i][x]  = sum_y  bT[x][y]  QyT[r0+i][y]        Qy^T b        (M = nx, N = rows, K = ny)
+//   t2T[x][i] = sum_x' t1[i][x'] QxT[x][x'] / mu     (.. Qx) ./ mu (M = rows, N = nx, K = nx)
+//   t1[i][x]  = sum_y  t2T[x][y] Qy[r0+i][y]         Qy ..         (M = nx, N = rows, K = ny)
+//   e[i][x]   = sum_x' Qx[x][x'] t1[i][x']           .. Qx^T       (M = nx, N = rows, K = nx)
+// with i the half's rows r0 + i.  bT and t2T are shared by the pair (device-coherent 8-byte stores
+// and loads, a meeting after each is complete), t1 is the half's own.
+
+constexpr int kBfKC = 32;                      // k per chunk: one MFMA
+constexpr int kBfPitch = kBfKC + 8;            // BF16 per LDS row of a chunk (80 bytes)
+constexpr int kBfRowsMax = 384;                // A rows + BT rows of the largest product (256 + 128)
+constexpr int kBfBuf = kBfRowsMax * 2 * kBfPitch;  // BF16 of one chunk buffer, both planes
+constexpr int kBfTP = 128 + 8;                 // BF16 pitch of the explicit part's transpose tile
+
+struct BfOp {
+    const __bf16* hi;
+    const __bf16* lo;
+    int ld;  // leading dimension (BF16)
+};
+
+__device__ __forceinline__ uint64_t get64(const __bf16* p)
+{
+    return __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<__bf16*>(p)), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void put64(__bf16* p, uint64_t v)
+{
+    __hip_atomic_store(reinterpret_cast<uint64_t*>(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// four FP32 values as BF16 hi and lo parts, packed 4 x 16 bits
+__device__ __forceinline__ void split4(const f32x4_t& v, uint64_t& hi, uint64_t& lo)
+{
+    bf16x4_t h, l;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const __bf16 b = (__bf16)v[r];
+        h[r] = b;
+        l[r] = (__bf16)(v[r] - (float)b);
+    }
+    hi = __builtin_bit_cast(uint64_t, h);
+    lo = __builtin_bit_cast(uint64_t, l);
+}
+
+// OutT[j][i] = out(i, j, sum_k A[i][k] BT[j][k]) (out receives four consecutive i from i) for M = 64 TM,
+// N = 64 TN, K a multiple of 32.  16 waves in a 4 x 4 grid, wave (wm, wn) owning rows 16 TM wm .. and
+// columns 16 TN wn .. (TM x TN tiles of 16 x 16).  Per k-chunk of 32 the A rows and BT rows of both
+// planes are staged in LDS (two buffers: the next chunk's global loads are in flight while the
+// current chunk's MFMAs run); the 80-byte row pitch puts the 16-byte fragment reads of 16
+// consecutive rows on distinct banks.  ACOH: A is read through device-coherent loads.
+template <int TM, int TN, bool ACOH, typename O>
+__device__ __forceinline__ void bf_gemm(const BfOp A, const BfOp B, int K, __bf16* lds, O&& out)
+{
+    constexpr int M = 64 * TM, N = 64 * TN, R = M + N;
+    static_assert(R <= kBfRowsMax, "chunk buffer too small");
+    constexpr int SEG = R * 8;  // 16-byte pieces of a chunk: R rows x 2 planes x 4
+    constexpr int PER = (SEG + kBlockL - 1) / kBlockL;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int wm = wave >> 2, wn = wave & 3;
+    uint64_t ld0[PER], ld1[PER];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int sg = tid + q * kBlockL;
+            if (sg < SEG) {
+                const int row = sg >> 3, plane = (sg >> 2) & 1, seg = sg & 3;
+                const bool isa = row < M;
+                const __bf16* base = isa ? (plane ? A.lo : A.hi) : (plane ? B.lo : B.hi);
+                const int r = isa ? row : row - M;
+                const __bf16* src = base + (int64_t)r * (isa ? A.ld : B.ld) + k0 + 8 * seg;
+                if (ACOH && isa) {
+                    ld0[q] = get64(src);
+                    ld1[q] = get64(src + 4);
+                } else {
+                    const uint4 v = *reinterpret_cast<const uint4*>(src);
+                    ld0[q] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+                    ld1[q] = (uint64_t)v.z | ((uint64_t)v.w << 32);
+                }
+            }
+        }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int sg = tid + q * kBlockL;
+            if (sg < SEG) {
+                const int row = sg >> 3, plane = (sg >> 2) & 1, seg = sg & 3;
+                uint4 v;
+                v.x = (uint32_t)ld0[q];
+                v.y = (uint32_t)(ld0[q] >> 32);
+                v.z = (uint32_t)ld1[q];
+                v.w = (uint32_t)(ld1[q] >> 32);
+                *reinterpret_cast<uint4*>(lds + buf * kBfBuf + (plane * R + row) * kBfPitch + 8 * seg) = v;
+            }
+        }
+    };
+    f32x4_t acc[TM][TN];
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) acc[tm][tn] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    const int nk = K / kBfKC;
+    load(0);
+    stage(0);
+    __syncthreads();
+#pragma unroll 1
+    for (int kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        if (kc + 1 < nk) load((kc + 1) * kBfKC);
+        const __bf16* Lh = lds + buf * kBfBuf;
+        const __bf16* Ll = Lh + R * kBfPitch;
+        bf16x8_t bh[TN], bl[TN];
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn) {
+            const int o = (M + wn * 16 * TN + 16 * tn + li) * kBfPitch + 8 * lk;
+            bh[tn] = *reinterpret_cast<const bf16x8_t*>(Lh + o);
+            bl[tn] = *reinterpret_cast<const bf16x8_t*>(Ll + o);
+        }
+#pragma unroll
+        for (int tm = 0; tm < TM; ++tm) {
+            const int o = (wm * 16 * TM + 16 * tm + li) * kBfPitch + 8 * lk;
+            const bf16x8_t ah = *reinterpret_cast<const bf16x8_t*>(Lh + o);
+            const bf16x8_t al = *reinterpret_cast<const bf16x8_t*>(Ll + o);
+#pragma unroll
+            for (int tn = 0; tn < TN; ++tn) {
+                acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[tn], acc[tm][tn], 0, 0, 0);
+                acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[tn], acc[tm][tn], 0, 0, 0);
+                acc[tm][tn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[tn], acc[tm][tn], 0, 0, 0);
+            }
+        }
+        if (kc + 1 < nk) stage(buf ^ 1);
+        __syncthreads();
+    }
+    // item r of the lane: row 4 lk + r, column li of its tile
+#pragma unroll
+    for (int tm = 0; tm < TM; ++tm)
+#pragma unroll
+        for (int tn = 0; tn < TN; ++tn)
+            out(wm * 16 * TM + 16 * tm + 4 * lk, wn * 16 * TN + 16 * tn + li, acc[tm][tn]);
+}
+
+// the window's tasks p = q, q + pairs, ... on pair q; nx = 64 NXT, half rows ny / 2 = 64 RT
+template <int NXT, int RT>
+__global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScratch sc, WinPair wp)
+{
+    __shared__ __align__(16) __bf16 lds[2 * kBfBuf];
+    __shared__ int ok;
+    constexpr int NX = 64 * NXT, ROWS = 64 * RT, NY = 2 * ROWS;
+    const int pr = pair::pair_of(blockIdx.x), half = pair::half_of(blockIdx.x);
+    const int r0 = half * ROWS;
+    const int64_t n = a.n, o = (int64_t)r0 * NX, cnt = (int64_t)ROWS * NX;
+    const int tid = threadIdx.x;
+    const SpecTables T = spec_tables(a);
+    const BfOp qyt{bf_table(a, 0, 0) + r0 * NY, bf_table(a, 0, 1) + r0 * NY, NY};
+    const BfOp qxt{bf_table(a, 1, 0), bf_table(a, 1, 1), NX};
+    const BfOp qy{bf_table(a, 2, 0) + r0 * NY, bf_table(a, 2, 1) + r0 * NY, NY};
+    const BfOp qx{bf_table(a, 3, 0), bf_table(a, 3, 1), NX};
+    const float cx2 = (float)(2.0 * a.coarse.cx), cy2 = (float)(2.0 * a.coarse.cy);
+    const double react = a.coarse.react;
+    unsigned k = 0;
+    bool alive = true;
+    for (int64_t task = pr; alive && task <= a.NT; task += wp.pairs) {
+        double* __restrict__ w = sc.vec(task, 4);
+        __bf16* bt = reinterpret_cast<__bf16*>(sc.vec(task, 0));  // bT [NX][NY], hi then lo plane
+        __bf16* t1 = reinterpret_cast<__bf16*>(sc.vec(task, 1));  // t1 [NY][NX] (the half's rows)
+        __bf16* t2 = reinterpret_cast<__bf16*>(sc.vec(task, 2));  // t2T [NX][NY]
+        const BfOp opb{bt, bt + n, NY}, opt2{t2, t2 + n, NY};
+        const BfOp opt1{t1 + o, t1 + n + o, NX};
+        const int64_t s0 = task - a.k + 1 > 0 ? task - a.k + 1 : 0;
+        for (int64_t e = tid; e < cnt; e += kBlockL) w[o + e] = cpoint_residual(a, s0, o + e);
+        __syncthreads();
+        // C[x][i] -> t1[i][x .. x+3] (the half's rows)
+        auto to_t1 = [&](int x, int i, f32x4_t v) {
+            uint64_t h, l;
+            split4(v, h, l);
+            *reinterpret_cast<uint64_t*>(t1 + o + (int64_t)i * NX + x) = h;
+            *reinterpret_cast<uint64_t*>(t1 + n + o + (int64_t)i * NX + x) = l;
+        };
+        for (int64_t jj = s0 + 1; alive && jj <= task; ++jj) {
+            for (int q = 0; alive && q < a.substeps; ++q) {
+                const double* v = !a.fas ? nullptr
+                                : q == 0 ? a.u + ((jj - 1) * a.m) * n
+                                         : a.traj + ((jj - 1) * (a.substeps - 1) + q - 1) * n;
+                // the explicit part in FP64, split, and transposed through LDS into bT[x][r0 ..], in
+                // two passes of 128 columns
+                for (int c0 = 0; c0 < NX; c0 += 128) {
+                    const int cols = NX - c0 < 128 ? NX - c0 : 128;
+                    for (int e = tid; e < ROWS * cols; e += kBlockL) {
+                        const int y = e / cols, x = c0 + e % cols;
+                        const int64_t i = o + (int64_t)y * NX + x;
+                        const double ee = w[i];
+                        double b;
+                        if (v) {
+                            const double vv = v[i];
+                            b = ee + react * (ee - ee * (3.0 * vv * vv + 3.0 * vv * ee + ee * ee));
+                        } else {
+                            b = explicit_part(a.coarse, ee);
+                        }
+                        const __bf16 h = (__bf16)b;
+                        lds[(x - c0) * kBfTP + y] = h;
+                        lds[(128 + x - c0) * kBfTP + y] = (__bf16)(b - (double)h);
+                    }
+                    __syncthreads();
+                    for (int e = tid; e < cols * (ROWS / 4) * 2; e += kBlockL) {
+                        const int plane = e / (cols * (ROWS / 4)), rest = e % (cols * (ROWS / 4));
+                        const int x = rest / (ROWS / 4), y4 = 4 * (rest % (ROWS / 4));
+                        const uint64_t val = *reinterpret_cast<const uint64_t*>(lds + (plane * 128 + x) * kBfTP + y4);
+                        put64(bt + plane * n + (int64_t)(c0 + x) * NY + r0 + y4, val);
+                    }
+                    __syncthreads();
+                }
+                if (!(alive = pair_meet(wp, pr, half, ++k, &ok))) break;
+                bf_gemm<NXT, RT, true>(opb, qyt, NY, lds, to_t1);  // Qy^T b
+                __syncthreads();
+                bf_gemm<RT, NXT, false>(opt1, qxt, NX, lds, [&](int i, int x, f32x4_t c) {  // (.. Qx) ./ mu
+                    const float ex = (float)T.ex[x];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) c[r] = c[r] / (1.0f + (cx2 * ex + cy2 * (float)T.ey[r0 + i + r]));
+                    uint64_t h, l;
+                    split4(c, h, l);
+                    put64(t2 + (int64_t)x * NY + r0 + i, h);
+                    put64(t2 + n + (int64_t)x * NY + r0 + i, l);
+                });
+                if (!(alive = pair_meet(wp, pr, half, ++k, &ok))) break;
+                bf_gemm<NXT, RT, true>(opt2, qy, NY, lds, to_t1);  // Qy ..
+                __syncthreads();
+                bf_gemm<NXT, RT, false>(qx, opt1, NX, lds, [&](int x, int i, f32x4_t c) {  // .. Qx^T
+                    double* dst = w + o + (int64_t)i * NX + x;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) dst[r] = (double)c[r];
+                });
+                __syncthreads();
+            }
+            if (!alive) break;
+            for (int64_t e = tid; e < cnt; e += kBlockL) w[o + e] = w[o + e] + cpoint_residual(a, jj, o + e);
+            __syncthreads();
+        }
+        if (!alive) break;
+        for (int64_t e = tid; e < cnt; e += kBlockL) a.e[task * n + o + e] = w[o + e];
+        __syncthreads();
+    }
+    if (!alive && tid == 0) atomicOr(a.fail, kFailPairTimeout);
 }
 
 __global__ void clear_counters_kernel(unsigned* c, int n)
@@ -899,23 +1171,51 @@ hipError_t launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipSt
 }
 
 // the paired window kernels of an nx x ny grid with NT-tile products, and the pairs to launch (0: the
-// one-workgroup kernels take the grid)
+// one-workgroup kernels take the grid).  pre: the kernel that runs before the windows (FP64 FAS
+// right-hand sides, or the trajectory of v for the BF16 windows; null when none is needed).
 struct CoarsePair {
-    const void* tau;
+    const void* pre;
     const void* win;
     int pairs;
 };
+
+template <int NT>
+static const void* bf_window_kernel(int rt)
+{
+    if (rt == 1) return (const void*)coarse_pair_bf_kernel<NT, 1>;
+    if (rt == 2) return (const void*)coarse_pair_bf_kernel<NT, 2>;
+    return nullptr;
+}
 
 static CoarsePair coarse_pair(const KArgs& a)
 {
     CoarsePair cp{nullptr, nullptr, 0};
     const int nt = a.spectral ? spectral_nt(a.g.nx, a.g.ny) : 0;
     if (a.g.ny % 128) return cp;  // halves of whole 64-row blocks
-    if (nt == 4) cp = {(const void*)coarse_pair_kernel<4, true>, (const void*)coarse_pair_kernel<4, false>, 0};
-    if (nt == 3) cp = {(const void*)coarse_pair_kernel<3, true>, (const void*)coarse_pair_kernel<3, false>, 0};
-    if (nt == 2) cp = {(const void*)coarse_pair_kernel<2, true>, (const void*)coarse_pair_kernel<2, false>, 0};
+    if (a.spectral == 2) {
+        // nx of 128, 192 or 256 points, halves of 64 or 128 rows
+        const int rt = a.g.ny / 128;
+        if (nt == 4) cp.win = bf_window_kernel<4>(rt);
+        if (nt == 3) cp.win = bf_window_kernel<3>(rt);
+        if (nt == 2) cp.win = bf_window_kernel<2>(rt);
+        if (a.fas && a.substeps > 1) {
+            if (nt == 4) cp.pre = (const void*)coarse_pair_kernel<4, kTrajTask>;
+            if (nt == 3) cp.pre = (const void*)coarse_pair_kernel<3, kTrajTask>;
+            if (nt == 2) cp.pre = (const void*)coarse_pair_kernel<2, kTrajTask>;
+        }
+    } else {
+        if (nt == 4) cp = {(const void*)coarse_pair_kernel<4, kTauTask>, (const void*)coarse_pair_kernel<4, kWinTask>, 0};
+        if (nt == 3) cp = {(const void*)coarse_pair_kernel<3, kTauTask>, (const void*)coarse_pair_kernel<3, kWinTask>, 0};
+        if (nt == 2) cp = {(const void*)coarse_pair_kernel<2, kTauTask>, (const void*)coarse_pair_kernel<2, kWinTask>, 0};
+        if (!a.fas) cp.pre = nullptr;
+    }
     if (!cp.win) return cp;
-    int pairs = (resident_blocks(cp.win, kBlockL) / 2) / 8 * 8;
+    int resident = resident_blocks(cp.win, kBlockL);
+    if (cp.pre) {
+        const int rp = resident_blocks(cp.pre, kBlockL);
+        if (rp < resident) resident = rp;
+    }
+    int pairs = (resident / 2) / 8 * 8;
     const int64_t want = (a.NT + 1 + 7) / 8 * 8;
     if (pairs > want) pairs = (int)want;
     cp.pairs = pairs >= 8 ? pairs : 0;
@@ -928,6 +1228,7 @@ hipError_t launch_coarse_large(const KArgs& a, hipStream_t s)
 {
     if (a.spectral) launch_spectral_tables(a, s);
     const CoarsePair cp = coarse_pair(a);
+    if (a.spectral == 2 && cp.pairs == 0) return hipErrorNotSupported;  // no one-workgroup BF16 form
     if (cp.pairs > 0) {
         // the meeting counters in the fourth vector of task 0, which no paired task uses
         WinPair wp;
@@ -937,9 +1238,9 @@ hipError_t launch_coarse_large(const KArgs& a, hipStream_t s)
         KArgs ka = a;
         LScratch sc = scratch_of(a);
         void* args[] = {&ka, &sc, &wp};
-        if (a.fas && a.NT >= 1) {
+        if (cp.pre && a.NT >= 1) {
             hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(256), 0, s, wp.epoch, 2 * cp.pairs);
-            hipError_t e = hipLaunchCooperativeKernel(cp.tau, dim3(2 * cp.pairs), dim3(kBlockL), args, 0, s);
+            hipError_t e = hipLaunchCooperativeKernel(cp.pre, dim3(2 * cp.pairs), dim3(kBlockL), args, 0, s);
             if (e != hipSuccess) return e;
         }
         hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(256), 0, s, wp.epoch, 2 * cp.pairs);

@@ -149,7 +149,8 @@ def test_source_accepted_for_1d_only(abi):
 
 
 def test_bf16_psi_restrictions(abi):
-    """coarse_solver 2 is built for the 2D kinds on grids up to 128 per side (FAS with one substep)."""
+    """coarse_solver 2 is built for the 2D kinds: grids up to 128 per side (FAS with one substep), and the
+    paired large-grid windows (rows of 128, 192 or 256 points, 128 or 256 rows; FAS with any substeps)."""
     ok = W.Problem(W.HEAT2D, nx=64, ny=96, nt=64)
     for p, o, expect in [
             (ok, W.Options(m=4, k=2, coarse_solver=2), True),
@@ -159,6 +160,12 @@ def test_bf16_psi_restrictions(abi):
             (ok, W.Options(m=4, k=2, coarse_solver=2, coarse_form=2, coarse_substeps=2), False),
             (W.Problem(W.HEAT1D, nx=64, nt=64), W.Options(m=4, k=2, coarse_solver=2), False),
             (W.Problem(W.AC2D, nx=64, ny=64, nt=64), W.Options(m=4, k=2, coarse_solver=2), True),
+            (W.Problem(W.AC2D, nx=256, ny=256, nt=64), W.Options(m=4, k=2, coarse_solver=2, coarse_substeps=4), True),
+            (W.Problem(W.HEAT2D, nx=192, ny=128, nt=64), W.Options(m=4, k=2, coarse_solver=2), True),
+            (W.Problem(W.HEAT2D, nx=128, ny=256, nt=64), W.Options(m=4, k=2, coarse_solver=2), True),
+            (W.Problem(W.HEAT2D, nx=256, ny=192, nt=64), W.Options(m=4, k=2, coarse_solver=2), False),
+            (W.Problem(W.HEAT2D, nx=320, ny=256, nt=64), W.Options(m=4, k=2, coarse_solver=2), False),
+            (W.Problem(W.HEAT2D, nx=160, ny=256, nt=64), W.Options(m=4, k=2, coarse_solver=2), False),
             (ok, W.Options(m=4, k=2, coarse_solver=3), False)]:
         n = abi.lib().atm_workspace_bytes(ctypes.byref(abi.problem(p)), ctypes.byref(abi.options(o)))
         assert (n > 0) == expect, (p, o)

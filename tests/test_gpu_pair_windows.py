@@ -81,3 +81,88 @@ def test_paired_windows_solve(atm, orc, precision):
     status, hist, st = atm.atm_solve(p, o, ud)
     assert status == atm.ATM_OK and st["final_residual"] <= 1e-11
     assert np.linalg.norm(host(ud) - seq) <= (p.nt + 1) * 1e-11 + 1e-12 * np.linalg.norm(seq)
+
+
+# ---------------------------------------------------------------------------
+# Psi's eigenbasis solve on the BF16 matrix cores (coarse_solver 2): windows in terms of e
+# ---------------------------------------------------------------------------
+
+BF_PAIRED = [
+    # (kind, nx, ny, nt, m, k, coarse substeps)
+    (W.HEAT2D, 256, 256, 12, 4, 2, 1),   # one window step: the tight bound
+    (W.AC2D, 256, 256, 16, 4, 2, 4),     # the 256 x 256 periodic grid with four substeps, one step
+    (W.HEAT2D, 256, 256, 12, 4, 3, 1),
+    (W.AC2D, 192, 128, 12, 3, 4, 2),     # FAS: v through the first of two substeps from the trajectory
+    (W.HEAT2D, 128, 256, 10, 2, 3, 1),
+    (W.AC2D, 192, 128, 262, 2, 3, 1),    # 132 windows: with at most 128 pairs resident a pair takes two
+]
+
+
+def bf_ids(c):
+    return f"k{c[0]}-{c[1]}x{c[2]}-nt{c[3]}-m{c[4]}-k{c[5]}-s{c[6]}"
+
+
+def bf_options(kind, m, k, form, sub):
+    return W.Options(m=m, k=k, coarse_form=form, coarse_substeps=sub, coarse_solver=2)
+
+
+def test_bf16_paired_kernel_is_taken(atm):
+    for kind, nx, ny, nt, m, k, sub in BF_PAIRED:
+        p, _ = small(kind, nx, ny, nt)
+        assert atm.atm_coarse_kernel(p, bf_options(kind, m, k, 0, sub)) == "coarse_pair_bf_kernel"
+
+
+@pytest.mark.parametrize("form", [1, 2])
+@pytest.mark.parametrize("case", BF_PAIRED, ids=bf_ids)
+def test_bf16_paired_windows_match_oracle(atm, orc, case, form):
+    """Each product takes BF16 hi + lo parts of its operands (about 2^-17 relative each) with FP32 sums over
+    at most 256 terms, so one substep of M^-1 is within about 4e-5 of the FP64 solve relative to the
+    correction it acts on; a window of k - 1 steps of s substeps accumulates at most (k - 1) s of them.
+    The bound asserted is 5e-5 per substep of the deepest window, relative to max |e|."""
+    kind, nx, ny, nt, m, k, sub = case
+    p, u0 = small(kind, nx, ny, nt)
+    o = bf_options(kind, m, k, form, sub)
+    NT = p.nt // m
+    g = W.initial_guess(p, u0, "random", seed=4) * 0.5
+    g[0] = u0
+    u = orc.f_relax(p, o, g)
+    y = y_of(orc, p, o, u)
+    rc = np.zeros((NT + 1, p.n))
+    vc = np.stack([u[j * m] for j in range(NT + 1)])
+    for j in range(1, NT + 1):
+        rc[j] = y[j] - u[j * m]
+    ref = orc.local_solves(p, o, rc, vc)
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o))
+    e = dev(np.zeros((NT + 1, p.n)))
+    atm.atm_coarse_solve(p, o, dev(u), dev(y), e, ws)
+    got = host(e)
+    scale = float(np.max(np.abs(ref)))
+    err = float(np.max(np.abs(got - ref)))
+    bound = 5e-5 * (k - 1) * sub * scale
+    print(f"BF16 paired windows {bf_ids(case)} form {form}: max error {err:.2e} of max |e| {scale:.2e} "
+          f"({err / scale:.1e} relative, bound {bound / scale:.1e})", flush=True)
+    assert err <= bound
+    # the error is that of the products, not of a wrong window: the exact windows' first entries (p < 1)
+    # are the residuals themselves
+    np.testing.assert_array_equal(got[0], ref[0])
+    e2 = dev(np.zeros((NT + 1, p.n)))
+    atm.atm_coarse_solve(p, o, dev(u), dev(y), e2, ws)
+    assert np.array_equal(host(e2), got)
+
+
+@pytest.mark.parametrize("kind,sub,precision", [(W.HEAT2D, 1, 0), (W.HEAT2D, 1, 1), (W.AC2D, 2, 1)])
+def test_bf16_paired_windows_solve(atm, orc, kind, sub, precision):
+    """The BF16 Psi changes the convergence rate only: the solve reaches the FP64 fixed point."""
+    nx, ny, nt, m, k = 192, 128, 24, 2, 3
+    p, u0 = small(kind, nx, ny, nt)
+    seq = orc.sequential(p, u0)
+    o = W.Options(m=m, k=k, relax=1, tol=1e-11 if precision == 0 else 1e-10, precision=precision,
+                  coarse_substeps=sub, coarse_solver=2, max_iter=60)
+    assert atm.atm_coarse_kernel(p, o) == "coarse_pair_bf_kernel"
+    ud = dev(W.initial_guess(p, u0))
+    status, hist, st = atm.atm_solve(p, o, ud)
+    err = float(np.linalg.norm(host(ud) - seq))
+    print(f"BF16 paired solve kind {kind} s {sub} precision {precision}: {st['iterations']} cycles, "
+          f"final residual {st['final_residual']:.2e}, |u - sequential| {err:.2e}", flush=True)
+    assert status == atm.ATM_OK and st["final_residual"] <= o.tol
+    assert err <= (p.nt + 1) * 10 * o.tol + 1e-12 * np.linalg.norm(seq)

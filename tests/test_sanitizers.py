@@ -60,7 +60,8 @@ CONFIGS = [
     (dict(kind=W.HEAT2D, nx=0, ny=16, nt=32), dict(m=4, k=2)),            # refused: empty grid
     (dict(kind=W.HEAT2D, nx=16, ny=16, nt=32), dict(m=1, k=2)),           # refused: m < 2
     (dict(kind=W.HEAT2D, nx=16, ny=16, nt=3), dict(m=4, k=2)),            # refused: fewer steps than m
-    (dict(kind=W.AC2D, nx=256, ny=256, nt=64), dict(m=4, k=2, coarse_solver=2)),  # refused: BF16 Psi, large grid
+    (dict(kind=W.AC2D, nx=256, ny=256, nt=64), dict(m=4, k=2, coarse_solver=2, coarse_substeps=4)),
+    (dict(kind=W.AC2D, nx=320, ny=256, nt=64), dict(m=4, k=2, coarse_solver=2)),  # refused: BF16 Psi, 320 columns
     (dict(kind=W.HEAT1D, nx=64, nt=64), dict(m=4, k=2, precision=1)),     # refused: FP32 form in 1D
     (dict(kind=9, nx=16, ny=16, nt=32), dict(m=4, k=2)),                  # refused: unknown kind
 ]
