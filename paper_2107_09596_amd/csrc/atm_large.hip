@@ -947,20 +947,27 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScrat
                 // two passes of 128 columns
                 for (int c0 = 0; c0 < NX; c0 += 128) {
                     const int cols = NX - c0 < 128 ? NX - c0 : 128;
-                    for (int e = tid; e < ROWS * cols; e += kBlockL) {
-                        const int y = e / cols, x = c0 + e % cols;
-                        const int64_t i = o + (int64_t)y * NX + x;
-                        const double ee = w[i];
-                        double b;
-                        if (v) {
-                            const double vv = v[i];
-                            b = ee + react * (ee - ee * (3.0 * vv * vv + 3.0 * vv * ee + ee * ee));
-                        } else {
-                            b = explicit_part(a.coarse, ee);
+                    // ROWS * cols is a multiple of 4 kBlockL: batches of four points per thread, every
+                    // load of a batch issued before any is used
+                    for (int b0 = tid; b0 < ROWS * cols; b0 += 4 * kBlockL) {
+                        double ew[4], vw[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int e = b0 + u * kBlockL, y = e / cols, x = c0 + e % cols;
+                            const int64_t i = o + (int64_t)y * NX + x;
+                            ew[u] = w[i];
+                            vw[u] = v ? v[i] : 0.0;
                         }
-                        const __bf16 h = (__bf16)b;
-                        lds[(x - c0) * kBfTP + y] = h;
-                        lds[(128 + x - c0) * kBfTP + y] = (__bf16)(b - (double)h);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int e = b0 + u * kBlockL, y = e / cols, x = e % cols;
+                            const double ee = ew[u], vv = vw[u];
+                            const double b = v ? ee + react * (ee - ee * (3.0 * vv * vv + 3.0 * vv * ee + ee * ee))
+                                               : explicit_part(a.coarse, ee);
+                            const __bf16 h = (__bf16)b;
+                            lds[x * kBfTP + y] = h;
+                            lds[(128 + x) * kBfTP + y] = (__bf16)(b - (double)h);
+                        }
                     }
                     __syncthreads();
                     for (int e = tid; e < cols * (ROWS / 4) * 2; e += kBlockL) {
