@@ -525,18 +525,22 @@ __device__ __forceinline__ void sweep2d_mixed_body(const KArgs& a, int64_t j, do
                                                   [&](int s, double) { return xo[off + (int64_t)s * nx]; });
         }
         __syncthreads();
+        double psi2 = 0.0;
         if (EX || sd.nr > 0)
             strip_stencil<double, S, EX>(sd, ldsd, [&](int s, double u_, double c_, double d_, double w_, double e_) {
-                const double res = explicit_part(a.fine, up[s]) - stencil_value(a.fine, u_, c_, d_, w_, e_);
+                const double ps = explicit_part(a.fine, up[s]);
+                psi2 += ps * ps;
+                const double res = ps - stencil_value(a.fine, u_, c_, d_, w_, e_);
                 r[s] = (float)res;
                 return res;
             });
-        __syncthreads();  // every read of the FP64 staging precedes its reuse as FP32
+        // (its barrier: every read of the FP64 staging precedes its reuse as FP32)
+        psi2 = block_sum1(psi2, red, slot, kWaves2D);
         if (!PER) lds_clear_halo(a.g, lpf);
 #pragma unroll
         for (int s = 0; s < S; ++s) x[s] = 0.0f;
         its += cg2d<float, S, EX, PER, true>(a.g, a.fine, sf, x, r, q, lpf, red, slot, a.rtol2_mixed, a.maxit,
-                                             a.fail);
+                                             a.fail, kDefectFloor2 * psi2);
         {
             const int64_t off = opaque_off(sd.gbase);
 #pragma unroll

@@ -386,7 +386,7 @@ __device__ __forceinline__ T stencil_value(const StepCoef& c, T up, T cen, T dn,
 // sets *fail and returns with the current iterate.  Returns the iteration count.
 template <typename T, int S, bool EXACT, bool PER, bool STOREQ>
 __device__ int cg2d(const Grid2D& g, const StepCoef& c, const Strip& st, T (&x)[S], T (&r)[S], T (&q)[S], T* lp,
-                    double* red, int& slot, double rtol2, int maxit, int* fail)
+                    double* red, int& slot, double rtol2, int maxit, int* fail, double bb_floor = 0.0)
 {
     constexpr int V = Lds2D<T>::V;
     typedef typename Lds2D<T>::vec vec;
@@ -405,8 +405,9 @@ __device__ int cg2d(const Grid2D& g, const StepCoef& c, const Strip& st, T (&x)[
             return r[s];
         });
     block_sum2(bb, rr, red, slot, kWaves2D);
-    // b = 0 has the solution x = 0 (set after the loop, which is skipped)
-    const bool bzero = (bb == 0.0);
+    // b = 0 has the solution x = 0 (set after the loop, which is skipped); so does a b at or below
+    // bb_floor (a defect at the rounding level of its own evaluation)
+    const bool bzero = !(bb > bb_floor);
     const double thresh = rtol2 * bb;
     double gamma = rr;
     // p~ = r (every reader of the staged x has passed the reduction's barrier)

@@ -163,6 +163,11 @@ hipError_t launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipSt
 // workgroup pairs for this grid and workspace (0 if the pair kernel does not take it), and the
 // cooperative launch.  Header::fail bit 2 marks a pair whose partner did not arrive.
 constexpr int kFailPairTimeout = 2;
+
+// The FP32 defect-correction steps take no correction for a defect rho = psi(v_{t-1}) - M s_t with
+// |rho| <= 1e-15 |psi(v_{t-1})|: it is of the order of the rounding of its own FP64 evaluation (a few
+// units of 1.1e-16 per point relative to psi(v)), so d = 0 is as good as any FP32 solve of it.
+constexpr double kDefectFloor2 = 1e-30;
 int sweep_pair_pairs(const KArgs& a, int64_t n_tasks);
 // workgroups of threads threads of kernel fn resident at once on the current device (0 if unknown)
 int resident_blocks(const void* fn, int threads);

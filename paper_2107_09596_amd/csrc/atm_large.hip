@@ -96,7 +96,7 @@ __device__ __forceinline__ Nb<T> load_nb(const Grid2D& g, const LCol& col, const
 template <typename T>
 __device__ int cg_large(const Grid2D& g, const StepCoef& c, const LCol& col, T* __restrict__ x, T* __restrict__ r,
                         T* __restrict__ p, T* __restrict__ q, double* red, int& slot, double rtol2, int maxit,
-                        int* fail)
+                        int* fail, double bb_floor = 0.0)
 {
     constexpr int U = kRowBatch;
     double bb = 0.0, rr = 0.0;
@@ -127,7 +127,7 @@ __device__ int cg_large(const Grid2D& g, const StepCoef& c, const LCol& col, T* 
         }
     }
     block_sum2(bb, rr, red, slot, kWavesL);
-    const bool bzero = (bb == 0.0);
+    const bool bzero = !(bb > bb_floor);
     const double thresh = rtol2 * bb;
     double gamma = rr;
     int it = 0;
@@ -326,15 +326,19 @@ __global__ __launch_bounds__(kBlockL) void sweep_large_mixed_kernel(KArgs a, LSc
             xo_ = (a.mode == 0 ? a.u + ((j + 1) * a.m) * n : (a.mode == 1 ? a.y : a.aux) + (j + 1) * n);
         const double* __restrict__ xo = xo_;
         double* __restrict__ dst = ystep ? a.y + (j + 1) * n : a.u + (j * a.m + t) * n;
+        double psi2 = 0.0;
         FOR_ROWS(col, g, y)
         {
             const int64_t i = (int64_t)y * g.nx + col.x;
-            const double rho = explicit_part(a.fine, prev[i]) - stencil_g(g, a.fine, col, xo, y);
+            const double ps = explicit_part(a.fine, prev[i]);
+            psi2 += ps * ps;
+            const double rho = ps - stencil_g(g, a.fine, col, xo, y);
             r[i] = (float)rho;
             x[i] = 0.0f;
         }
-        __syncthreads();
-        its += cg_large<float>(g, a.fine, col, x, r, p, q, red, slot, a.rtol2_mixed, a.maxit, a.fail);
+        psi2 = block_sum1(psi2, red, slot, kWavesL);  // its barrier also orders the stores above
+        its += cg_large<float>(g, a.fine, col, x, r, p, q, red, slot, a.rtol2_mixed, a.maxit, a.fail,
+                               kDefectFloor2 * psi2);
         FOR_ROWS(col, g, y)
         {
             const int64_t i = (int64_t)y * g.nx + col.x;

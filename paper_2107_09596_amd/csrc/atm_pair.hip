@@ -162,7 +162,7 @@ struct V2 {
     double a, b;
 };
 template <int NX, int R, typename VIN, typename VOUT>
-__device__ __forceinline__ void defect_pass(const StepCoef& c, const Half<NX, R>& h, float* P, const double* __restrict__ s,
+__device__ __forceinline__ double defect_pass(const StepCoef& c, const Half<NX, R>& h, float* P, const double* __restrict__ s,
                                             VIN&& vin, VOUT&& vout)
 {
     constexpr int H = Half<NX, R>::H, PW = NX + 2, NY = 2 * H;
@@ -172,6 +172,7 @@ __device__ __forceinline__ void defect_pass(const StepCoef& c, const Half<NX, R>
     // the neighbour columns at wrapped (always valid) addresses, zero beyond a Dirichlet edge
     const int cw = col > 0 ? col - 1 : NX - 1, ce = col < NX - 1 ? col + 1 : 0;
     const bool wm = col > 0 || h.periodic, em = col < NX - 1 || h.periodic;
+    double psi2 = 0.0;  // this thread's share of |psi(v)|^2
     for (int rb = threadIdx.x / NX; rb < H; rb += kBatch * RS) {
         const int r0 = (int)opq((uint32_t)rb);  // the offsets are formed here, not held across the CG
         V2 in[kBatch];
@@ -196,9 +197,12 @@ __device__ __forceinline__ void defect_pass(const StepCoef& c, const Half<NX, R>
             const double v = vout(in[b], o, li);
             const double u_ = (Y > 0 || h.periodic) ? up[b] : 0.0, d_ = (Y < NY - 1 || h.periodic) ? dn[b] : 0.0;
             const double w_ = wm ? w[b] : 0.0, e_ = em ? ea[b] : 0.0;
-            P[li] = (float)(explicit_part(c, v) - stencil_value(c, u_, cen[b], d_, w_, e_));
+            const double ps = explicit_part(c, v);
+            psi2 += ps * ps;
+            P[li] = (float)(ps - stencil_value(c, u_, cen[b], d_, w_, e_));
         }
     }
+    return psi2;
 }
 
 // the partner's mailbox slot of handshake k and the packs in it: first rows (r, p, p of the next
@@ -320,6 +324,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
     __syncthreads();
 
     float xv[R], rv[R], qv[R];
+    double psi_part = 0.0;  // this thread's share of |psi(v_{t-1})|^2 of the current defect
 
     for (int64_t j = h.pair; j <= a.NT && alive; j += pa.pairs) {
         const int64_t total = (j < a.NT) ? a.m : (a.nt - a.NT * a.m);
@@ -337,7 +342,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                 return c0;
             };
             if (total >= 1)
-                defect_pass<NX, R>(c, h, P, xo, start_in, start_out);
+                psi_part = defect_pass<NX, R>(c, h, P, xo, start_in, start_out);
             else if (a.mode != 0)
                 for (int e = threadIdx.x; e < H * NX; e += kThreads) {
                     const uint32_t o = (uint32_t)(h.half * H) * NX + e;
@@ -372,7 +377,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                 put(ms + pk_step, ra);
                 put(ms + 2 * pk_step, rb);
             }
-            double tot[kParts] = {0.0, 0.0, 0.0, rr_part};
+            double tot[kParts] = {psi_part, 0.0, 0.0, rr_part};
             if (!handshake<NX, R>(pa, h, k, tot, red, slot, parts, &flag)) {
                 alive = false;
                 break;
@@ -388,7 +393,8 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
             const double bb = uniform(tot[3]);
             const double thresh = a.rtol2_mixed * bb;
             int it = 0;
-            bool converged = !(bb > thresh);  // b = 0 (d = 0 is exact), or a tolerance that b meets
+            // b = 0 (d = 0 is exact), or a defect at the rounding level of its own FP64 evaluation
+            bool converged = !(bb > thresh) || !(bb > kDefectFloor2 * uniform(tot[0]));
             while (!converged && it < a.maxit) {
                 // the boundary packs, r and p before the update, stored first (their latency is hidden
                 // by the pass)
@@ -502,7 +508,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
             if (t < total) {
                 xn = (t + 1 < a.m) ? a.u + (j * a.m + t + 1) * n
                                    : (a.mode == 0 ? a.u + ((j + 1) * a.m) * n : (a.mode == 1 ? a.y : a.aux) + (j + 1) * n);
-                defect_pass<NX, R>(c, h, P, xn, upd_in, upd_out);
+                psi_part = defect_pass<NX, R>(c, h, P, xn, upd_in, upd_out);
             } else {
                 for (int e = threadIdx.x; e < H * NX; e += kThreads) {
                     const uint32_t o = (uint32_t)(h.half * H) * NX + e;
