@@ -39,6 +39,11 @@ PEAK_FP64_MFMA_TFLOPS = 78.6
 PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
+# relative tolerance of the headline's FP32 correction solves: the fastest of 1e-6 .. 1e-3 measured on
+# this workload (1e-6: 614 ms in 16 cycles, 1e-5: 557 ms / 16, 1e-4: 540 ms / 17, 3e-4: 519 ms / 17,
+# 1e-3: 549 ms / 19); the solve's own 1e-8 stopping test is the same at every setting
+HEADLINE_MIXED_RTOL = 3e-4
+
 # Algorithmic HBM bytes per fine point-update of the FP32-fine / FP64-residual sweep: the stored
 # FP64 value of the point is read once (its defect) and the FP64 result written once.
 SWEEP_MIXED_BYTES_PER_POINT = 16
@@ -466,6 +471,7 @@ def main():
     p, o, u0 = W.config("c3")
     o.profile = 1
     o.coarse_solver = 2  # Psi's eigenbasis solve on the BF16 matrix cores (split operands)
+    o.mixed_cg_rtol = HEADLINE_MIXED_RTOL
     dev = torch.device("cuda:0")
     guess = torch.from_numpy(W.initial_guess(p, u0)).to(dev)
     u = torch.empty_like(guess)
@@ -532,7 +538,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": f"2D Allen-Cahn 256x256 periodic, eps 0.02, dt 1e-5, Nt 8192, m 64, k {o.k}, FCF, "
-                               f"{o.coarse_substeps} coarse substeps (Psi in the eigenbasis on the BF16 matrix cores, split operands), FP32 fine CG to 1e-6 "
+                               f"{o.coarse_substeps} coarse substeps (Psi in the eigenbasis on the BF16 matrix cores, split operands), FP32 fine CG to {o.mixed_cg_rtol:g} "
                                f"of the defect, FP64 residual/correction/iterate, zero guess, tol 1e-8",
                    "global_batch": 1, "seq_len": p.nt, "parallelism": "time-parallel, 1 GPU"},
         "iterations": st["iterations"], "final_residual": st["final_residual"], "stopping_norm": hist[-1],
