@@ -403,7 +403,7 @@ atm_status header_status(const atm::Header& h, int maxit)
     return ATM_OK;
 }
 
-atm_status read_header(const atm::KArgs& a, hipStream_t s, atm::Header* out)
+atm_status pinned_header(atm::Header** out)
 {
     static thread_local atm::Header* pinned = nullptr;
     if (!pinned) {
@@ -411,9 +411,47 @@ atm_status read_header(const atm::KArgs& a, hipStream_t s, atm::Header* out)
         ATM_HIP(hipHostMalloc(&ptr, sizeof(atm::Header), hipHostMallocDefault));
         pinned = static_cast<atm::Header*>(ptr);
     }
+    *out = pinned;
+    return ATM_OK;
+}
+
+atm_status read_header(const atm::KArgs& a, hipStream_t s, atm::Header* out)
+{
+    atm::Header* pinned = nullptr;
+    atm_status st = pinned_header(&pinned);
+    if (st) return st;
     ATM_HIP(hipMemcpyAsync(pinned, a.hdr, sizeof(atm::Header), hipMemcpyDeviceToHost, s));
     ATM_HIP(hipStreamSynchronize(s));
     *out = *pinned;
+    return ATM_OK;
+}
+
+// The norm kernels publish the header into the pinned buffer themselves (publish_header): arm the
+// buffer with a mark no norm produces before the launch, and read it after synchronising.
+constexpr uint64_t kUnpublished = 0x7FF4DEADBEEF0002ull;
+
+atm_status arm_published(atm::KArgs& a)
+{
+    atm::Header* pinned = nullptr;
+    atm_status st = pinned_header(&pinned);
+    if (st) return st;
+    memcpy(&pinned->norm2, &kUnpublished, sizeof(double));
+    a.hdr_host = pinned;
+    return ATM_OK;
+}
+
+atm_status read_published(const atm::KArgs& a, hipStream_t s, atm::Header* out)
+{
+    ATM_HIP(hipStreamSynchronize(s));
+    const volatile atm::Header* h = a.hdr_host;
+    out->norm2 = h->norm2;
+    out->fail = h->fail;
+    out->cg_fine = h->cg_fine;
+    out->cg_coarse = h->cg_coarse;
+    out->skipped = h->skipped;
+    uint64_t bits;
+    memcpy(&bits, &out->norm2, sizeof(bits));
+    if (bits == kUnpublished) return fail(ATM_ERR_DEVICE, "the norm kernel did not publish its header");
     return ATM_OK;
 }
 
@@ -463,10 +501,12 @@ atm_status do_norm(atm::KArgs a, double* u, double* y, hipStream_t s, double* no
 {
     a.u = u;
     a.y = y;
-    atm::launch_norm(a, s);
-    atm_status st = check_launch();
+    atm_status st = arm_published(a);
     if (st) return st;
-    st = read_header(a, s, hdr);
+    atm::launch_norm(a, s);
+    st = check_launch();
+    if (st) return st;
+    st = read_published(a, s, hdr);
     if (st) return st;
     *norm_out = sqrt(hdr->norm2);
     return header_status(*hdr, a.maxit);
@@ -478,7 +518,7 @@ atm_status finish_norm(const atm::KArgs& a, hipStream_t s, double* norm_out, atm
 {
     atm_status st = check_launch();
     if (st) return st;
-    st = read_header(a, s, hdr);
+    st = read_published(a, s, hdr);
     if (st) return st;
     *norm_out = sqrt(hdr->norm2);
     return header_status(*hdr, a.maxit);
@@ -492,6 +532,8 @@ atm_status do_implicit_norm(atm::KArgs a, const double* u, hipStream_t s, double
         return fail(ATM_ERR_UNSUPPORTED, "implicit residual: %lld partial sums exceed the workspace's %lld",
                     (long long)atm::implicit_residual_blocks(a), (long long)cap);
     a.u = (double*)u;
+    atm_status st = arm_published(a);
+    if (st) return st;
     atm::launch_implicit_residual(a, s);
     return finish_norm(a, s, norm_out, hdr);
 }
@@ -500,6 +542,8 @@ atm_status do_step_norm(atm::KArgs a, const atm_problem* p, const atm_options* o
                         double* norm_out, atm::Header* hdr)
 {
     a.u = (double*)u;
+    atm_status st = arm_published(a);
+    if (st) return st;
     if (a.large)
         atm::launch_step_residual_large(a, sweep_tasks(p, o), s);
     else

@@ -209,7 +209,32 @@ __global__ __launch_bounds__(kNormBlock) void norm_final_kernel(KArgs a, int64_t
     double acc = 0.0, unused = 0.0;
     for (int64_t j = threadIdx.x; j < count; j += kNormBlock) acc += a.partials[j];
     block_sum2(acc, unused, red, slot, kNormBlock / 64);
-    if (threadIdx.x == 0) a.hdr->norm2 = acc;
+    if (threadIdx.x == 0) {
+        a.hdr->norm2 = acc;
+        publish_header(a);
+    }
+}
+
+// The same sum in one workgroup for small problems (N_T n <= kNormSmall): thread t adds the squares of
+// the elements t, t + 1024, ... of the C-point residuals in order, then the block sum
+constexpr int kNormSmallBlock = 1024;
+constexpr int64_t kNormSmall = 1 << 16;
+__global__ __launch_bounds__(kNormSmallBlock) void norm_small_kernel(KArgs a)
+{
+    __shared__ double red[2 * 2 * (kNormSmallBlock / 64)];
+    int slot = 0;
+    double acc = 0.0, unused = 0.0;
+    const int64_t total = a.NT * a.n;
+    for (int64_t e = threadIdx.x; e < total; e += kNormSmallBlock) {
+        const int64_t j = e / a.n + 1, idx = e % a.n;
+        const double r = a.y[j * a.n + idx] - a.u[(j * a.m) * a.n + idx];
+        acc += r * r;
+    }
+    block_sum2(acc, unused, red, slot, kNormSmallBlock / 64);
+    if (threadIdx.x == 0) {
+        a.hdr->norm2 = acc;
+        publish_header(a);
+    }
 }
 
 __global__ void reset_header_kernel(Header* h)
@@ -335,6 +360,10 @@ void launch_coarse(const KArgs& a, hipStream_t s)
 
 void launch_norm(const KArgs& a, hipStream_t s)
 {
+    if (a.NT * a.n <= kNormSmall) {
+        hipLaunchKernelGGL(norm_small_kernel, dim3(1), dim3(kNormSmallBlock), 0, s, a);
+        return;
+    }
     const int64_t chunks = norm_chunks(a);
     const int64_t blocks = a.NT >= 1 ? a.NT * chunks : 0;
     if (blocks > 0) hipLaunchKernelGGL(norm_partial_kernel, dim3(blocks), dim3(kNormBlock), 0, s, a, chunks);

@@ -28,6 +28,7 @@ struct KArgs {
     double* tau;        // FAS right-hand side, [N_T+1][n]
     double* partials;   // [max(N_T+1, kResidBlocks)] partial sums of norms
     Header* hdr;
+    Header* hdr_host;   // nullable: pinned host copy of the header, written by the kernel that ends a norm
     int* fail;
     unsigned long long* cg_count;
     // sizes
@@ -93,6 +94,20 @@ __device__ __forceinline__ double sweep_start(const KArgs& a, int64_t j, int64_t
     if (a.mode == 1) return uc + a.aux[j * a.n + idx];
     if (a.mode == 2) return j == 0 ? uc : a.aux[j * a.n + idx];
     return uc;
+}
+
+// The kernel that ends a norm (thread 0, after writing norm2) copies the header into the caller's
+// pinned host buffer with system-scope stores, so that the host reads it after synchronising without
+// a separate copy.
+__device__ __forceinline__ void publish_header(const KArgs& a)
+{
+    if (!a.hdr_host) return;
+    const Header h = *a.hdr;
+    __hip_atomic_store(&a.hdr_host->norm2, h.norm2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&a.hdr_host->fail, h.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&a.hdr_host->cg_fine, h.cg_fine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&a.hdr_host->cg_coarse, h.cg_coarse, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(&a.hdr_host->skipped, h.skipped, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __device__ __forceinline__ void count_cg(const KArgs& a, long long its)

@@ -1165,7 +1165,10 @@ __global__ __launch_bounds__(256) void sum_partials_large_kernel(KArgs a, int64_
     double acc = 0.0, unused = 0.0;
     for (int64_t b = threadIdx.x; b < count; b += 256) acc += a.partials[b];
     block_sum2(acc, unused, red, slot, 4);
-    if (threadIdx.x == 0) a.hdr->norm2 = acc;
+    if (threadIdx.x == 0) {
+        a.hdr->norm2 = acc;
+        publish_header(a);
+    }
 }
 
 hipError_t launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipStream_t s)

@@ -229,7 +229,10 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(KArgs a, int64_t coun
     double acc = 0.0, unused = 0.0;
     for (int64_t b = threadIdx.x; b < count; b += 256) acc += a.partials[b];
     block_sum2(acc, unused, red, slot, 4);
-    if (threadIdx.x == 0) a.hdr->norm2 = acc;
+    if (threadIdx.x == 0) {
+        a.hdr->norm2 = acc;
+        publish_header(a);
+    }
 }
 
 #define ATM_MIXED_S(kernel, S, EX, PER, grid, stream, a) \
