@@ -144,7 +144,7 @@ Layout layout(const atm_problem* p, const atm_options* o)
     off += ml_bf(p, o) ? align_up(slab2)
                        : ((spectral(p, o) && o->coarse_solver == 2 && !large_grid(p)) ? align_up(slab) : 0);
     L.traj = off;  // the paired BF16 windows, FAS form with s > 1 substeps: v through Psi's first s - 1
-    off += traj_rows(p, o) ? align_up((size_t)traj_rows(p, o) * (size_t)n_space(p) * sizeof(double)) : 0;
+    off += traj_rows(p, o) ? align_up((size_t)traj_rows(p, o) * (size_t)n_space(p) * sizeof(float)) : 0;
     // three levels: the level-1 iterate [N_T+1][n]; the level-1 sweeps' y (two), the level-2 FAS
     // right-hand side and corrections, [N_2+1][n] each
     L.u1 = off;
@@ -337,7 +337,7 @@ atm_status make_args_in(const atm_problem* p, const atm_options* o, void* ws, si
     a.spectral = spectral(p, o) ? (o->coarse_solver == 2 ? 2 : 1) : 0;
     a.spec = (a.spectral || ml_bf(p, o)) ? (double*)(base + L.spec) : nullptr;
     a.cres = (a.spectral == 2 && !large_grid(p)) ? (double*)(base + L.cres) : nullptr;
-    a.traj = traj_rows(p, o) ? (double*)(base + L.traj) : nullptr;
+    a.traj = traj_rows(p, o) ? (float*)(base + L.traj) : nullptr;
     if (large_grid(p)) {
         a.large = 1;
         a.large_scratch = (double*)(base + L.large);

@@ -723,8 +723,8 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_kernel(KArgs a, LScratch 
             for (int q = 0; alive && q < steps; ++q) {
                 alive = spectral_step_pair<NT>(a, T, w, t0, t1, t2, gl, r0, rows, wp, pr, half, k, &ok);
                 if (MODE == kTrajTask && alive) {
-                    double* dst = a.traj + ((task - 1) * (a.substeps - 1) + q) * n;
-                    for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) dst[o + e] = w[o + e];
+                    float* dst = a.traj + ((task - 1) * (a.substeps - 1) + q) * n;
+                    for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) dst[o + e] = (float)w[o + e];
                 }
             }
             if (!alive || !WIN) break;
@@ -752,14 +752,16 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_kernel(KArgs a, LScratch 
 // ---------------------------------------------------------------------------
 // The paired windows with Psi's eigenbasis solve on the BF16 matrix cores (coarse_solver 2)
 // ---------------------------------------------------------------------------
-// A window carries e (the correction; FAS form: e = w - v) in FP64 in its global scratch.  Every
-// substep forms its explicit part in FP64 -- the FAS form the difference of the explicit parts at
-// v + e and at v, e + react (e - e (3 v^2 + 3 v e + e^2)), so that the products' error scales with e
-// and vanishes with it -- splits it into BF16 planes hi + lo and applies M^-1 by the four products
+// A window carries e (the correction; FAS form: e = w - v) in FP32 in its global scratch (the products
+// are accurate to about 1e-5 of e, FP32 keeps 6e-8).  Every substep forms its explicit part in FP64 --
+// the FAS form the difference of the explicit parts at v + e and at v, e + react (e - e (3 v^2 + 3 v e
+// + e^2)), so that the products' error scales with e and vanishes with it -- splits it into BF16 planes
+// hi + lo and applies M^-1 by the four products
 // of the eigenbasis solve, each taken as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
 // sums (about 16 significant bits per operand: Psi to about 1e-5 relative, which changes the
 // two-level convergence rate and never the fixed point).  v passes through Psi's substeps as well:
-// v^(0) = v_{j-1} is the C-point, v^(1 .. s-1) are the FP64 trajectory (kTrajTask).
+// v^(0) = v_{j-1} is the C-point, v^(1 .. s-1) come from the FP64 trajectory (kTrajTask), stored in
+// FP32 (v enters only the explicit parts' difference, multiplied by e).
 //
 // Every product is OutT[j][i] = sum_k A[i][k] BT[j][k] with A [M][K] and BT [N][K] stored
 // k-contiguous (BF16 hi and lo planes), so that each lane reads 8 consecutive k of a fragment and
@@ -926,14 +928,14 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScrat
     unsigned k = 0;
     bool alive = true;
     for (int64_t task = pr; alive && task <= a.NT; task += wp.pairs) {
-        double* __restrict__ w = sc.vec(task, 4);
+        float* __restrict__ w = reinterpret_cast<float*>(sc.vec(task, 4));
         __bf16* bt = reinterpret_cast<__bf16*>(sc.vec(task, 0));  // bT [NX][NY], hi then lo plane
         __bf16* t1 = reinterpret_cast<__bf16*>(sc.vec(task, 1));  // t1 [NY][NX] (the half's rows)
         __bf16* t2 = reinterpret_cast<__bf16*>(sc.vec(task, 2));  // t2T [NX][NY]
         const BfOp opb{bt, bt + n, NY}, opt2{t2, t2 + n, NY};
         const BfOp opt1{t1 + o, t1 + n + o, NX};
         const int64_t s0 = task - a.k + 1 > 0 ? task - a.k + 1 : 0;
-        for (int64_t e = tid; e < cnt; e += kBlockL) w[o + e] = cpoint_residual(a, s0, o + e);
+        for (int64_t e = tid; e < cnt; e += kBlockL) w[o + e] = (float)cpoint_residual(a, s0, o + e);
         __syncthreads();
         // C[x][i] -> t1[i][x .. x+3] (the half's rows)
         auto to_t1 = [&](int x, int i, f32x4_t v) {
@@ -944,9 +946,9 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScrat
         };
         for (int64_t jj = s0 + 1; alive && jj <= task; ++jj) {
             for (int q = 0; alive && q < a.substeps; ++q) {
-                const double* v = !a.fas ? nullptr
-                                : q == 0 ? a.u + ((jj - 1) * a.m) * n
-                                         : a.traj + ((jj - 1) * (a.substeps - 1) + q - 1) * n;
+                const double* v64 = (a.fas && q == 0) ? a.u + ((jj - 1) * a.m) * n : nullptr;
+                const float* v32 = (a.fas && q > 0) ? a.traj + ((jj - 1) * (a.substeps - 1) + q - 1) * n : nullptr;
+                const bool fas = a.fas != 0;
                 // the explicit part in FP64, split, and transposed through LDS into bT[x][r0 ..], in
                 // two passes of 128 columns
                 for (int c0 = 0; c0 < NX; c0 += 128) {
@@ -959,15 +961,15 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScrat
                         for (int u = 0; u < 4; ++u) {
                             const int e = b0 + u * kBlockL, y = e / cols, x = c0 + e % cols;
                             const int64_t i = o + (int64_t)y * NX + x;
-                            ew[u] = w[i];
-                            vw[u] = v ? v[i] : 0.0;
+                            ew[u] = (double)w[i];
+                            vw[u] = v64 ? v64[i] : (v32 ? (double)v32[i] : 0.0);
                         }
 #pragma unroll
                         for (int u = 0; u < 4; ++u) {
                             const int e = b0 + u * kBlockL, y = e / cols, x = e % cols;
                             const double ee = ew[u], vv = vw[u];
-                            const double b = v ? ee + react * (ee - ee * (3.0 * vv * vv + 3.0 * vv * ee + ee * ee))
-                                               : explicit_part(a.coarse, ee);
+                            const double b = fas ? ee + react * (ee - ee * (3.0 * vv * vv + 3.0 * vv * ee + ee * ee))
+                                                 : explicit_part(a.coarse, ee);
                             const __bf16 h = (__bf16)b;
                             lds[x * kBfTP + y] = h;
                             lds[(128 + x) * kBfTP + y] = (__bf16)(b - (double)h);
@@ -998,18 +1000,17 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScrat
                 bf_gemm<NXT, RT, true>(opt2, qy, NY, lds, to_t1);  // Qy ..
                 __syncthreads();
                 bf_gemm<NXT, RT, false>(qx, opt1, NX, lds, [&](int x, int i, f32x4_t c) {  // .. Qx^T
-                    double* dst = w + o + (int64_t)i * NX + x;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) dst[r] = (double)c[r];
+                    *reinterpret_cast<f32x4_t*>(w + o + (int64_t)i * NX + x) = c;
                 });
                 __syncthreads();
             }
             if (!alive) break;
-            for (int64_t e = tid; e < cnt; e += kBlockL) w[o + e] = w[o + e] + cpoint_residual(a, jj, o + e);
+            for (int64_t e = tid; e < cnt; e += kBlockL)
+                w[o + e] = (float)((double)w[o + e] + cpoint_residual(a, jj, o + e));
             __syncthreads();
         }
         if (!alive) break;
-        for (int64_t e = tid; e < cnt; e += kBlockL) a.e[task * n + o + e] = w[o + e];
+        for (int64_t e = tid; e < cnt; e += kBlockL) a.e[task * n + o + e] = (double)w[o + e];
         __syncthreads();
     }
     if (!alive && tid == 0) atomicOr(a.fail, kFailPairTimeout);
