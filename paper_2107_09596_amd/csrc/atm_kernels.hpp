@@ -71,8 +71,8 @@ struct KArgs {
     // coarse solve so that each window step reads one row (grids up to 128 per side)
     double* cres;
     // spectral 2 on the paired large-grid windows, FAS form with s > 1 substeps: v_{j-1} carried
-    // through Psi's first s - 1 substeps (FP64 steps, stored in FP32), [N_T][s - 1][n] (entry
-    // (j - 1, q - 1): q substeps from the C-point u_{(j-1)m})
+    // through Psi's first s - 1 substeps (the BF16 eigenbasis solve, stored in FP32), [N_T][s - 1][n]
+    // (entry (j - 1, q - 1): q substeps from the C-point u_{(j-1)m})
     float* traj;
 };
 

@@ -684,10 +684,9 @@ __device__ __forceinline__ bool spectral_step_pair(const KArgs& a, const SpecTab
     return true;
 }
 
-// The tasks of the paired kernels: windows p = 0 .. N_T (linear or FAS form); the FAS right-hand
-// sides tau_j = (v_j - Psi(v_{j-1})) + r_j, j = 1 .. N_T; or the trajectory of v_{j-1} through Psi's
-// first s - 1 substeps, j = 1 .. N_T (the BF16 windows' FAS form in terms of e).
-enum PairTask { kWinTask = 0, kTauTask = 1, kTrajTask = 2 };
+// The tasks of the paired kernels: windows p = 0 .. N_T (linear or FAS form), or the FAS right-hand
+// sides tau_j = (v_j - Psi(v_{j-1})) + r_j, j = 1 .. N_T.
+enum PairTask { kWinTask = 0, kTauTask = 1 };
 
 // Pair q takes the tasks q, q + pairs, ... of its kind.
 template <int NT, int MODE>
@@ -718,15 +717,9 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_kernel(KArgs a, LScratch 
             }
         }
         __syncthreads();
-        const int steps = MODE == kTrajTask ? a.substeps - 1 : a.substeps;
         for (int64_t jj = s0 + 1; alive && jj <= task; ++jj) {
-            for (int q = 0; alive && q < steps; ++q) {
+            for (int q = 0; alive && q < a.substeps; ++q)
                 alive = spectral_step_pair<NT>(a, T, w, t0, t1, t2, gl, r0, rows, wp, pr, half, k, &ok);
-                if (MODE == kTrajTask && alive) {
-                    float* dst = a.traj + ((task - 1) * (a.substeps - 1) + q) * n;
-                    for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) dst[o + e] = (float)w[o + e];
-                }
-            }
             if (!alive || !WIN) break;
             for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) {
                 const int64_t i = o + e;
@@ -735,14 +728,12 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_kernel(KArgs a, LScratch 
             __syncthreads();
         }
         if (!alive) break;
-        if (MODE != kTrajTask) {
-            for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) {
-                const int64_t i = o + e;
-                if (MODE == kTauTask)
-                    a.tau[task * n + i] = (a.u[(task * a.m) * n + i] - w[i]) + cpoint_residual(a, task, i);
-                else
-                    a.e[task * n + i] = a.fas ? w[i] - a.u[(task * a.m) * n + i] : w[i];
-            }
+        for (int64_t e = threadIdx.x; e < cnt; e += kBlockL) {
+            const int64_t i = o + e;
+            if (MODE == kTauTask)
+                a.tau[task * n + i] = (a.u[(task * a.m) * n + i] - w[i]) + cpoint_residual(a, task, i);
+            else
+                a.e[task * n + i] = a.fas ? w[i] - a.u[(task * a.m) * n + i] : w[i];
         }
         __syncthreads();
     }
@@ -760,8 +751,9 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_kernel(KArgs a, LScratch 
 // of the eigenbasis solve, each taken as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
 // sums (about 16 significant bits per operand: Psi to about 1e-5 relative, which changes the
 // two-level convergence rate and never the fixed point).  v passes through Psi's substeps as well:
-// v^(0) = v_{j-1} is the C-point, v^(1 .. s-1) come from the FP64 trajectory (kTrajTask), stored in
-// FP32 (v enters only the explicit parts' difference, multiplied by e).
+// v^(0) = v_{j-1} is the C-point, v^(1 .. s-1) its trajectory through Psi's substeps, computed once per
+// coarse solve by the same kernel (TRAJ) with the same products and stored in FP32 (v enters only the
+// explicit parts' difference, multiplied by e, so its own 1e-5 does not reach the fixed point).
 //
 // Every product is OutT[j][i] = sum_k A[i][k] BT[j][k] with A [M][K] and BT [N][K] stored
 // k-contiguous (BF16 hi and lo planes), so that each lane reads 8 consecutive k of a fragment and
@@ -907,8 +899,10 @@ __device__ __forceinline__ void bf_gemm(const BfOp A, const BfOp B, int K, __bf1
             out(wm * 16 * TM + 16 * tm + 4 * lk, wn * 16 * TN + 16 * tn + li, acc[tm][tn]);
 }
 
-// the window's tasks p = q, q + pairs, ... on pair q; nx = 64 NXT, half rows ny / 2 = 64 RT
-template <int NXT, int RT>
+// the window's tasks p = q, q + pairs, ... on pair q; nx = 64 NXT, half rows ny / 2 = 64 RT.  TRAJ: the
+// tasks j = 1 .. N_T instead: v_{j-1} = u_{(j-1)m} carried through Psi's first s - 1 substeps (the plain
+// explicit part, the same products), each substep's result stored in a.traj
+template <int NXT, int RT, bool TRAJ = false>
 __global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScratch sc, WinPair wp)
 {
     __shared__ __align__(16) __bf16 lds[2 * kBfBuf];
@@ -927,15 +921,16 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScrat
     const double react = a.coarse.react;
     unsigned k = 0;
     bool alive = true;
-    for (int64_t task = pr; alive && task <= a.NT; task += wp.pairs) {
+    for (int64_t task = (TRAJ ? 1 : 0) + pr; alive && task <= a.NT; task += wp.pairs) {
         float* __restrict__ w = reinterpret_cast<float*>(sc.vec(task, 4));
         __bf16* bt = reinterpret_cast<__bf16*>(sc.vec(task, 0));  // bT [NX][NY], hi then lo plane
         __bf16* t1 = reinterpret_cast<__bf16*>(sc.vec(task, 1));  // t1 [NY][NX] (the half's rows)
         __bf16* t2 = reinterpret_cast<__bf16*>(sc.vec(task, 2));  // t2T [NX][NY]
         const BfOp opb{bt, bt + n, NY}, opt2{t2, t2 + n, NY};
         const BfOp opt1{t1 + o, t1 + n + o, NX};
-        const int64_t s0 = task - a.k + 1 > 0 ? task - a.k + 1 : 0;
-        for (int64_t e = tid; e < cnt; e += kBlockL) w[o + e] = (float)cpoint_residual(a, s0, o + e);
+        const int64_t s0 = TRAJ ? task - 1 : (task - a.k + 1 > 0 ? task - a.k + 1 : 0);
+        for (int64_t e = tid; e < cnt; e += kBlockL)
+            w[o + e] = TRAJ ? (float)a.u[(s0 * a.m) * n + o + e] : (float)cpoint_residual(a, s0, o + e);
         __syncthreads();
         // C[x][i] -> t1[i][x .. x+3] (the half's rows)
         auto to_t1 = [&](int x, int i, f32x4_t v) {
@@ -945,10 +940,10 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScrat
             *reinterpret_cast<uint64_t*>(t1 + n + o + (int64_t)i * NX + x) = l;
         };
         for (int64_t jj = s0 + 1; alive && jj <= task; ++jj) {
-            for (int q = 0; alive && q < a.substeps; ++q) {
-                const double* v64 = (a.fas && q == 0) ? a.u + ((jj - 1) * a.m) * n : nullptr;
-                const float* v32 = (a.fas && q > 0) ? a.traj + ((jj - 1) * (a.substeps - 1) + q - 1) * n : nullptr;
-                const bool fas = a.fas != 0;
+            for (int q = 0; alive && q < (TRAJ ? a.substeps - 1 : a.substeps); ++q) {
+                const bool fas = !TRAJ && a.fas != 0;
+                const double* v64 = (fas && q == 0) ? a.u + ((jj - 1) * a.m) * n : nullptr;
+                const float* v32 = (fas && q > 0) ? a.traj + ((jj - 1) * (a.substeps - 1) + q - 1) * n : nullptr;
                 // the explicit part in FP64, split, and transposed through LDS into bT[x][r0 ..], in
                 // two passes of 128 columns
                 for (int c0 = 0; c0 < NX; c0 += 128) {
@@ -1001,17 +996,22 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScrat
                 __syncthreads();
                 bf_gemm<NXT, RT, false>(qx, opt1, NX, lds, [&](int x, int i, f32x4_t c) {  // .. Qx^T
                     *reinterpret_cast<f32x4_t*>(w + o + (int64_t)i * NX + x) = c;
+                    if (TRAJ)
+                        *reinterpret_cast<f32x4_t*>(a.traj + ((task - 1) * (a.substeps - 1) + q) * n + o +
+                                                    (int64_t)i * NX + x) = c;
                 });
                 __syncthreads();
             }
-            if (!alive) break;
+            if (!alive || TRAJ) break;
             for (int64_t e = tid; e < cnt; e += kBlockL)
                 w[o + e] = (float)((double)w[o + e] + cpoint_residual(a, jj, o + e));
             __syncthreads();
         }
         if (!alive) break;
-        for (int64_t e = tid; e < cnt; e += kBlockL) a.e[task * n + o + e] = (double)w[o + e];
-        __syncthreads();
+        if (!TRAJ) {
+            for (int64_t e = tid; e < cnt; e += kBlockL) a.e[task * n + o + e] = (double)w[o + e];
+            __syncthreads();
+        }
     }
     if (!alive && tid == 0) atomicOr(a.fail, kFailPairTimeout);
 }
@@ -1194,11 +1194,11 @@ struct CoarsePair {
     int pairs;
 };
 
-template <int NT>
+template <int NT, bool TRAJ = false>
 static const void* bf_window_kernel(int rt)
 {
-    if (rt == 1) return (const void*)coarse_pair_bf_kernel<NT, 1>;
-    if (rt == 2) return (const void*)coarse_pair_bf_kernel<NT, 2>;
+    if (rt == 1) return (const void*)coarse_pair_bf_kernel<NT, 1, TRAJ>;
+    if (rt == 2) return (const void*)coarse_pair_bf_kernel<NT, 2, TRAJ>;
     return nullptr;
 }
 
@@ -1214,9 +1214,9 @@ static CoarsePair coarse_pair(const KArgs& a)
         if (nt == 3) cp.win = bf_window_kernel<3>(rt);
         if (nt == 2) cp.win = bf_window_kernel<2>(rt);
         if (a.fas && a.substeps > 1) {
-            if (nt == 4) cp.pre = (const void*)coarse_pair_kernel<4, kTrajTask>;
-            if (nt == 3) cp.pre = (const void*)coarse_pair_kernel<3, kTrajTask>;
-            if (nt == 2) cp.pre = (const void*)coarse_pair_kernel<2, kTrajTask>;
+            if (nt == 4) cp.pre = bf_window_kernel<4, true>(rt);
+            if (nt == 3) cp.pre = bf_window_kernel<3, true>(rt);
+            if (nt == 2) cp.pre = bf_window_kernel<2, true>(rt);
         }
     } else {
         if (nt == 4) cp = {(const void*)coarse_pair_kernel<4, kTauTask>, (const void*)coarse_pair_kernel<4, kWinTask>, 0};
