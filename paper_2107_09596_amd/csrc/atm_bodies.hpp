@@ -540,7 +540,7 @@ __device__ __forceinline__ void sweep2d_mixed_body(const KArgs& a, int64_t j, do
 #pragma unroll
         for (int s = 0; s < S; ++s) x[s] = 0.0f;
         its += cg2d<float, S, EX, PER, true>(a.g, a.fine, sf, x, r, q, lpf, red, slot, a.rtol2_mixed, a.maxit,
-                                             a.fail, kDefectFloor2 * psi2);
+                                             a.fail, defect_floor2(a.fine) * psi2);
         {
             const int64_t off = opaque_off(sd.gbase);
 #pragma unroll

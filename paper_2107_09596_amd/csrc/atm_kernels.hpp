@@ -180,9 +180,14 @@ hipError_t launch_sweep_large(const KArgs& a, int64_t n_tasks, bool mixed, hipSt
 constexpr int kFailPairTimeout = 2;
 
 // The FP32 defect-correction steps take no correction for a defect rho = psi(v_{t-1}) - M s_t with
-// |rho| <= 1e-15 |psi(v_{t-1})|: it is of the order of the rounding of its own FP64 evaluation (a few
-// units of 1.1e-16 per point relative to psi(v)), so d = 0 is as good as any FP32 solve of it.
-constexpr double kDefectFloor2 = 1e-30;
+// |rho| <= 4 eps (1 + 2 d) |psi(v_{t-1})| (eps = 2^-53, d the step operator's diagonal): the terms of
+// its FP64 evaluation add up to about (1 + 2 d) |v| per point, so such a defect is of the order of
+// that evaluation's own rounding, and d = 0 is as good as any FP32 solve of it.
+__host__ __device__ inline double defect_floor2(const StepCoef& c)
+{
+    const double f = 4.0 * 1.1102230246251565e-16 * (1.0 + 2.0 * c.d);
+    return f * f;
+}
 int sweep_pair_pairs(const KArgs& a, int64_t n_tasks);
 // workgroups of threads threads of kernel fn resident at once on the current device (0 if unknown)
 int resident_blocks(const void* fn, int threads);

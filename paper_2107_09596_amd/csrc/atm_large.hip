@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kBlockL) void sweep_large_mixed_kernel(KArgs a, LSc
         }
         psi2 = block_sum1(psi2, red, slot, kWavesL);  // its barrier also orders the stores above
         its += cg_large<float>(g, a.fine, col, x, r, p, q, red, slot, a.rtol2_mixed, a.maxit, a.fail,
-                               kDefectFloor2 * psi2);
+                               defect_floor2(a.fine) * psi2);
         FOR_ROWS(col, g, y)
         {
             const int64_t i = (int64_t)y * g.nx + col.x;

@@ -391,10 +391,32 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
             }
             __syncthreads();
             const double bb = uniform(tot[3]);
-            const double thresh = a.rtol2_mixed * bb;
             int it = 0;
             // b = 0 (d = 0 is exact), or a defect at the rounding level of its own FP64 evaluation
-            bool converged = !(bb > thresh) || !(bb > kDefectFloor2 * uniform(tot[0]));
+            bool converged = !(bb > 0.0) || !(bb > defect_floor2(c) * uniform(tot[0]));
+            // The CG runs on the unit right-hand side rho / |rho| (its sums stay clear of FP32's
+            // underflow however small the defect) and d = |rho| x.  Both halves scale by the same factor
+            // of the pair's total, so the ghost rows (the partner's unscaled r) scale to the partner's
+            // own values.
+            const double sig = converged ? 1.0 : sqrt(bb);
+            const float inv = uniform((float)(1.0 / sig)), sig32 = uniform((float)sig);
+            const double thresh = a.rtol2_mixed;
+            if (!converged) {
+                float chunk = 0.0f;
+                rr_part = 0.0;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    rv[i] = rv[i] * inv;
+                    Pr[i * PW] = rv[i];
+                    chunk += rv[i] * rv[i];
+                    if ((i & 7) == 7 || i == R - 1) {
+                        rr_part += (double)chunk;
+                        chunk = 0.0f;
+                    }
+                }
+                *Pg = *Pg * inv;
+                __syncthreads();
+            }
             while (!converged && it < a.maxit) {
                 // the boundary packs, r and p before the update, stored first (their latency is hidden
                 // by the pass)
@@ -493,7 +515,8 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
             // d goes to the p rows of LDS (p is no longer needed), then a row-order pass forms v_t and
             // the next defect in its place
 #pragma unroll
-            for (int i = 0; i < R; ++i) Pr[i * PW] = i < R - XL ? xv[i] : XS[(i - (R - XL)) * kThreads + threadIdx.x];
+            for (int i = 0; i < R; ++i)
+                Pr[i * PW] = sig32 * (i < R - XL ? xv[i] : XS[(i - (R - XL)) * kThreads + threadIdx.x]);
             __syncthreads();
             const bool ystep = (t == a.m);
             const double* so = xo;

@@ -142,6 +142,47 @@ def test_mixed_sweep_keeps_the_fp64_solution(atm, orc, case):
     assert_close(host(yd)[1:], seq[[j * m for j in range(1, NT + 1)]], rtol=1e-13, what="y at the C-points")
 
 
+FLOOR_CASES = [
+    # (kind, nx, ny, nt, m): the strip sweep, the large-grid sweep and the paired sweep
+    (W.AC2D, 32, 32, 24, 4),
+    (W.HEAT2D, 40, 24, 20, 4),
+    (W.AC2D, 320, 64, 8, 4),
+    (W.AC2D, 256, 256, 8, 4),
+]
+
+
+@pytest.mark.parametrize("case", FLOOR_CASES, ids=lambda c: f"k{c[0]}-{c[1]}x{c[2]}-nt{c[3]}-m{c[4]}")
+def test_rounding_level_defects_take_no_correction(atm, orc, case):
+    """Repeated F-relaxations of the oracle's sequential solution with its F-points perturbed: the first
+    corrects them; once their defects are at the rounding level of their own FP64 evaluation those steps
+    take no correction, so the iterate keeps its bits and the CG count settles to that of the steps that
+    form Phi of each interval's last F-point against the C-point that follows (unchanged by
+    F-relaxation, with the oracle's own CG error)."""
+    kind, nx, ny, nt, m = case
+    p, u0 = small(kind, nx, ny, nt)
+    o = W.Options(m=m, k=2, relax=1, precision=1, tol=0.0, max_iter=0)
+    seq = orc.sequential(p, u0)
+    g = seq.copy()
+    rng = np.random.default_rng(11)
+    for t in range(1, p.nt + 1):
+        if t % m:
+            g[t] += 1e-9 * np.max(np.abs(seq)) * rng.standard_normal(p.n)
+    ud = dev(g)
+    ws = atm.workspace(atm.atm_workspace_bytes(p, o))
+    counts, changed = [], []
+    prev = host(ud)
+    for _ in range(4):
+        _, _, st = atm.atm_solve(p, o, ud, ws=ws, allow=(atm.ATM_OK, atm.ATM_NOT_CONVERGED))
+        counts.append(st["cg_fine"])
+        cur = host(ud)
+        changed.append(not np.array_equal(cur, prev))
+        prev = cur
+    print(f"floor {case}: CG iterations per F-relaxation {counts}, iterate changed {changed}", flush=True)
+    assert changed[0] and not changed[-1]
+    assert counts[0] > counts[-1] == counts[-2]
+    np.testing.assert_allclose(prev, seq, rtol=0, atol=1e-12 * np.max(np.abs(seq)))
+
+
 MIXED_SOLVES = [
     # (kind, nx, ny, nt, m, k, relax)
     (W.HEAT2D, 64, 64, 96, 8, 3, 1),
