@@ -40,8 +40,8 @@ PEAK_BF16_MFMA_TFLOPS = 2500.0
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
 # relative tolerance of the headline's FP32 correction solves: the fastest of 1e-6 .. 1e-3 measured on
-# this workload (1e-6: 614 ms in 16 cycles, 1e-5: 557 ms / 16, 1e-4: 540 ms / 17, 3e-4: 519 ms / 17,
-# 1e-3: 549 ms / 19); the solve's own 1e-8 stopping test is the same at every setting
+# this workload (1e-6: 565 ms in 16 cycles, 1e-5: 515 ms / 16, 1e-4: 495 ms / 17, 3e-4: 470 ms / 17,
+# 1e-3: 496 ms / 19); the solve's own 1e-8 stopping test is the same at every setting
 HEADLINE_MIXED_RTOL = 3e-4
 
 # Algorithmic HBM bytes per fine point-update of the FP32-fine / FP64-residual sweep: the stored
