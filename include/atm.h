@@ -116,11 +116,14 @@ typedef struct atm_options {
                               coarse_cg_rtol).  Both take the same step: the eigenbasis solve is exact to
                               rounding, CG to its tolerance.  2: the eigenbasis solve on the BF16 matrix
                               cores with split operands (each value hi + lo in BF16, products in FP32),
-                              accurate to about 1e-5 relative; grids up to 128 per side.  In the FAS
-                              form (coarse_substeps 1) the windows carry e = w - v:
+                              accurate to about 1e-5 relative; grids up to 128 per side (FAS form with
+                              coarse_substeps 1), and the two-CU windows of grids with rows of 128, 192
+                              or 256 points and 128 or 256 rows (any coarse_substeps).  In the FAS
+                              form the windows carry e = w - v:
                               e_j = M^-1 (psi(v_{j-1} + e_{j-1}) - psi(v_{j-1})) + r_j, the explicit
                               parts' difference in FP64, so that the solve's error scales with e (a
-                              plain Psi(w) - Psi(v) would keep it) */
+                              plain Psi(w) - Psi(v) would keep it); with several substeps the difference
+                              is taken substep by substep along v's own path through them */
     int32_t levels;        /* 0 or 2: two-level AT-MGRIT (Alg. 1).  3: the multilevel FAS V-cycle of
                               Alg. 2 (section 2.2) over three levels: level 1 takes every m-th point of
                               the fine grid and steps with dt m in coarse_substeps substeps (CG to
