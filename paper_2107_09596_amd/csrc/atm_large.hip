@@ -747,10 +747,10 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_kernel(KArgs a, LScratch 
 // are accurate to about 1e-5 of e, FP32 keeps 6e-8).  Every substep forms its explicit part in FP64 --
 // the FAS form the difference of the explicit parts at v + e and at v, e + react (e - e (3 v^2 + 3 v e
 // + e^2)), so that the products' error scales with e and vanishes with it -- splits it into BF16 planes
-// hi + lo and applies M^-1 by the four products
-// of the eigenbasis solve, each taken as hi*hi + hi*lo + lo*hi on v_mfma_f32_16x16x32_bf16 with FP32
-// sums (about 16 significant bits per operand: Psi to about 1e-5 relative, which changes the
-// two-level convergence rate and never the fixed point).  v passes through Psi's substeps as well:
+// hi + lo and applies M^-1 by the four products of the eigenbasis solve, each taken as hi*hi + hi*lo +
+// lo*hi on v_mfma_f32_16x16x32_bf16 with FP32 sums (about 16 significant bits per operand: Psi to
+// about 1e-5 relative, which changes the two-level convergence rate and never the fixed point).  v
+// passes through Psi's substeps as well:
 // v^(0) = v_{j-1} is the C-point, v^(1 .. s-1) its trajectory through Psi's substeps, computed once per
 // coarse solve by the same kernel (TRAJ) with the same products and stored in FP32 (v enters only the
 // explicit parts' difference, multiplied by e, so its own 1e-5 does not reach the fixed point).
