@@ -49,6 +49,7 @@ struct PairArgs {
     int slot;         // floats per mailbox slot: pack_floats(NX), then kParts doubles
     int pack;         // pack_floats(NX): where the sums of a slot start
     int spin_cap;     // polls of the partner's counter before giving up
+    float* xg;        // rows of x kept in global memory: [2 pairs][x_global_rows][kThreads] floats
 };
 
 // A 32-bit offset hidden from the optimiser, so that the row offsets of the unrolled strip loops are
@@ -267,6 +268,12 @@ __device__ __forceinline__ bool handshake(const PairArgs& pa, const Half<NX, R>&
 // Rows of x a thread keeps in LDS rather than registers: the 256 x 256 grid's R = 64 rows of x, r and
 // M p fill the registers of a thread; LDS beyond p and the sums holds 14 of them.
 constexpr int x_lds_rows(int nx, int r) { return (nx == 256 && r == 64) ? 14 : 0; }
+// Rows of x kept in global memory (coalesced, one row of the workgroup's threads after another) on the
+// same grid: 16 more, which the update pass loads as one batch half-way through its rows, where the
+// compiler would otherwise spill about as many and reload them one at a time.
+constexpr int x_global_rows(int nx, int r) { return (nx == 256 && r == 64) ? 16 : 0; }
+constexpr int kXgMax = 16;
+constexpr int kXgLoadRow = 16;  // the update pass's row before which the batch is issued
 
 template <int NX, int R>
 __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, PairArgs pa)
@@ -283,6 +290,16 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
     // the last XL rows of x of every thread, in the LDS that p leaves free (fewer registers to spill)
     constexpr int XL = x_lds_rows(NX, R);
     __shared__ float XS[XL > 0 ? XL * kThreads : 1];
+    // rows XR .. R - XL - 1 of x in global memory, rows from R - XL in LDS, the first XR in registers
+    constexpr int XG = x_global_rows(NX, R), XR = R - XL - XG;
+    static_assert(XG <= kXgMax && (XG == 0 || kXgLoadRow <= XR) && R % 8 == 0, "x rows");
+    // (a uniform base and a 32-bit offset formed where it is used: one register per access, not one
+    // 64-bit address per row held across the time loop)
+    float* const XGb = XG > 0 ? pa.xg + (size_t)blockIdx.x * XG * kThreads : nullptr;
+    const uint32_t tid4 = threadIdx.x * 4u;
+    auto xg = [&](int j) -> float& {
+        return *reinterpret_cast<float*>(reinterpret_cast<char*>(XGb) + (opq((uint32_t)j * (kThreads * 4u)) + tid4));
+    };
     __shared__ double red[2 * kParts * kWaves];
     __shared__ double parts[2][kParts];
     __shared__ int flag;
@@ -357,8 +374,10 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                 float chunk = 0.0f;
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
-                    if (i < R - XL)
+                    if (i < XR)
                         xv[i] = 0.0f;
+                    else if (i < R - XL)
+                        xg(i - XR) = 0.0f;
                     else
                         XS[(i - (R - XL)) * kThreads + threadIdx.x] = 0.0f;
                     rv[i] = Pr[i * PW];
@@ -474,28 +493,42 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                 const float g_er = get(ps + NX + (h.xe >= 0 ? h.xe : h.x));
                 const float g_own = top ? Pr[0] : Pr[(R - 1) * PW];
                 // pass 2: x += a p, r -= a q, p = r + b p (each thread reads and writes only its own points
-                // of p), this thread's share of the new (r, r), and the ghost rows
+                // of p), this thread's share of the new (r, r), and the ghost rows.  The rows go eight at a
+                // time, every load of p of the eight issued before the first is used.
                 {
                     float crr = 0.0f;
                     rr_part = 0.0;
+                    float xgv[XG > 0 ? XG : 1];
 #pragma unroll
-                    for (int i = 0; i < R; ++i) {
-                        const float pc = Pr[i * PW];
-                        if (i < R - XL)
-                            xv[i] = xv[i] + a32 * pc;
-                        else {
-                            float& xl = XS[(i - (R - XL)) * kThreads + threadIdx.x];
-                            xl = xl + a32 * pc;
+                    for (int i0 = 0; i0 < R; i0 += 8) {
+                        float pcs[8];
+#pragma unroll
+                        for (int b = 0; b < 8; ++b) pcs[b] = Pr[(i0 + b) * PW];
+                        if (XG > 0 && i0 == kXgLoadRow) {
+#pragma unroll
+                            for (int j = 0; j < XG; ++j) xgv[j] = xg(j);
                         }
-                        float pn;
-                        cg_update(a32, b32, qv[i], pc, rv[i], pn);
-                        Pr[i * PW] = pn;
-                        crr += rv[i] * rv[i];
-                        if ((i & 7) == 7 || i == R - 1) {
-                            rr_part += (double)crr;
-                            crr = 0.0f;
+                        row_fence();
+#pragma unroll
+                        for (int b = 0; b < 8; ++b) {
+                            const int i = i0 + b;
+                            const float pc = pcs[b];
+                            if (i < XR)
+                                xv[i] = xv[i] + a32 * pc;
+                            else if (i < R - XL)
+                                xg(i - XR) = xgv[i - XR] + a32 * pc;
+                            else {
+                                float& xl = XS[(i - (R - XL)) * kThreads + threadIdx.x];
+                                xl = xl + a32 * pc;
+                            }
+                            float pn;
+                            cg_update(a32, b32, qv[i], pc, rv[i], pn);
+                            Pr[i * PW] = pn;
+                            crr += rv[i] * rv[i];
                         }
-                        if ((i & 7) == 7) row_fence();
+                        rr_part += (double)crr;
+                        crr = 0.0f;
+                        row_fence();
                     }
                     const float w = h.xw >= 0 ? g_wr : 0.0f, e = h.xe >= 0 ? g_er : 0.0f;
                     const float q = top ? stencil32(d32, cx32, cy32, g_p1, g_p0, g_own, w, e)
@@ -516,7 +549,7 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
             // the next defect in its place
 #pragma unroll
             for (int i = 0; i < R; ++i)
-                Pr[i * PW] = sig32 * (i < R - XL ? xv[i] : XS[(i - (R - XL)) * kThreads + threadIdx.x]);
+                Pr[i * PW] = sig32 * (i < XR ? xv[i] : (i < R - XL ? xg(i - XR) : XS[(i - (R - XL)) * kThreads + threadIdx.x]));
             __syncthreads();
             const bool ystep = (t == a.m);
             const double* so = xo;
@@ -569,6 +602,7 @@ namespace atm {
 namespace {
 
 constexpr int kSpinCap = 1 << 21;  // polls of the partner's counter (about a second) before giving up
+constexpr size_t xg_offset_pad = 64;  // floats between the mailbox and the rows of x in global memory
 
 struct PairShape {
     void* fn;  // the kernel instantiation, null when the grid has none
@@ -608,7 +642,7 @@ int sweep_pair_pairs(const KArgs& a, int64_t n_tasks)
     if (pairs < 8) return 0;
     // the mailbox in the large-grid scratch (free while the sweep runs)
     const size_t slot = ((size_t)pair::pack_floats(a.g.nx) + 2 * pair::kParts + 63) / 64 * 64;
-    const size_t need = 2 * (size_t)pairs * 2 * slot * sizeof(float);
+    const size_t need = (2 * (size_t)pairs * 2 * slot + xg_offset_pad + 2 * (size_t)pairs * pair::kXgMax * pair::kThreads) * sizeof(float);
     const size_t have = (size_t)(a.NT + 1) * 5 * (size_t)a.n * sizeof(double);
     return need <= have ? pairs : 0;
 }
@@ -622,6 +656,7 @@ hipError_t launch_sweep_pair(const KArgs& a, int pairs, hipStream_t s)
     pa.pack = pair::pack_floats(a.g.nx);
     pa.spin_cap = kSpinCap;
     pa.mail = reinterpret_cast<float*>(a.large_scratch);
+    pa.xg = pa.mail + 2 * (size_t)pairs * 2 * pa.slot + xg_offset_pad;
     hipLaunchKernelGGL(pair::reset_mailbox_kernel, dim3(8), dim3(256), 0, s, pa);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
