@@ -274,6 +274,7 @@ constexpr int x_lds_rows(int nx, int r) { return (nx == 256 && r == 64) ? 14 : 0
 constexpr int x_global_rows(int nx, int r) { return (nx == 256 && r == 64) ? 16 : 0; }
 constexpr int kXgMax = 16;
 constexpr int kXgLoadRow = 16;  // the update pass's row before which the batch is issued
+constexpr int kStencilBatch = 4;  // rows of the stencil pass whose LDS loads are issued together
 
 template <int NX, int R>
 __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, PairArgs pa)
@@ -448,25 +449,40 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                 // pass 1: q = M p and the partial sums
                 double sums[kParts] = {0.0, 0.0, 0.0, rr_part};
                 {
+                    // the rows go PB at a time, every LDS load of the PB rows issued before the first is used
+                    constexpr int PB = kStencilBatch;
+                    static_assert(R % PB == 0 && 8 % PB == 0, "whole batches");
                     float cpq = 0.0f, crq = 0.0f, cqq = 0.0f;
                     float up = Pr[-PW], cen = Pr[0];
 #pragma unroll
-                    for (int i = 0; i < R; ++i) {
-                        const float dn = Pr[(i + 1) * PW];
-                        const float q = stencil32(d32, cx32, cy32, up, cen, dn, Pw[i * PW], Pe[i * PW]);
-                        qv[i] = q;
-                        cpq += cen * q;
-                        crq += rv[i] * q;
-                        cqq += q * q;
-                        if ((i & 7) == 7 || i == R - 1) {
-                            sums[0] += (double)cpq;
-                            sums[1] += (double)crq;
-                            sums[2] += (double)cqq;
-                            cpq = crq = cqq = 0.0f;
+                    for (int i0 = 0; i0 < R; i0 += PB) {
+                        float dns[PB], ws[PB], es[PB];
+#pragma unroll
+                        for (int b = 0; b < PB; ++b) {
+                            dns[b] = Pr[(i0 + b + 1) * PW];
+                            ws[b] = Pw[(i0 + b) * PW];
+                            es[b] = Pe[(i0 + b) * PW];
                         }
-                        up = cen;
-                        cen = dn;
-                        if ((i & 3) == 3) row_fence();
+                        row_fence();
+#pragma unroll
+                        for (int b = 0; b < PB; ++b) {
+                            const int i = i0 + b;
+                            const float dn = dns[b];
+                            const float q = stencil32(d32, cx32, cy32, up, cen, dn, ws[b], es[b]);
+                            qv[i] = q;
+                            cpq += cen * q;
+                            crq += rv[i] * q;
+                            cqq += q * q;
+                            if ((i & 7) == 7 || i == R - 1) {
+                                sums[0] += (double)cpq;
+                                sums[1] += (double)crq;
+                                sums[2] += (double)cqq;
+                                cpq = crq = cqq = 0.0f;
+                            }
+                            up = cen;
+                            cen = dn;
+                        }
+                        row_fence();
                     }
                 }
                 ++k;
