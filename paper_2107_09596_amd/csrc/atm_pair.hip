@@ -274,7 +274,7 @@ constexpr int x_lds_rows(int nx, int r) { return (nx == 256 && r == 64) ? 14 : 0
 constexpr int x_global_rows(int nx, int r) { return (nx == 256 && r == 64) ? 16 : 0; }
 constexpr int kXgMax = 16;
 constexpr int kXgLoadRow = 16;  // the update pass's row before which the batch is issued
-constexpr int kStencilBatch = 4;  // rows of the stencil pass whose LDS loads are issued together
+constexpr int kStencilBatch = 8;  // rows of the stencil pass whose LDS loads are issued together
 
 template <int NX, int R>
 __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, PairArgs pa)
