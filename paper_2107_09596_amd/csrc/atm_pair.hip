@@ -308,7 +308,10 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
 
     HF h;
     h.x = threadIdx.x % NX;
-    h.g = threadIdx.x / NX;
+    // the row group, alike on every lane of a wave (a wave's 64 threads lie in one row of NX columns),
+    // kept in a scalar register with everything that depends on it alone
+    static_assert(NX % 64 == 0, "a wave within one row group");
+    h.g = (int)__builtin_amdgcn_readfirstlane(threadIdx.x / NX);
     h.half = half_of(blockIdx.x);
     h.pair = pair_of(blockIdx.x);
     h.periodic = a.g.periodic != 0;
