@@ -61,6 +61,13 @@ __device__ __forceinline__ uint32_t opq(uint32_t v)
     return v;
 }
 
+// the same for a value alike on every lane, kept in a scalar register
+__device__ __forceinline__ uint32_t opqs(uint32_t v)
+{
+    __asm__ volatile("" : "+s"(v));
+    return v;
+}
+
 // No instruction; memory accesses are not moved across it by the compiler.  Placed every few rows
 // of the unrolled strip passes so that the loads of all rows are not issued at once (they would
 // hold one register each).
@@ -508,9 +515,14 @@ __global__ __launch_bounds__(kThreads) void sweep_pair_mixed_kernel(KArgs a, Pai
                 const bool top = first_group;
                 const float* ps = partner_slot(pa, h.pair, h.half, k) + (top ? 3 * NX : 0);
                 const float g_r = get(ps + h.x), g_p0 = get(ps + NX + h.x), g_p1 = get(ps + 2 * NX + h.x);
-                const float g_wr = get(ps + NX + (h.xw >= 0 ? h.xw : h.x));
-                const float g_er = get(ps + NX + (h.xe >= 0 ? h.xe : h.x));
-                const float g_own = top ? Pr[0] : Pr[(R - 1) * PW];
+                // (the west and east columns as 32-bit byte offsets from the uniform slot address, formed
+                // here from the thread index rather than held across the loop; wrapped columns, which the
+                // Dirichlet edge then ignores)
+                const uint32_t xc = opq(threadIdx.x) % NX;
+                const uint32_t ow = (NX + (xc > 0 ? xc - 1 : NX - 1)) * 4u, oe = (NX + (xc < NX - 1 ? xc + 1 : 0)) * 4u;
+                const float g_wr = get(reinterpret_cast<const float*>(reinterpret_cast<const char*>(ps) + ow));
+                const float g_er = get(reinterpret_cast<const float*>(reinterpret_cast<const char*>(ps) + oe));
+                const float g_own = Pr[opqs(top ? 0u : (uint32_t)((R - 1) * PW))];
                 // pass 2: x += a p, r -= a q, p = r + b p (each thread reads and writes only its own points
                 // of p), this thread's share of the new (r, r), and the ghost rows.  The rows go eight at a
                 // time, every load of p of the eight issued before the first is used.
