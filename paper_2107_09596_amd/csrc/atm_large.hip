@@ -782,6 +782,20 @@ __device__ __forceinline__ uint64_t get64(const __bf16* p)
     return __hip_atomic_load(reinterpret_cast<uint64_t*>(const_cast<__bf16*>(p)), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// Loads at a uniform global base plus a 32-bit byte offset (one scalar pair and one vector register,
+// global rather than generic addressing)
+typedef __attribute__((address_space(1))) const char gbyte;
+__device__ __forceinline__ uint64_t gget64(const __bf16* base, uint32_t off)
+{
+    return __hip_atomic_load((__attribute__((address_space(1))) uint64_t*)((gbyte*)base + off), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+}
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ u32x4_t gload16(const __bf16* base, uint32_t off)
+{
+    return *(__attribute__((address_space(1))) const u32x4_t*)((gbyte*)base + off);
+}
 __device__ __forceinline__ void put64(__bf16* p, uint64_t v)
 {
     __hip_atomic_store(reinterpret_cast<uint64_t*>(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -812,27 +826,44 @@ __device__ __forceinline__ void bf_gemm(const BfOp A, const BfOp B, int K, __bf1
 {
     constexpr int M = 64 * TM, N = 64 * TN, R = M + N;
     static_assert(R <= kBfRowsMax, "chunk buffer too small");
-    constexpr int SEG = R * 8;  // 16-byte pieces of a chunk: R rows x 2 planes x 4
-    constexpr int PER = (SEG + kBlockL - 1) / kBlockL;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    static_assert(M % 16 == 0, "a wave's rows within one operand");
+    // A chunk is loaded in wave pieces of 16 rows x 4 16-byte segments of one plane (planes outermost):
+    // the operand and plane of a piece are alike on its wave, so its base address is scalar and a
+    // lane's address is that base plus a 32-bit offset.
+    constexpr int WP = R / 16 * 2;  // wave pieces of a chunk
+    constexpr int PER = (WP + kWavesL - 1) / kWavesL;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lk = lane >> 4;
     const int wm = wave >> 2, wn = wave & 3;
     uint64_t ld0[PER], ld1[PER];
+    // each piece's base (scalar, chosen once) and the lane's offset in it at k = 0
+    const __bf16* pbase[PER];
+    uint32_t poff[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int wp = q * kWavesL + wave;
+        const int plane = wp / (R / 16), rb = wp % (R / 16);
+        const bool isa = rb * 16 < M;
+        const __bf16* b = isa ? (plane ? A.lo : A.hi) : (plane ? B.lo : B.hi);
+        const uint64_t bb = reinterpret_cast<uint64_t>(b);
+        const uint32_t blo = __builtin_amdgcn_readfirstlane((uint32_t)bb), bhi = __builtin_amdgcn_readfirstlane((uint32_t)(bb >> 32));
+        pbase[q] = reinterpret_cast<const __bf16*>(((uint64_t)bhi << 32) | blo);
+        const int ld = isa ? A.ld : B.ld;
+        const int r = (isa ? rb * 16 : rb * 16 - M) + (lane >> 2);
+        poff[q] = (uint32_t)(r * ld + 8 * (lane & 3)) * 2u;
+    }
     auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int sg = tid + q * kBlockL;
-            if (sg < SEG) {
-                const int row = sg >> 3, plane = (sg >> 2) & 1, seg = sg & 3;
-                const bool isa = row < M;
-                const __bf16* base = isa ? (plane ? A.lo : A.hi) : (plane ? B.lo : B.hi);
-                const int r = isa ? row : row - M;
-                const __bf16* src = base + (int64_t)r * (isa ? A.ld : B.ld) + k0 + 8 * seg;
+            const int wp = q * kWavesL + wave;
+            if (wp < WP) {
+                const bool isa = wp % (R / 16) * 16 < M;
+                const uint32_t off = poff[q] + (uint32_t)k0 * 2u;
                 if (ACOH && isa) {
-                    ld0[q] = get64(src);
-                    ld1[q] = get64(src + 4);
+                    ld0[q] = gget64(pbase[q], off);
+                    ld1[q] = gget64(pbase[q], off + 8u);
                 } else {
-                    const uint4 v = *reinterpret_cast<const uint4*>(src);
+                    const u32x4_t v = gload16(pbase[q], off);
                     ld0[q] = (uint64_t)v.x | ((uint64_t)v.y << 32);
                     ld1[q] = (uint64_t)v.z | ((uint64_t)v.w << 32);
                 }
@@ -842,9 +873,9 @@ __device__ __forceinline__ void bf_gemm(const BfOp A, const BfOp B, int K, __bf1
     auto stage = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const int sg = tid + q * kBlockL;
-            if (sg < SEG) {
-                const int row = sg >> 3, plane = (sg >> 2) & 1, seg = sg & 3;
+            const int wp = q * kWavesL + wave;
+            if (wp < WP) {
+                const int plane = wp / (R / 16), row = wp % (R / 16) * 16 + (lane >> 2), seg = lane & 3;
                 uint4 v;
                 v.x = (uint32_t)ld0[q];
                 v.y = (uint32_t)(ld0[q] >> 32);
