@@ -944,6 +944,11 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScrat
     const int64_t n = a.n, o = (int64_t)r0 * NX, cnt = (int64_t)ROWS * NX;
     const int tid = threadIdx.x;
     const SpecTables T = spec_tables(a);
+    // the eigenvalue factors of the two directions as FP32, in LDS for the products' epilogue (read
+    // there once per output tile, where global loads would each wait out a memory latency)
+    __shared__ float eig[NX + NY];
+    for (int e = tid; e < NX + NY; e += kBlockL) eig[e] = (float)(e < NX ? T.ex[e] : T.ey[e - NX]);
+    __syncthreads();
     const BfOp qyt{bf_table(a, 0, 0) + r0 * NY, bf_table(a, 0, 1) + r0 * NY, NY};
     const BfOp qxt{bf_table(a, 1, 0), bf_table(a, 1, 1), NX};
     const BfOp qy{bf_table(a, 2, 0) + r0 * NY, bf_table(a, 2, 1) + r0 * NY, NY};
@@ -1014,9 +1019,9 @@ __global__ __launch_bounds__(kBlockL) void coarse_pair_bf_kernel(KArgs a, LScrat
                 bf_gemm<NXT, RT, true>(opb, qyt, NY, lds, to_t1);  // Qy^T b
                 __syncthreads();
                 bf_gemm<RT, NXT, false>(opt1, qxt, NX, lds, [&](int i, int x, f32x4_t c) {  // (.. Qx) ./ mu
-                    const float ex = (float)T.ex[x];
+                    const float ex = eig[x];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) c[r] = c[r] / (1.0f + (cx2 * ex + cy2 * (float)T.ey[r0 + i + r]));
+                    for (int r = 0; r < 4; ++r) c[r] = c[r] / (1.0f + (cx2 * ex + cy2 * eig[NX + r0 + i + r]));
                     uint64_t h, l;
                     split4(c, h, l);
                     put64(t2 + (int64_t)x * NY + r0 + i, h);
