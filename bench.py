@@ -53,7 +53,7 @@ FLOPS_PER_CG_ITER_POINT = 18
 # HBM traffic per launch of the headline's sweep kernel (bytes read, bytes written), from rocprofv3
 # FETCH_SIZE and WRITE_SIZE on the headline workload, scaled by the same counters of a plain device
 # copy; keyed by the kernel they were taken on (a kernel without counters reports null)
-SWEEP_TRAFFIC_BYTES = {"sweep_pair_mixed_kernel": (12.867e9, 6.244e9)}
+SWEEP_TRAFFIC_BYTES = {"sweep_pair_mixed_kernel": (12.866e9, 6.246e9)}
 
 
 def parse():
