@@ -4,8 +4,9 @@
 // The CG state of one fine step of a 256 x 256 grid (x, r, p and M p in FP32: 1 MB) does not fit
 // on one CU (512 KB of registers, 160 KB of LDS), so each interval is taken by a pair of 512-thread
 // workgroups, each owning half of the rows: x, r and M p of its half in registers (a thread holds
-// R consecutive rows of one column), the search direction p of its half in LDS with one ghost row
-// above and below.  128 intervals then use all 256 CUs.
+// R consecutive rows of one column; on the 256 x 256 grid the last rows of x go to the LDS that p
+// leaves free and to a coalesced global buffer), the search direction p of its half in LDS with one
+// ghost row above and below.  128 intervals then use all 256 CUs.
 //
 // The two halves meet once per CG iteration.  After the stencil pass each half publishes, through
 // a mailbox in global memory, three partial sums -- (p, M p), (r, M p), (M p, M p) -- and the true
@@ -49,7 +50,7 @@ struct PairArgs {
     int slot;         // floats per mailbox slot: pack_floats(NX), then kParts doubles
     int pack;         // pack_floats(NX): where the sums of a slot start
     int spin_cap;     // polls of the partner's counter before giving up
-    float* xg;        // rows of x kept in global memory: [2 pairs][x_global_rows][kThreads] floats
+    float* xg;        // rows of x kept in global memory: [2 x pairs workgroups][x_global_rows][kThreads]
 };
 
 // A 32-bit offset hidden from the optimiser, so that the row offsets of the unrolled strip loops are
